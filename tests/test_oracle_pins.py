@@ -1,0 +1,290 @@
+"""Pins of the FP64 oracle against facts it does not compute itself.
+
+Each test ties the oracle to something independent of its own code: a
+quadrature of the kernel, an infinite-lattice sum, a library neighbour
+search, an O(N^2) evaluation with a different root finder, conservation laws
+of the pairwise force, and finite differences of the density solve (the
+first law du = P / rho^2 drho and the force as minus the gradient of the
+thermal energy). A dropped term, a wrong sign, power or index in the oracle
+fails at least one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.spatial import cKDTree
+
+import oracle
+import workloads
+from oracle import brute
+
+
+# --- the kernel (section 2: bell-shaped, compact support W(q) = 0 for q > 1) ---
+
+def test_kernel_integrates_to_one():
+    val, err = integrate.quad(lambda r: 4 * math.pi * r * r * 8 / math.pi * float(brute._w(r)), 0, 1,
+                              points=[0.5], epsabs=1e-13, epsrel=1e-13)
+    assert abs(val - 1.0) < 1e-12
+
+
+def test_kernel_shape_continuity_and_derivative():
+    for q0 in (0.5, 1.0):
+        assert abs(float(brute._w(q0 - 1e-12)) - float(brute._w(q0 + 1e-12))) < 1e-10
+        assert abs(float(brute._dw(q0 - 1e-12)) - float(brute._dw(q0 + 1e-12))) < 1e-10
+    q = np.linspace(0.01, 0.99, 97)
+    fd = (brute._w(q + 1e-6) - brute._w(q - 1e-6)) / 2e-6
+    assert np.max(np.abs(fd - brute._dw(q))) < 1e-8
+    assert float(brute._w(0.0)) == 1.0 and float(brute._w(1.0)) == 0.0
+    assert float(brute._w(1.5)) == 0.0
+
+
+# --- perfect cubic lattice: infinite-lattice closed form -----------------------
+
+LATTICE_H_OVER_A = 2.251489742231818
+LATTICE_RHO = 1.004020800085607      # rho a^3 / m
+LATTICE_F = 1.010015781338927
+LATTICE_NGB = 56                     # shells 6 + 12 + 8 + 6 + 24
+
+
+def _infinite_lattice_root():
+    """Root of sum_n w(|n| / h) = 4.5 over the infinite unit lattice (an
+    explicit sum over lattice vectors, no periodic box, no search grid)."""
+    g = np.arange(-4, 5)
+    n = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    r = np.sqrt((n ** 2).sum(1).astype(float))
+    lo, hi = 2.0, 3.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if brute._w(r / mid).sum() < 4.5:
+            lo = mid
+        else:
+            hi = mid
+    h = 0.5 * (lo + hi)
+    q = r / h
+    M0 = brute._w(q).sum()
+    M1 = (q * brute._dw(q)).sum()
+    return h, 8 / (math.pi * h ** 3) * M0, -3 * M0 / M1, int(((r < h) & (r > 0)).sum())
+
+
+def test_infinite_lattice_sum_matches_quoted_values():
+    h, rho, f, k = _infinite_lattice_root()
+    assert abs(h - LATTICE_H_OVER_A) < 1e-13
+    assert abs(rho - LATTICE_RHO) < 1e-13
+    assert abs(f - LATTICE_F) < 1e-13
+    assert k == LATTICE_NGB
+
+
+@pytest.mark.parametrize("m_side", [6, 16])
+def test_oracle_perfect_lattice(m_side):
+    d = workloads.lattice_box(m_side, None, jitter=0.0)
+    r = oracle.run(d)
+    a = 1.0 / m_side
+    m = float(d["mass"][0])  # the float32-rounded mass both sides see
+    assert np.max(np.abs(r["h"] / a - LATTICE_H_OVER_A)) < 1e-12
+    assert np.max(np.abs(r["rho"] * a ** 3 / m - LATTICE_RHO)) < 1e-12
+    assert np.max(np.abs(r["f"] - LATTICE_F)) < 1e-12
+    assert np.all(r["nngb"] == LATTICE_NGB)
+    assert np.max(np.abs(r["nw"] - 48.0)) < 1e-11
+    # zero force and zero heating by symmetry
+    assert np.max(np.linalg.norm(r["acc"], axis=1) / r["gross_a"]) < 1e-12
+    assert np.all(r["dudt"] == 0.0)
+
+
+# --- O(N^2) brute force (different search and root finder) --------------------
+
+def _cases():
+    rng = np.random.default_rng([1508, 99])
+    yield "lattice8", workloads.lattice_box(8, [1508, 90], jitter=0.2, vel_sigma=0.3)
+    yield "lattice10", workloads.lattice_box(10, [1508, 91], jitter=0.1, u=2.0, vel_sigma=0.1)
+    n = 700
+    pos = rng.uniform(0, 1, size=(n, 3))
+    yield "uniform", dict(pos=pos, vel=rng.normal(0, 0.2, (n, 3)), mass=rng.uniform(0.5, 1.5, n) / n,
+                          u=rng.uniform(0.5, 2.0, n), h0=np.full(n, 0.25), box_first=np.array([0, n]),
+                          box_len=np.array([1.0]))
+    # a clump plus background: density contrast ~ 30
+    c = 0.3 + 0.05 * rng.normal(size=(400, 3))
+    pos = np.mod(np.concatenate([rng.uniform(0, 1, (400, 3)), c]), 1.0)
+    n = pos.shape[0]
+    yield "clump", dict(pos=pos, vel=rng.normal(0, 0.1, (n, 3)), mass=np.full(n, 1.0 / n),
+                        u=np.ones(n), h0=np.full(n, 0.1), box_first=np.array([0, n]),
+                        box_len=np.array([1.0]))
+
+
+@pytest.mark.parametrize("name,d", list(_cases()), ids=[c[0] for c in _cases()])
+def test_oracle_vs_brute_force(name, d):
+    r = oracle.run(d)
+    b = brute.density(d["pos"], d["mass"])
+    for k in ("h", "rho", "f", "nw"):
+        assert np.max(np.abs(r[k] - b[k]) / np.abs(b[k])) < 1e-12, k
+    assert np.array_equal(r["nngb"], b["nngb"])
+    bf = brute.force(d["pos"], d["vel"], d["mass"], d["u"], b["h"], b["rho"], b["f"])
+    err_a = np.linalg.norm(r["acc"] - bf["acc"], axis=1) / bf["gross_a"]
+    err_u = np.abs(r["dudt"] - bf["dudt"]) / np.maximum(bf["gross_u"], 1e-300)
+    assert err_a.max() < 1e-12
+    assert err_u.max() < 1e-12
+    assert np.array_equal(r["npair"], bf["npair"])
+
+
+# --- library neighbour search --------------------------------------------------
+
+def test_neighbour_counts_match_kdtree():
+    d = workloads.sedov(n_side=24)
+    r = oracle.density(d["pos"], d["mass"], h_start=d["h0"])
+    tree = cKDTree(d["pos"], boxsize=1.0)
+    idx = np.arange(0, d["pos"].shape[0], 7)
+    counts = np.array([len(tree.query_ball_point(d["pos"][i], r["h"][i])) - 1 for i in idx])
+    assert np.array_equal(counts, r["nngb"][idx])
+    # converged weighted count and the identity rho h^3 = 3 m nw / (4 pi)
+    assert np.max(np.abs(r["nw"] - 48.0)) < 48 * 1e-12
+    m = d["mass"].astype(float)
+    assert np.max(np.abs(r["rho"] * r["h"] ** 3 / (3 * m * r["nw"] / (4 * math.pi)) - 1)) < 1e-12
+
+
+# --- conservation of the pairwise force ----------------------------------------
+
+@pytest.mark.parametrize("alpha", [0.0, 0.8])
+def test_momentum_and_energy_conservation(alpha):
+    d = workloads.lattice_box(12, [1508, 77], jitter=0.3, u=1.0, vel_sigma=0.2)
+    rng = np.random.default_rng(5)
+    d["u"] = rng.uniform(0.5, 2.0, d["u"].size)
+    r = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"], alpha=alpha)
+    assert np.max(np.abs(r["mom"])) <= 1e-13 * r["mom_scale"]
+    assert abs(r["energy"]) <= 1e-13 * r["energy_scale"]
+
+
+def test_zero_velocity_gives_zero_heating():
+    d = workloads.sedov(n_side=16)
+    r = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"])
+    assert np.all(r["dudt"] == 0.0)
+    assert np.max(np.abs(r["mom"])) <= 1e-13 * r["mom_scale"]
+
+
+def test_viscosity_only_heats():
+    d = workloads.lattice_box(10, [1508, 78], jitter=0.2, u=1.0, vel_sigma=0.5)
+    r0 = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"], alpha=0.0)
+    r1 = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"], alpha=0.8)
+    m = d["mass"].astype(float)
+    # total viscous heating is positive and matches the kinetic energy lost
+    heat = float((m * (r1["dudt"] - r0["dudt"])).sum())
+    va = lambda r: float((m * np.einsum("ij,ij->i", d["vel"].astype(float), r["acc"])).sum())
+    assert heat > 0
+    assert abs(heat + (va(r1) - va(r0))) <= 1e-12 * r1["energy_scale"]
+
+
+# --- finite differences of the density solve ------------------------------------
+
+def _fd_case():
+    d = workloads.lattice_box(10, [1508, 79], jitter=0.25, u=1.0, vel_sigma=0.3)
+    rng = np.random.default_rng(11)
+    d["u"] = rng.uniform(0.5, 2.0, d["u"].size)
+    return d
+
+
+def test_first_law_du_equals_p_over_rho2_drho():
+    """With alpha = 0, du_i/dt = P_i / rho_i^2 * drho_i/dt, where drho/dt is the
+    finite difference of the full density solve (h re-converged) along the
+    velocities. Pins the kernel derivative, its h^-4 scaling, f and Phi."""
+    d = _fd_case()
+    pos, vel, m, u = d["pos"], d["vel"].astype(float), d["mass"], d["u"].astype(float)
+    r = oracle.run_box(pos, vel, m, u, alpha=0.0)
+    dt = 1e-6
+    rp = oracle.density(np.mod(pos + vel * dt, 1.0), m, h_start=r["h"])
+    rm = oracle.density(np.mod(pos - vel * dt, 1.0), m, h_start=r["h"])
+    drho = (rp["rho"] - rm["rho"]) / (2 * dt)
+    P = (5.0 / 3.0 - 1.0) * r["rho"] * u
+    pred = P / r["rho"] ** 2 * drho
+    assert np.max(np.abs(pred - r["dudt"]) / r["gross_u"]) < 1e-5
+
+
+def test_acceleration_is_minus_gradient_of_thermal_energy():
+    """With alpha = 0 and adiabatic u_k ~ rho_k^(gamma-1), m_i a_i = -dU/dx_i
+    with U = sum_k m_k u_k, by central differences of the density solve."""
+    d = _fd_case()
+    pos, m, u = d["pos"], d["mass"].astype(float), d["u"].astype(float)
+    gamma = 5.0 / 3.0
+    r = oracle.run_box(pos, d["vel"], m, u, alpha=0.0)
+    eps = 1e-6
+
+    def energy(p):
+        rr = oracle.density(np.mod(p, 1.0), m, h_start=r["h"])
+        return float((m * u * (rr["rho"] / r["rho"]) ** (gamma - 1.0)).sum())
+
+    for i in (0, 137, 555, 999):
+        for ax in range(3):
+            pp = pos.copy(); pp[i, ax] += eps
+            pm = pos.copy(); pm[i, ax] -= eps
+            grad = (energy(pp) - energy(pm)) / (2 * eps)
+            assert abs(-grad / m[i] - r["acc"][i, ax]) < 1e-5 * r["gross_a"][i], (i, ax)
+
+
+def test_grad_h_factor_from_density_derivative():
+    """f = [1 + h / (3 rho) drho/dh]^-1 with drho/dh by central differences of
+    Eq. 1 at fixed positions."""
+    d = _fd_case()
+    r = oracle.density(d["pos"], d["mass"])
+    sep = brute.separations(d["pos"])
+    rr = np.sqrt((sep ** 2).sum(-1))
+    m = d["mass"].astype(float)
+
+    def rho_at(h):
+        return (m[None, :] * 8 / (math.pi * h[:, None] ** 3) * brute._w(rr / h[:, None])).sum(1)
+
+    eps = 1e-6 * r["h"]
+    drho = (rho_at(r["h"] + eps) - rho_at(r["h"] - eps)) / (2 * eps)
+    f = 1.0 / (1.0 + r["h"] / (3 * r["rho"]) * drho)
+    assert np.max(np.abs(f - r["f"])) < 1e-7
+
+
+# --- symmetries -------------------------------------------------------------------
+
+def test_mirror_translation_and_permutation():
+    d = workloads.lattice_box(10, [1508, 80], jitter=0.3, u=1.0, vel_sigma=0.2)
+    base = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"])
+    # mirror x -> L - x flips a_x and v_x
+    pos = d["pos"].copy(); pos[:, 0] = np.mod(1.0 - pos[:, 0], 1.0)
+    vel = d["vel"].astype(float).copy(); vel[:, 0] *= -1
+    mir = oracle.run_box(pos, vel, d["mass"], d["u"])
+    assert np.max(np.abs(mir["h"] - base["h"]) / base["h"]) < 1e-12
+    tol = 1e-11 * base["gross_a"]
+    assert np.all(np.abs(mir["acc"][:, 0] + base["acc"][:, 0]) < tol)
+    assert np.all(np.abs(mir["acc"][:, 1] - base["acc"][:, 1]) < tol)
+    assert np.all(np.abs(mir["dudt"] - base["dudt"]) < 1e-11 * base["gross_u"])
+    # periodic translation
+    tr = oracle.run_box(np.mod(d["pos"] + [0.31, 0.77, 0.05], 1.0), d["vel"], d["mass"], d["u"])
+    assert np.max(np.abs(tr["rho"] - base["rho"]) / base["rho"]) < 1e-12
+    assert np.all(np.linalg.norm(tr["acc"] - base["acc"], axis=1) < 1e-11 * base["gross_a"])
+    # permutation
+    perm = np.random.default_rng(3).permutation(d["pos"].shape[0])
+    pr = oracle.run_box(d["pos"][perm], d["vel"][perm], d["mass"][perm], d["u"][perm])
+    assert np.max(np.abs(pr["h"] - base["h"][perm]) / base["h"][perm]) < 1e-12
+    assert np.all(np.linalg.norm(pr["acc"] - base["acc"][perm], axis=1) < 1e-11 * base["gross_a"][perm])
+
+
+def test_root_independent_of_starting_guess():
+    d = workloads.small()
+    a = oracle.density(d["pos"], d["mass"], h_start=d["h0"] * 0.3)
+    b = oracle.density(d["pos"], d["mass"], h_start=d["h0"] * 2.0)
+    assert np.max(np.abs(a["h"] - b["h"]) / a["h"]) < 1e-12
+
+
+def test_lone_self_term():
+    """Eq. 1 sums over all j including i: in a box too sparse for anything but
+    the particle itself inside a small h, rho is m W(0, h) = 8 m / (pi h^3)."""
+    # two particles far apart: the root needs h beyond L/2 -> error path
+    pos = np.array([[0.1, 0.1, 0.1], [0.6, 0.6, 0.6]])
+    with pytest.raises(RuntimeError):
+        oracle.density(pos, np.ones(2))
+    # self term: weighted count of a lone particle is 32/3 at any h
+    assert abs(32.0 / 3.0 * float(brute._w(0.0)) - 32.0 / 3.0) == 0.0
+
+
+def test_targets_subset_matches_full():
+    d = workloads.sedov(n_side=20)
+    full = oracle.run_box(d["pos"], d["vel"], d["mass"], d["u"])
+    idx = np.arange(0, d["pos"].shape[0], 13)
+    sub = oracle.density(d["pos"], d["mass"], targets=idx)
+    assert np.array_equal(sub["h"][idx], full["h"][idx])
+    fo = oracle.force(d["pos"], d["vel"], d["mass"], d["u"], full["h"], full["rho"], full["f"], targets=idx)
+    assert np.array_equal(fo["acc"][idx], full["acc"][idx])
