@@ -1,0 +1,224 @@
+"""Benchmark: particle-neighbour interactions per second of one SPH
+density + force pass on one MI355X.
+
+A step is one full pass of the hot path over the Sedov-blast set (64^3
+particles on a jittered lattice in a periodic unit box, u = 1e-5 except
+total energy 1 in the 32 central particles, v = 0): the density loop with
+the smoothing-length solve to convergence, then the ghost step and the force
+loop. The cells are built once before timing (the build is reported
+separately), the starting h is restored before every step, and all inputs
+are resident in HBM. The interaction count of a pass is
+
+    #{(i, j), j != i: r_ij < h_i}  +  #{(i, j), j != i: r_ij < max(h_i, h_j)}
+
+counted once per pass however many Newton sweeps h needed. The same pass in
+the plain FP64 form is timed beside it, and the FP64 CPU oracle on the
+host's cores.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-neighbour interactions/s (density+force), FP32 batched vs FP64 plain"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (public figure)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FLOPs per unit of work (FMA = 2, add/mul/min = 1; sqrt and
+# reciprocals listed apart and not counted):
+#   a candidate pair tested and rejected            8   (3 sub, r^2, compare)
+#   a density interaction at one trial h           26   (+1 sqrt)
+#   a force interaction, gather form (per side)    61   (+1 rsqrt, +1 rcp)
+FLOP_REJECT = 8
+FLOP_DENSITY = 26
+FLOP_FORCE = 61
+# FLOPs the kernels as written execute per candidate pair (every candidate goes
+# through the full branch-free body), counted from their source.
+HW_FLOP_DENSITY_CAND = 31
+HW_FLOP_FORCE_CAND = 72
+
+
+def _workload(name: str):
+    import workloads
+    if name == "sedov":
+        return workloads.sedov(), ("sedov blast 64^3: 262,144 equal-mass particles, jittered lattice, "
+                                   "periodic unit box, u=1e-5 with total energy 1 in the 32 central "
+                                   "particles, v=0, gamma=5/3, cubic spline, 48 weighted neighbours")
+    if name == "small":
+        return workloads.small(), "small 16^3 jittered lattice, u=1, v=0"
+    if name == "batched":
+        return workloads.batched(), "256 periodic boxes of 20^3..40^3 jittered-lattice particles, v~N(0,0.1)"
+    if name == "clustered":
+        return workloads.clustered(), "2^19 uniform + 64 Plummer spheres x 8192, periodic unit box"
+    if name == "large":
+        return workloads.lognormal(), "256^3 particles from a log-normal density field"
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(d: dict, min_seconds: float) -> dict:
+    import oracle
+    reps, t_tot, inter = 0, 0.0, 0
+    while reps < 1 or (t_tot < min_seconds and reps < 20):
+        r = oracle.run(d)
+        t_tot += r["t_density"] + r["t_force"]
+        inter = int(r["nngb"].sum() + r["npair"].sum())
+        reps += 1
+    return {"value": inter * reps / t_tot, "unit": "interactions/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "the full workload (every particle, density with h solved to 1e-13 + force), "
+                      "%d repetition(s), %.1f s" % (reps, t_tot)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sedov")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1508_00115_amd as sph
+
+    d, desc = _workload(args.workload)
+    n = d["pos"].shape[0]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    pos = torch.from_numpy(d["pos"]).to(dev)
+    h0 = torch.from_numpy(d["h0"]).to(dev)
+    mass = torch.from_numpy(d["mass"]).to(dev)
+    vel = torch.from_numpy(d["vel"]).to(dev)
+    u = torch.from_numpy(d["u"]).to(dev)
+    h = h0.clone()
+    rho = torch.empty_like(h)
+    f = torch.empty_like(h)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    dudt = torch.empty_like(h)
+
+    ctx = sph.Context(0, timing=1)
+    ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
+    build_ms = ctx.timings()["build_ms"]
+
+    def step():
+        h.copy_(h0)
+        dr = ctx.density(mass, h, rho, f)
+        fr = ctx.force(vel, u, acc, dudt, cons=False)
+        t = ctx.timings()
+        return dr["stats"], fr["stats"], t
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dk, fk, dc, fc = [], [], [], []
+    e0.record(stream)
+    for _ in range(args.steps):
+        sd, sf, t = step()
+        dk.append(t["density_kernel_ms"])
+        fk.append(t["force_kernel_ms"])
+        dc.append(t["density_call_ms"])
+        fc.append(t["force_call_ms"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    inter = sd["interactions_density"] + sf["interactions_force"]
+    value = inter / (ms_step * 1e-3)
+
+    # ---- plain FP64 form on the same cells -------------------------------------------
+    mass64, vel64, u64 = mass.double(), vel.double(), u.double()
+    h0_64 = h0.double()
+    h64 = h0_64.clone()
+    rho64, f64 = torch.empty_like(h64), torch.empty_like(h64)
+    acc64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    dudt64 = torch.empty_like(h64)
+
+    def step64():
+        h64.copy_(h0_64)
+        ctx.density_f64(mass64, h64, rho64, f64)
+        ctx.force_f64(vel64, u64, acc64, dudt64, cons=False)
+
+    step64()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.fp64_steps):
+        step64()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step64 = e0.elapsed_time(e1) / args.fp64_steps
+    value64 = inter / (ms_step64 * 1e-3)
+
+    # ---- roofline of the dominant kernel ------------------------------------------------
+    dens_ms = float(np.mean(dk))
+    force_ms = float(np.mean(fk))
+    dens_alg = FLOP_DENSITY * sd["sweep_interactions_density"] + \
+        FLOP_REJECT * (sd["candidates_density"] - sd["sweep_interactions_density"])
+    force_alg = FLOP_FORCE * sf["interactions_force"] + \
+        FLOP_REJECT * (sf["candidates_force"] - sf["interactions_force"])
+    if dens_ms >= force_ms:
+        kname, kms, alg, hw = "k_density", dens_ms, dens_alg, HW_FLOP_DENSITY_CAND * sd["candidates_density"]
+    else:
+        kname, kms, alg, hw = "k_force", force_ms, force_alg, HW_FLOP_FORCE_CAND * sf["candidates_force"]
+    achieved = alg / (kms * 1e-3) / 1e12
+    useful = (FLOP_DENSITY * sd["sweep_interactions_density"] + FLOP_FORCE * sf["interactions_force"]) / \
+        ((dens_ms + force_ms) * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "particles": n, "interactions_per_pass": inter,
+                   "density_interactions": sd["interactions_density"],
+                   "force_interactions": sf["interactions_force"], "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg,
+                     "executed_flop_per_launch": hw},
+        "kernels_ms": {"density_kernel": dens_ms, "density_call": float(np.mean(dc)),
+                       "force_kernel": force_ms, "force_call": float(np.mean(fc)), "build": build_ms},
+        "useful_tflops": useful,
+        "density": {"sweeps": sd["sweeps"], "rebuilds": sd["rebuilds"],
+                    "candidates": sd["candidates_density"],
+                    "sweep_interactions": sd["sweep_interactions_density"],
+                    "cells": sd["n_cells"], "cell_pairs": sd["n_pairs"]},
+        "force": {"candidates": sf["candidates_force"]},
+        "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
+        "speedup_vs_fp64_plain": value / value64,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,216 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) SPH neighbour-interaction library.
+ *
+ * The library computes the smoothed-particle-hydrodynamics sums of the Swift
+ * paper (Theuns, Chalk, Schaller & Gonnet, "Swift: task-based hydrodynamics
+ * and gravity for cosmological simulations"):
+ *
+ *   - cell binning: particles are grouped in cubic cells no smaller than the
+ *     search radius of the particles they hold, refined adaptively
+ *     (section 3.1, Fig. 1); neighbouring cells are found with a tree
+ *     (end of section 3.1);
+ *   - the density loop: rho_i = sum_j m_j W(|r_i - r_j|, h_i) over all j
+ *     including i (section 2, Eq. 1), with h_i solved so that a fixed
+ *     weighted number of neighbours contributes (section 2, after Eq. 2);
+ *   - after the density (the dependency of section 3.1), the symmetric
+ *     pressure-gradient loop in the grad-h form of Gadget-2 that the paper
+ *     says Swift implements (section 2, after Eq. 2), with a signal-velocity
+ *     artificial viscosity, giving accelerations and du/dt.
+ *
+ * Kernel: cubic spline with compact support h, W(r, h) = 8 / (pi h^3) w(r/h),
+ *   w(q) = 1 - 6 q^2 + 6 q^3 (q <= 1/2), 2 (1 - q)^3 (1/2 < q <= 1), 0 beyond.
+ * h_i: (4 pi / 3) h_i^3 sum_j W(r_ij, h_i) = n_ngb.
+ * Grad-h factor: f_i = [1 + h_i / (3 rho_i) d rho_i / d h_i]^-1.
+ * Equation of state: P = (gamma - 1) rho u; sound speed c = sqrt(gamma (gamma - 1) u).
+ * Force, for each pair with 0 < r < max(h_i, h_j), rhat = (r_i - r_j) / r,
+ *   D_k = dW/dr(r, h_k),  Phi_k = f_k P_k / rho_k^2,
+ *   w_ij = min((v_i - v_j) . rhat, 0),
+ *   Pi_ij = -alpha (c_i + c_j - 3 w_ij) w_ij / (rho_i + rho_j),
+ *   G_ij = Phi_i D_i + Phi_j D_j + Pi_ij (D_i + D_j) / 2,
+ *   a_i = -sum_j m_j G_ij rhat,
+ *   du_i/dt = sum_j m_j (Phi_i D_i + Pi_ij (D_i + D_j) / 4) (v_i - v_j) . rhat.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked "device" are HIP device (or managed) memory; "host"
+ *     pointers are ordinary host memory. The caller owns every buffer it
+ *     passes; the library never frees or keeps caller memory beyond the call,
+ *     except where stated. Device inputs must stay valid and unchanged until
+ *     the work enqueued on `stream` has finished.
+ *   - Per-particle arrays are in the caller's particle order. Vectors are AoS
+ *     (x, y, z) per particle.
+ *   - Boxes: particles [box_first[b], box_first[b+1]) live in periodic cubic
+ *     box b of side box_len[b]; boxes never interact.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, 0 = null
+ *     stream). Calls return after enqueueing, except where a host output
+ *     (stats, cons) or an internal decision (rebuild) needs a result: those
+ *     calls synchronise `stream` once.
+ *   - Errors: every call returns an sph_status. On error the outputs are
+ *     unspecified and sph_last_error() describes the cause. A context stays
+ *     usable after any error except SPH_E_HIP.
+ *   - A context is not thread-safe; use one context per stream.
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_E_ARG = 1,            /* invalid argument (null, size, non-finite, order) */
+    SPH_E_HIP = 2,            /* a HIP runtime call failed */
+    SPH_E_NOMEM = 3,          /* device allocation failed or workspace_limit exceeded */
+    SPH_E_H_TOO_LARGE = 4,    /* a search radius reaches L/3 of its box */
+    SPH_E_NOT_CONVERGED = 5,  /* some h did not converge within max_iter */
+    SPH_E_STATE = 6           /* call out of order (e.g. force before density) */
+} sph_status;
+
+/* Parameters, copied by sph_create. Zero-initialise and set what you need;
+ * a zero field takes the default shown. */
+typedef struct {
+    double  n_ngb;        /* weighted neighbour number the h solve targets (48) */
+    double  gamma;        /* adiabatic index of the ideal-gas law (5/3) */
+    double  alpha_visc;   /* artificial-viscosity strength (0.8); negative = off */
+    double  n_tol;        /* h solve stops when |n_i / n_ngb - 1| <= n_tol (1e-6),
+                             or when the Newton step is below FP32 resolution */
+    int32_t max_iter;     /* Newton iterations per particle (64) */
+    double  h_margin;     /* cells are built for search radii h_margin * h_guess
+                             (1.26); h may grow by this factor before a rebuild */
+    double  cell_ratio;   /* cells below the top grid are at least
+                             cell_ratio * (largest search radius inside) wide (1.0) */
+    int32_t leaf_target;  /* a cell with more particles than this is split when
+                             the width rule allows it (64) */
+    int64_t workspace_limit; /* device bytes the context may allocate; 0 = no limit */
+    int32_t timing;       /* nonzero: record HIP events around the hot kernels
+                             (read with sph_get_timings; adds one stream
+                             synchronisation to sph_force) */
+} sph_params;
+
+/* Durations of the last calls, in milliseconds of GPU time measured with HIP
+ * events on the caller's stream (zero unless sph_params.timing was set). */
+typedef struct {
+    double density_kernel_ms;  /* FP32 density kernel, summed over rebuild passes */
+    double density_call_ms;    /* whole sph_density: prologues, kernels, copies */
+    double force_kernel_ms;    /* FP32 force kernel */
+    double force_call_ms;      /* whole sph_force: ghost step, kernel, copies */
+    double build_ms;           /* host wall time of the last sph_build_cells */
+    int32_t density_launches;  /* density kernel launches of the last sph_density */
+} sph_timings;
+
+typedef struct {
+    int32_t sweeps;             /* most Newton evaluations any particle needed */
+    int32_t rebuilds;           /* cell rebuilds forced by h outgrowing its cell */
+    int64_t unconverged;        /* particles whose h did not converge */
+    int64_t interactions_density; /* #{(i, j), j != i : r_ij < h_i} at the final h */
+    int64_t interactions_force;   /* #{(i, j), j != i : r_ij < max(h_i, h_j)} */
+    int64_t candidates_density; /* (i, j) candidate pairs tested, summed over sweeps */
+    int64_t candidates_force;   /* (i, j) candidate pairs tested by the force loop */
+    int64_t n_cells;            /* leaf cells of the current build */
+    int64_t n_pairs;            /* (cell, neighbour cell) entries, self included */
+    int64_t sweep_interactions_density; /* pairs inside the trial h, summed over
+                                           every Newton evaluation */
+} sph_stats;
+
+/* Create a context on HIP device `hip_device`. `params` (host) may be NULL
+ * for all defaults. On success *out owns device memory until sph_destroy. */
+sph_status sph_create(const sph_params* params, int hip_device, sph_ctx** out);
+
+/* Free everything the context owns. Waits for its pending work. NULL is a no-op. */
+void sph_destroy(sph_ctx* ctx);
+
+/*
+ * Bin particles into cells and build the cell-pair (self and pair task)
+ * lists: section 3.1 and Fig. 1 (cells at least as wide as the search radius,
+ * so neighbours lie in the same or adjacent cells; the mesh refined
+ * adaptively; neighbouring cells found with a tree).
+ *   n_boxes    number of periodic boxes (1 .. 1024)
+ *   box_first  host, n_boxes + 1 entries, box_first[0] = 0, non-decreasing,
+ *              box_first[n_boxes] = n
+ *   box_len    host, n_boxes side lengths (> 0)
+ *   n          number of particles (>= 1)
+ *   pos        device, 3n doubles (AoS), any real values (wrapped into each box)
+ *   h_guess    device, n floats (> 0): starting smoothing lengths; the cells
+ *              are sized for search radii h_margin * h_guess
+ * The context keeps a copy of the wrapped positions; `pos` and `h_guess` may
+ * be reused once the stream reaches this call's end.
+ * Errors: SPH_E_ARG, SPH_E_H_TOO_LARGE (h_margin * max h_guess of a box above
+ * a third of its side), SPH_E_NOMEM, SPH_E_HIP. Synchronises `stream`.
+ */
+sph_status sph_build_cells(sph_ctx* ctx, int32_t n_boxes, const int64_t* box_first,
+                           const double* box_len, int64_t n, const double* pos,
+                           const float* h_guess, void* stream);
+
+/*
+ * Density loop (section 2, Eq. 1) with the smoothing length of every particle
+ * solved for n_ngb weighted neighbours (section 2), FP32 arithmetic on FP32
+ * cell-relative offsets of the FP64 positions.
+ *   mass        device, n floats (> 0)
+ *   h           device, n floats: in, starting h (usually the h_guess given
+ *               to sph_build_cells); out, converged h
+ *   rho         device, n floats out: density at the converged h
+ *   f_gradh     device, n floats out: grad-h factor f
+ *   n_weighted  device, n floats out, may be NULL: (4 pi / 3) h^3 sum_j W
+ *   stats       host, may be NULL: filled on return
+ * If some h outgrows its cell the cells are rebuilt around the current h and
+ * the unconverged particles are solved again (counted in stats->rebuilds).
+ * Errors: SPH_E_STATE (no build), SPH_E_ARG, SPH_E_NOT_CONVERGED (outputs of
+ * the converged particles are valid), SPH_E_H_TOO_LARGE, SPH_E_HIP.
+ * Synchronises `stream` once.
+ */
+sph_status sph_density(sph_ctx* ctx, const float* mass, float* h, float* rho, float* f_gradh,
+                       float* n_weighted, sph_stats* stats, void* stream);
+
+/*
+ * Force loop after the density (section 3.1: the density of a cell and its
+ * neighbours precedes its pressure gradient): the ghost step computes P, c and
+ * Phi from the density and u, then each pair inside max(h_i, h_j) adds the
+ * pressure and viscosity terms of the Gadget-2 grad-h form (section 2, after
+ * Eq. 2) to a_i and du_i/dt. FP32 arithmetic and accumulation.
+ *   vel    device, 3n floats (AoS)
+ *   u      device, n floats (>= 0): specific internal energy
+ *   acc    device, 3n floats out
+ *   dudt   device, n floats out
+ *   cons   host, may be NULL: 4 doubles per box, sum_i m_i a_i (x, y, z) and
+ *          sum_i m_i (v_i . a_i + du_i/dt), accumulated in FP64
+ *   stats  host, may be NULL: interaction counts of this call
+ * Uses the h, rho and f of the last successful sph_density on this context.
+ * Errors: SPH_E_STATE, SPH_E_ARG, SPH_E_HIP. Synchronises `stream` only when
+ * cons or stats is given.
+ */
+sph_status sph_force(sph_ctx* ctx, const float* vel, const float* u, float* acc, float* dudt,
+                     double* cons, sph_stats* stats, void* stream);
+
+/*
+ * The same density solve and force in plain FP64: one thread per particle
+ * walking its cell's neighbour list on FP64 positions, no LDS staging and no
+ * pair symmetry. The baseline the FP32 path is measured against; same
+ * arguments and errors as the FP32 calls, FP64 arrays.
+ */
+sph_status sph_density_f64(sph_ctx* ctx, const double* mass, double* h, double* rho,
+                           double* f_gradh, double* n_weighted, sph_stats* stats, void* stream);
+sph_status sph_force_f64(sph_ctx* ctx, const double* vel, const double* u, double* acc,
+                         double* dudt, double* cons, sph_stats* stats, void* stream);
+
+/* Copy the durations of the last calls into *out (host). Errors: SPH_E_ARG. */
+sph_status sph_get_timings(const sph_ctx* ctx, sph_timings* out);
+
+/* Static description of a status code. */
+const char* sph_status_string(sph_status s);
+
+/* Message of the last error on this context ("" if none); ctx may be NULL for
+ * errors of sph_create. The string stays valid until the next call. */
+const char* sph_last_error(const sph_ctx* ctx);
+
+/* Library version string. */
+const char* sph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_MI355X_H */

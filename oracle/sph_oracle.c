@@ -332,13 +332,19 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
  * particle with h <= 0 is treated as unknown and skipped.
  *   gross_a_out   sum_j |m_j G|, the scale the acceleration error is judged by
  *   gross_u_out   sum_j |m_j (Phi_i D_i + Pi Dbar / 2)(v_ij . rhat)|
+ *   scale_a_out   sum_j m_j (|Phi_i| Dm_i + |Phi_j| Dm_j + |Pi| (Dm_i + Dm_j) / 2), where
+ *                 Dm_k = 8 / (pi h_k^4) max|w'| (max|w'| = 2) for r < h_k, else 0: the
+ *                 pair terms at full kernel slope. Unlike the gross sum it does not
+ *                 shrink where w'(q) -> 0 at the kernel edge, so errors are judged
+ *                 against a scale that rounding in q cannot exceed.
+ *   scale_u_out   sum_j m_j (|Phi_i| Dm_i + |Pi| (Dm_i + Dm_j) / 4) |v_ij . rhat|
  *   npair_out     #{j != i : r_ij < max(h_i, h_j)}
  */
 int orc_force(int64_t n, const double *pos, const double *vel, const double *mass,
               const double *u, const double *h, const double *rho, const double *f,
               double L, double gamma, double alpha, int64_t n_targets, const int64_t *targets,
               double *acc_out, double *dudt_out, double *gross_a_out, double *gross_u_out,
-              int64_t *npair_out, int nthreads, int64_t *bad)
+              double *scale_a_out, double *scale_u_out, int64_t *npair_out, int nthreads, int64_t *bad)
 {
     if (n <= 0 || !pos || !vel || !mass || !u || !h || !rho || !f || !acc_out || !dudt_out)
         return ORC_E_ARG;
@@ -384,7 +390,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             const double Pi_ = (gamma - 1.0) * rho[i] * u[i];
             const double ci = sqrt(gamma * (gamma - 1.0) * u[i]);
             const double Phii = f[i] * Pi_ / (rho[i] * rho[i]);
-            double ax = 0, ay = 0, az = 0, du = 0, ga = 0, gu = 0;
+            double ax = 0, ay = 0, az = 0, du = 0, ga = 0, gu = 0, sa = 0, su = 0;
             int64_t np = 0;
             for (int64_t k = 0; k < c.n; ++k) {
                 int64_t j = c.j[k];
@@ -415,6 +421,10 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                 du += e;
                 ga += fabs(mj * G);
                 gu += fabs(e);
+                double Dmi = r < hi_ ? 2.0 * 8.0 / (ORC_PI * hi_ * hi_ * hi_ * hi_) : 0.0;
+                double Dmj = r < hj ? 2.0 * 8.0 / (ORC_PI * hj * hj * hj * hj) : 0.0;
+                sa += mj * (fabs(Phii) * Dmi + fabs(Phij) * Dmj + fabs(Pv) * 0.5 * (Dmi + Dmj));
+                su += mj * (fabs(Phii) * Dmi + 0.25 * fabs(Pv) * (Dmi + Dmj)) * fabs(vr);
             }
             acc_out[3 * i + 0] = ax;
             acc_out[3 * i + 1] = ay;
@@ -422,6 +432,8 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             dudt_out[i] = du;
             if (gross_a_out) gross_a_out[i] = ga;
             if (gross_u_out) gross_u_out[i] = gu;
+            if (scale_a_out) scale_a_out[i] = sa;
+            if (scale_u_out) scale_u_out[i] = su;
             if (npair_out) npair_out[i] = np;
         }
         cand_free(&c);

@@ -1,0 +1,318 @@
+"""Python binding of the MI355X SPH neighbour-interaction library.
+
+The functions mirror the C ABI of ``include/sph.h`` one to one (same names,
+same arguments); ``Context`` wraps them for torch tensors. Everything here is
+argument marshalling: every step of the computation runs in the HIP kernels
+of ``libsph.so``. Importing the package does not load the library; the first
+call does, and fails loudly if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+SPH_OK = 0
+SPH_E_ARG = 1
+SPH_E_HIP = 2
+SPH_E_NOMEM = 3
+SPH_E_H_TOO_LARGE = 4
+SPH_E_NOT_CONVERGED = 5
+SPH_E_STATE = 6
+
+EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
+           "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
+           "sph_last_error", "sph_version")
+
+
+class sph_params(ctypes.Structure):
+    _fields_ = [("n_ngb", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("alpha_visc", ctypes.c_double), ("n_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("h_margin", ctypes.c_double),
+                ("cell_ratio", ctypes.c_double), ("leaf_target", ctypes.c_int32),
+                ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32)]
+
+
+class sph_stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("rebuilds", ctypes.c_int32),
+                ("unconverged", ctypes.c_int64), ("interactions_density", ctypes.c_int64),
+                ("interactions_force", ctypes.c_int64), ("candidates_density", ctypes.c_int64),
+                ("candidates_force", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("sweep_interactions_density", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class sph_timings(ctypes.Structure):
+    _fields_ = [("density_kernel_ms", ctypes.c_double), ("density_call_ms", ctypes.c_double),
+                ("force_kernel_ms", ctypes.c_double), ("force_call_ms", ctypes.c_double),
+                ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (status_string(code), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libsph.so``; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libsph.so is not built (run __graft_entry__.build() or "
+                           "python paper_1508_00115_amd/build.py); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    S = ctypes.c_int
+    lib.sph_create.argtypes = [ctypes.POINTER(sph_params), ctypes.c_int, ctypes.POINTER(P)]
+    lib.sph_create.restype = S
+    lib.sph_destroy.argtypes = [P]
+    lib.sph_destroy.restype = None
+    lib.sph_build_cells.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int64, P, P, P]
+    lib.sph_build_cells.restype = S
+    lib.sph_density.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
+    lib.sph_density.restype = S
+    lib.sph_force.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
+    lib.sph_force.restype = S
+    lib.sph_density_f64.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
+    lib.sph_density_f64.restype = S
+    lib.sph_force_f64.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
+    lib.sph_force_f64.restype = S
+    lib.sph_get_timings.argtypes = [P, ctypes.POINTER(sph_timings)]
+    lib.sph_get_timings.restype = S
+    lib.sph_status_string.argtypes = [S]
+    lib.sph_status_string.restype = ctypes.c_char_p
+    lib.sph_last_error.argtypes = [P]
+    lib.sph_last_error.restype = ctypes.c_char_p
+    lib.sph_version.argtypes = []
+    lib.sph_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+# ---- one-to-one wrappers of the C ABI -------------------------------------------
+
+
+def status_string(code: int) -> str:
+    return load_library().sph_status_string(int(code)).decode()
+
+
+def sph_last_error(ctx) -> str:
+    return load_library().sph_last_error(ctx).decode()
+
+
+def sph_version() -> str:
+    return load_library().sph_version().decode()
+
+
+def _check(code: int, ctx) -> None:
+    if code != SPH_OK:
+        raise SphError(code, sph_last_error(ctx))
+
+
+def sph_create(params: sph_params | None = None, hip_device: int = 0):
+    lib = load_library()
+    out = ctypes.c_void_p()
+    rc = lib.sph_create(ctypes.byref(params) if params is not None else None, int(hip_device),
+                        ctypes.byref(out))
+    _check(rc, None)
+    return out
+
+
+def sph_destroy(ctx) -> None:
+    load_library().sph_destroy(ctx)
+
+
+def sph_build_cells(ctx, n_boxes, box_first_ptr, box_len_ptr, n, pos_ptr, h_guess_ptr, stream) -> int:
+    return load_library().sph_build_cells(ctx, n_boxes, box_first_ptr, box_len_ptr, n, pos_ptr,
+                                          h_guess_ptr, stream)
+
+
+def sph_density(ctx, mass, h, rho, f, nw, stats, stream) -> int:
+    return load_library().sph_density(ctx, mass, h, rho, f, nw, stats, stream)
+
+
+def sph_force(ctx, vel, u, acc, dudt, cons, stats, stream) -> int:
+    return load_library().sph_force(ctx, vel, u, acc, dudt, cons, stats, stream)
+
+
+def sph_density_f64(ctx, mass, h, rho, f, nw, stats, stream) -> int:
+    return load_library().sph_density_f64(ctx, mass, h, rho, f, nw, stats, stream)
+
+
+def sph_force_f64(ctx, vel, u, acc, dudt, cons, stats, stream) -> int:
+    return load_library().sph_force_f64(ctx, vel, u, acc, dudt, cons, stats, stream)
+
+
+def sph_get_timings(ctx, out) -> int:
+    return load_library().sph_get_timings(ctx, out)
+
+
+# ---- torch convenience ---------------------------------------------------------------
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One library context on one GPU, driven with torch tensors."""
+
+    def __init__(self, device: int = 0, **params):
+        p = sph_params()
+        for k, v in params.items():
+            setattr(p, k, v)
+        self.device = device
+        self.ctx = sph_create(p, device)
+        self.n = 0
+        self.n_boxes = 0
+
+    def close(self):
+        if self.ctx:
+            sph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timings(self) -> dict:
+        t = sph_timings()
+        _check(sph_get_timings(self.ctx, ctypes.byref(t)), self.ctx)
+        return t.as_dict()
+
+    def build_cells(self, pos, h_guess, box_first=None, box_len=None, stream=None):
+        import torch
+        n = pos.shape[0]
+        if box_first is None:
+            box_first = np.array([0, n], dtype=np.int64)
+        if box_len is None:
+            box_len = np.ones(len(box_first) - 1)
+        bf = np.ascontiguousarray(box_first, dtype=np.int64)
+        bl = np.ascontiguousarray(box_len, dtype=np.float64)
+        rc = sph_build_cells(self.ctx, len(bl), bf.ctypes.data_as(ctypes.c_void_p),
+                             bl.ctypes.data_as(ctypes.c_void_p), n,
+                             _dev(pos, torch.float64, (n, 3), "pos"),
+                             _dev(h_guess, torch.float32, (n,), "h_guess"), _stream(stream))
+        _check(rc, self.ctx)
+        self.n = n
+        self.n_boxes = len(bl)
+
+    def density(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
+        """h is updated in place; returns the output tensors and the stats."""
+        import torch
+        n = self.n or mass.shape[0]
+        rho = torch.empty(n, dtype=torch.float32, device=h.device) if rho is None else rho
+        f = torch.empty(n, dtype=torch.float32, device=h.device) if f is None else f
+        st = sph_stats()
+        rc = sph_density(self.ctx, _dev(mass, torch.float32, (n,), "mass"),
+                         _dev(h, torch.float32, (n,), "h"), _dev(rho, torch.float32, (n,), "rho"),
+                         _dev(f, torch.float32, (n,), "f"),
+                         None if nw is None else _dev(nw, torch.float32, (n,), "nw"),
+                         ctypes.byref(st), _stream(stream))
+        _check(rc, self.ctx)
+        return {"h": h, "rho": rho, "f": f, "nw": nw, "stats": st.as_dict()}
+
+    def force(self, vel, u, acc=None, dudt=None, cons=True, stream=None) -> dict:
+        import torch
+        n = self.n or u.shape[0]
+        acc = torch.empty((n, 3), dtype=torch.float32, device=u.device) if acc is None else acc
+        dudt = torch.empty(n, dtype=torch.float32, device=u.device) if dudt is None else dudt
+        cb = np.zeros((self.n_boxes, 4)) if cons else None
+        st = sph_stats()
+        rc = sph_force(self.ctx, _dev(vel, torch.float32, (n, 3), "vel"), _dev(u, torch.float32, (n,), "u"),
+                       _dev(acc, torch.float32, (n, 3), "acc"), _dev(dudt, torch.float32, (n,), "dudt"),
+                       None if cb is None else cb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                       _stream(stream))
+        _check(rc, self.ctx)
+        return {"acc": acc, "dudt": dudt, "cons": cb, "stats": st.as_dict()}
+
+    def density_f64(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
+        import torch
+        n = self.n
+        rho = torch.empty(n, dtype=torch.float64, device=h.device) if rho is None else rho
+        f = torch.empty(n, dtype=torch.float64, device=h.device) if f is None else f
+        st = sph_stats()
+        rc = sph_density_f64(self.ctx, _dev(mass, torch.float64, (n,), "mass"),
+                             _dev(h, torch.float64, (n,), "h"), _dev(rho, torch.float64, (n,), "rho"),
+                             _dev(f, torch.float64, (n,), "f"),
+                             None if nw is None else _dev(nw, torch.float64, (n,), "nw"),
+                             ctypes.byref(st), _stream(stream))
+        _check(rc, self.ctx)
+        return {"h": h, "rho": rho, "f": f, "nw": nw, "stats": st.as_dict()}
+
+    def force_f64(self, vel, u, acc=None, dudt=None, cons=True, stream=None) -> dict:
+        import torch
+        n = self.n
+        acc = torch.empty((n, 3), dtype=torch.float64, device=u.device) if acc is None else acc
+        dudt = torch.empty(n, dtype=torch.float64, device=u.device) if dudt is None else dudt
+        cb = np.zeros((self.n_boxes, 4)) if cons else None
+        st = sph_stats()
+        rc = sph_force_f64(self.ctx, _dev(vel, torch.float64, (n, 3), "vel"),
+                           _dev(u, torch.float64, (n,), "u"), _dev(acc, torch.float64, (n, 3), "acc"),
+                           _dev(dudt, torch.float64, (n,), "dudt"),
+                           None if cb is None else cb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                           _stream(stream))
+        _check(rc, self.ctx)
+        return {"acc": acc, "dudt": dudt, "cons": cb, "stats": st.as_dict()}
+
+
+def run_workload(ctx: Context, d: dict, device="cuda:0", fp64: bool = False) -> dict:
+    """Upload a workload dict (see the ``workloads`` package) and run build,
+    density and force; returns host numpy copies of every output."""
+    import torch
+    pos = torch.from_numpy(d["pos"]).to(device)
+    h0 = torch.from_numpy(d["h0"]).to(device)
+    ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
+    ft = torch.float64 if fp64 else torch.float32
+    mass = torch.from_numpy(d["mass"]).to(device=device, dtype=ft)
+    h = torch.from_numpy(d["h0"]).to(device=device, dtype=ft)
+    vel = torch.from_numpy(d["vel"]).to(device=device, dtype=ft)
+    u = torch.from_numpy(d["u"]).to(device=device, dtype=ft)
+    nw = torch.empty_like(h)
+    if fp64:
+        dr = ctx.density_f64(mass, h, nw=nw)
+        fr = ctx.force_f64(vel, u)
+    else:
+        dr = ctx.density(mass, h, nw=nw)
+        fr = ctx.force(vel, u)
+    torch.cuda.synchronize()
+    out = {k: dr[k].double().cpu().numpy() for k in ("h", "rho", "f", "nw")}
+    out["acc"] = fr["acc"].double().cpu().numpy()
+    out["dudt"] = fr["dudt"].double().cpu().numpy()
+    out["cons"] = fr["cons"]
+    out["stats_density"] = dr["stats"]
+    out["stats_force"] = fr["stats"]
+    return out

@@ -1,0 +1,678 @@
+// Cell build: the cells of section 3.1 of the Swift paper.
+//
+// Particles are binned into a uniform top grid per box whose cells are at
+// least as wide as the largest search radius in the box (so every neighbour of
+// a particle lies in the same or one of the 26 adjacent top cells, Fig. 1),
+// then each top cell is refined as an octree: a cell is split when it holds
+// more than leaf_target particles and its children would still be at least
+// cell_ratio times the largest search radius inside (the mesh "needs to be
+// adaptive", section 3.1). Leaves hold contiguous ranges of the Morton-sorted
+// particles. For every leaf the tree is walked from the 27 surrounding top
+// cells to collect each leaf within reach -- the cell-pair tasks, found with a
+// tree as the end of section 3.1 describes -- with the periodic image of each.
+//
+// All of it runs on the GPU: integer keys, a radix sort, one pass of small
+// kernels per tree level, and a stack-based walk per leaf. The host only reads
+// back counts to size buffers.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int MAX_STACK = 96;
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+struct KeyLayout {
+    int bits_top;  // bits of the top-cell index
+    int levels;    // octree levels below the top grid (3 key bits each)
+};
+
+__global__ void k_wrap(int64_t n, const double* __restrict__ pos, const int64_t* __restrict__ box_first,
+                       int n_boxes, const double* __restrict__ box_len, const float* __restrict__ hg,
+                       double* __restrict__ pos_w, float* __restrict__ hg_copy,
+                       unsigned* __restrict__ box_hmax, float margin, int64_t* __restrict__ ctr)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int b = box_of(box_first, n_boxes, p);
+    const double L = box_len[b];
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * p + a];
+        bad |= !isfinite(x);
+        double y = x - L * floor(x / L);
+        if (!(y < L) || !(y >= 0.0)) y = 0.0;
+        pos_w[3 * p + a] = y;
+    }
+    float h = hg[p];
+    bad |= !(h > 0.0f) || !isfinite(h);
+    hg_copy[p] = h;
+    if (bad) {
+        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+        return;
+    }
+    atomicMax(&box_hmax[b], __float_as_uint(margin * h));
+}
+
+// Largest search radius per box from the stored (caller-order) h guesses.
+__global__ void k_box_hmax(int64_t n, const int64_t* __restrict__ box_first, int n_boxes,
+                           const float* __restrict__ hg, unsigned* __restrict__ box_hmax, float margin,
+                           int64_t* __restrict__ ctr)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float h = hg[p];
+    if (!(h > 0.0f) || !isfinite(h)) {
+        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+        return;
+    }
+    atomicMax(&box_hmax[box_of(box_first, n_boxes, p)], __float_as_uint(margin * h));
+}
+
+__global__ void k_keys(int64_t n, const double* __restrict__ pos_w, const int64_t* __restrict__ box_first,
+                       int n_boxes, const double* __restrict__ box_len, const int* __restrict__ box_G,
+                       KeyLayout kl, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int b = box_of(box_first, n_boxes, p);
+    const int G = box_G[b];
+    const double wtop = box_len[b] / G;
+    const uint32_t nsub = 1u << kl.levels;
+    uint32_t tc[3], sc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double y = pos_w[3 * p + a];
+        double c = floor(y / wtop);
+        int ci = (int)c;
+        ci = ci < 0 ? 0 : (ci >= G ? G - 1 : ci);
+        double s = (y - ci * wtop) / wtop * (double)nsub;
+        long si = (long)floor(s);
+        si = si < 0 ? 0 : (si >= (long)nsub ? (long)nsub - 1 : si);
+        tc[a] = (uint32_t)ci;
+        sc[a] = (uint32_t)si;
+    }
+    const uint64_t top = ((uint64_t)tc[0] * G + tc[1]) * G + tc[2];
+    const uint64_t mort = (spread3(sc[0]) << 2) | (spread3(sc[1]) << 1) | spread3(sc[2]);
+    keys[p] = ((uint64_t)b << (kl.bits_top + 3 * kl.levels)) | (top << (3 * kl.levels)) | mort;
+    vals[p] = (uint32_t)p;
+}
+
+__global__ void k_sorted_H(int64_t n, const uint32_t* __restrict__ perm, const float* __restrict__ hg,
+                           float margin, float* __restrict__ Hs, int* __restrict__ leaf_tmp)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    Hs[p] = margin * hg[perm[p]];
+    leaf_tmp[p] = -1;
+}
+
+__global__ void k_fill_int(int64_t n, int* __restrict__ a, int v)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) a[p] = v;
+}
+
+__global__ void k_lvl_head(int64_t n, const uint64_t* __restrict__ keys, const int* __restrict__ leaf_tmp,
+                           int shift, uint32_t* __restrict__ head)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t h = 0;
+    if (leaf_tmp[p] < 0) {
+        h = (p == 0) || (leaf_tmp[p - 1] >= 0) || ((keys[p] >> shift) != (keys[p - 1] >> shift));
+    }
+    head[p] = h;
+}
+
+// Node of every unassigned particle at level l; node start, count and
+// largest search radius.
+__global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const int* __restrict__ leaf_tmp,
+                            const uint32_t* __restrict__ head, const uint32_t* __restrict__ excl,
+                            const float* __restrict__ Hs, int level, KeyLayout kl, int64_t node_base,
+                            int* __restrict__ nid, int* __restrict__ nd_start, int* __restrict__ nd_count,
+                            unsigned* __restrict__ nd_hmax, int* __restrict__ nd_box,
+                            int* __restrict__ nd_level, int* __restrict__ nd_coord,
+                            const int* __restrict__ box_G)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || leaf_tmp[p] >= 0) return;
+    const int64_t id = node_base + (int64_t)excl[p] + head[p] - 1;
+    nid[p] = (int)id;
+    if (head[p]) {
+        const uint64_t k = keys[p];
+        const int b = (int)(k >> (kl.bits_top + 3 * kl.levels));
+        const uint64_t top = (k >> (3 * kl.levels)) & ((1ull << kl.bits_top) - 1);
+        const int G = box_G[b];
+        const uint64_t pre = (k & ((1ull << (3 * kl.levels)) - 1)) >> (3 * (kl.levels - level));
+        const uint32_t mx = compact3(pre >> 2), my = compact3(pre >> 1), mz = compact3(pre);
+        const uint32_t tz = (uint32_t)(top % G), ty = (uint32_t)((top / G) % G), tx = (uint32_t)(top / ((uint64_t)G * G));
+        nd_start[id] = (int)p;
+        nd_box[id] = b;
+        nd_level[id] = level;
+        nd_coord[3 * id + 0] = (int)((tx << level) | mx);
+        nd_coord[3 * id + 1] = (int)((ty << level) | my);
+        nd_coord[3 * id + 2] = (int)((tz << level) | mz);
+    }
+    atomicAdd(&nd_count[id], 1);
+    atomicMax(&nd_hmax[id], __float_as_uint(Hs[p]));
+}
+
+__global__ void k_lvl_decide(int64_t M, int64_t node_base, int level, int max_level, int leaf_target,
+                             float cell_ratio, const int* __restrict__ nd_count,
+                             const unsigned* __restrict__ nd_hmax, const int* __restrict__ nd_box,
+                             const double* __restrict__ box_len, const int* __restrict__ box_G,
+                             uint32_t* __restrict__ nflag, int* __restrict__ nd_child0,
+                             int* __restrict__ nd_child1)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int64_t id = node_base + k;
+    const int b = nd_box[id];
+    const double w = box_len[b] / box_G[b] / (double)(1u << level);
+    const float hm = __uint_as_float(nd_hmax[id]);
+    const bool split = level < max_level && nd_count[id] > leaf_target && (double)(cell_ratio * hm) <= 0.5 * w;
+    nflag[k] = split ? 0u : 1u;
+    nd_child0[id] = -1;
+    nd_child1[id] = -1;
+}
+
+__global__ void k_lvl_leaves(int64_t M, int64_t node_base, int64_t leaf_base,
+                             const uint32_t* __restrict__ nflag, const uint32_t* __restrict__ nscan,
+                             int* __restrict__ nd_leaf, int* __restrict__ lo2node)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int64_t id = node_base + k;
+    if (nflag[k]) {
+        const int64_t lo = leaf_base + nscan[k];
+        nd_leaf[id] = (int)lo;
+        lo2node[lo] = (int)id;
+    } else {
+        nd_leaf[id] = -1;
+    }
+}
+
+__global__ void k_lvl_assign(int64_t n, const int* __restrict__ nid, const int* __restrict__ nd_leaf,
+                             int* __restrict__ leaf_tmp)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || leaf_tmp[p] >= 0) return;
+    const int lf = nd_leaf[nid[p]];
+    if (lf >= 0) leaf_tmp[p] = lf;
+}
+
+// Children of the split nodes of the previous level: the level-l nodes holding
+// the first and last particle of each split parent.
+__global__ void k_lvl_children(int64_t Mprev, int64_t base_prev, const int* __restrict__ nd_leaf,
+                               const int* __restrict__ nd_start, const int* __restrict__ nd_count,
+                               const int* __restrict__ nid, int* __restrict__ nd_child0,
+                               int* __restrict__ nd_child1)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mprev) return;
+    const int64_t id = base_prev + k;
+    if (nd_leaf[id] >= 0) return;
+    const int s = nd_start[id];
+    nd_child0[id] = nid[s];
+    nd_child1[id] = nid[s + nd_count[id] - 1];
+}
+
+__global__ void k_top_table(int64_t M, const int* __restrict__ nd_box, const int* __restrict__ nd_coord,
+                            const int* __restrict__ box_G, const int64_t* __restrict__ box_top_base,
+                            int* __restrict__ top)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= M) return;
+    const int b = nd_box[id];
+    const int G = box_G[b];
+    const int64_t t = ((int64_t)nd_coord[3 * id] * G + nd_coord[3 * id + 1]) * G + nd_coord[3 * id + 2];
+    top[box_top_base[b] + t] = (int)id;
+}
+
+__global__ void k_leaf_head(int64_t n, const int* __restrict__ leaf_tmp, uint32_t* __restrict__ head)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    head[p] = (p == 0) || (leaf_tmp[p] != leaf_tmp[p - 1]);
+}
+
+__global__ void k_leaf_fill(int64_t n, const uint32_t* __restrict__ head, const uint32_t* __restrict__ excl,
+                            const int* __restrict__ leaf_tmp, const int* __restrict__ lo2node,
+                            int* __restrict__ leaf_of, int* __restrict__ lf_start, int* __restrict__ lf_node)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int L = (int)(excl[p] + head[p]) - 1;
+    leaf_of[p] = L;
+    if (head[p]) {
+        lf_start[L] = (int)p;
+        lf_node[L] = lo2node[leaf_tmp[p]];
+    }
+}
+
+__global__ void k_leaf_fix(int64_t nl, const int* __restrict__ lf_node, const int* __restrict__ nd_count,
+                           const unsigned* __restrict__ nd_hmax, int* __restrict__ nd_leaf,
+                           int* __restrict__ lf_count, float* __restrict__ lf_hmax)
+{
+    int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= nl) return;
+    const int id = lf_node[L];
+    nd_leaf[id] = (int)L;
+    lf_count[L] = nd_count[id];
+    lf_hmax[L] = __uint_as_float(nd_hmax[id]);
+}
+
+__device__ __forceinline__ void node_geom(int id, const int* nd_coord, const int* nd_level, double wtop,
+                                          double c[3], double& w)
+{
+    const int l = nd_level[id];
+    w = wtop / (double)(1u << l);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = ((double)nd_coord[3 * id + a] + 0.5) * w;
+}
+
+// Walk the tree from the 27 top cells around leaf a and list every leaf whose
+// cell box lies within max(Hmax_a, Hmax_leaf) of a's cell box. fill == false
+// counts, fill == true writes the list at p_start[a].
+__global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ lf_node,
+                           const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
+                           const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
+                           const int* __restrict__ nd_leaf, const int* __restrict__ nd_child0,
+                           const int* __restrict__ nd_child1, const int* __restrict__ top,
+                           const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
+                           const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
+                           const uint32_t* __restrict__ p_start, int* __restrict__ p_leaf,
+                           float4* __restrict__ p_shift, int* __restrict__ p_code,
+                           int64_t* __restrict__ ctr)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_leaves) return;
+    const int A = lf_node[a];
+    const int b = nd_box[A];
+    const int G = box_G[b];
+    const double L = box_len[b];
+    const double wtop = L / G;
+    double cA[3], wA;
+    node_geom(A, nd_coord, nd_level, wtop, cA, wA);
+    const float HA = __uint_as_float(nd_hmax[A]);
+    const int lA = nd_level[A];
+    const int tA[3] = {nd_coord[3 * A] >> lA, nd_coord[3 * A + 1] >> lA, nd_coord[3 * A + 2] >> lA};
+    const double eps = 1e-9 * wtop;
+    uint32_t cnt = 0;
+    const uint32_t base = fill ? p_start[a] : 0u;
+    int stack[MAX_STACK];
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int t[3] = {tA[0] + dx, tA[1] + dy, tA[2] + dz};
+                int s[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    s[k] = 0;
+                    if (t[k] < 0) { t[k] += G; s[k] = -1; }
+                    else if (t[k] >= G) { t[k] -= G; s[k] = 1; }
+                }
+                const int T = top[box_top_base[b] + ((int64_t)t[0] * G + t[1]) * G + t[2]];
+                if (T < 0) continue;
+                const double S[3] = {s[0] * L, s[1] * L, s[2] * L};
+                int sp = 0;
+                stack[sp++] = T;
+                while (sp > 0) {
+                    const int X = stack[--sp];
+                    double cX[3], wX;
+                    node_geom(X, nd_coord, nd_level, wtop, cX, wX);
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        double g = fabs(cX[k] + S[k] - cA[k]) - 0.5 * (wA + wX) - eps;
+                        g = g > 0.0 ? g : 0.0;
+                        d2 += g * g;
+                    }
+                    const double R = (double)fmaxf(HA, __uint_as_float(nd_hmax[X]));
+                    if (d2 >= R * R) continue;
+                    const int lf = nd_leaf[X];
+                    if (lf >= 0) {
+                        if (fill) {
+                            const uint32_t o = base + cnt;
+                            p_leaf[o] = lf;
+                            p_shift[o] = make_float4((float)(cX[0] + S[0] - cA[0]), (float)(cX[1] + S[1] - cA[1]),
+                                                     (float)(cX[2] + S[2] - cA[2]), 0.0f);
+                            p_code[o] = image_code(s[0], s[1], s[2]);
+                        }
+                        ++cnt;
+                    } else {
+                        const int c0 = nd_child0[X], c1 = nd_child1[X];
+                        if (sp + (c1 - c0 + 1) > MAX_STACK) {
+                            atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+                            continue;
+                        }
+                        for (int c = c1; c >= c0; --c) stack[sp++] = c;
+                    }
+                }
+            }
+    if (!fill) p_cnt[a] = cnt;
+}
+
+// Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
+__global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ pos_w,
+                              const int* __restrict__ leaf_of, const int* __restrict__ lf_node,
+                              const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
+                              const int* __restrict__ nd_box, const int* __restrict__ box_G,
+                              const double* __restrict__ box_len, double* __restrict__ pos_s,
+                              float4* __restrict__ xrel)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = perm[p];
+    const int id = lf_node[leaf_of[p]];
+    const int b = nd_box[id];
+    double c[3], w;
+    node_geom(id, nd_coord, nd_level, box_len[b] / box_G[b], c, w);
+    double x[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        x[a] = pos_w[3 * (int64_t)o + a];
+        pos_s[3 * p + a] = x[a];
+    }
+    xrel[p] = make_float4((float)(x[0] - c[0]), (float)(x[1] - c[1]), (float)(x[2] - c[2]), 0.0f);
+}
+
+int ceil_log2(uint64_t v)
+{
+    int b = 0;
+    while ((1ull << b) < v) ++b;
+    return b;
+}
+
+uint32_t read_u32(const uint32_t* d, hipStream_t s)
+{
+    uint32_t v = 0;
+    SPH_HIP(hipMemcpyAsync(&v, d, 4, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+namespace sph {
+
+// Everything after the positions are wrapped: keys, sort, tree, leaves, lists.
+static void build_from_wrapped(sph_ctx* c, hipStream_t s)
+{
+    const int64_t n = c->n;
+    const int nb = c->n_boxes;
+    const float margin = (float)c->prm.h_margin;
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+
+    // ---- largest search radius per box (k_wrap / k_box_hmax ran) -> top grid --------
+    unsigned* box_hmax = static_cast<unsigned*>(c->box_hmax.p);
+    std::vector<unsigned> hm(nb);
+    int64_t bad = 0;
+    SPH_HIP(hipMemcpyAsync(hm.data(), box_hmax, (size_t)nb * 4, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(&bad, &ctr[CT_BAD_INPUT], 8, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    SPH_REQUIRE(bad == 0, SPH_E_ARG, "non-finite position or non-positive/non-finite h_guess");
+    c->h_box_G.assign(nb, 0);
+    c->h_box_top_base.assign(nb + 1, 0);
+    uint64_t maxG3 = 1;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t cnt = c->h_box_first[b + 1] - c->h_box_first[b];
+        float H;
+        std::memcpy(&H, &hm[b], 4);
+        const double L = c->h_box_len[b];
+        int G = 3;
+        if (cnt > 0) {
+            SPH_REQUIRE(3.0 * (double)H <= L, SPH_E_H_TOO_LARGE,
+                        "box " + std::to_string(b) + ": search radius " + std::to_string(H) +
+                            " exceeds a third of the box side " + std::to_string(L));
+            G = (int)std::floor(L / (double)H);
+            // a top cell exactly one radius wide must still hold the radius after rounding
+            while (G > 3 && L / G < (double)H) --G;
+            G = std::max(3, std::min(G, 256));
+        }
+        c->h_box_G[b] = G;
+        c->h_box_top_base[b + 1] = c->h_box_top_base[b] + (int64_t)G * G * G;
+        maxG3 = std::max<uint64_t>(maxG3, (uint64_t)G * G * G);
+    }
+    c->n_top = c->h_box_top_base[nb];
+    c->bits_box = nb > 1 ? ceil_log2((uint64_t)nb) : 0;
+    c->bits_top = std::max(1, ceil_log2(maxG3));
+    c->levels = std::min(10, (63 - c->bits_box - c->bits_top) / 3);
+    SPH_REQUIRE(c->levels >= 1, SPH_E_ARG, "too many boxes or top cells for the key layout");
+    int* box_G = ensure<int>(c, c->box_G, nb);
+    int64_t* box_top_base = ensure<int64_t>(c, c->box_top_base, nb + 1);
+    SPH_HIP(hipMemcpyAsync(box_G, c->h_box_G.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(box_top_base, c->h_box_top_base.data(), (size_t)(nb + 1) * 8,
+                           hipMemcpyHostToDevice, s));
+
+    // ---- keys and sort -------------------------------------------------------------------
+    KeyLayout kl{c->bits_top, c->levels};
+    uint64_t* keys = ensure<uint64_t>(c, c->keys, n);
+    uint64_t* keys_alt = ensure<uint64_t>(c, c->keys_alt, n);
+    uint32_t* perm = ensure<uint32_t>(c, c->perm, n);
+    uint32_t* perm_alt = ensure<uint32_t>(c, c->perm_alt, n);
+    const int64_t* box_first = static_cast<int64_t*>(c->box_first.p);
+    const double* box_len = static_cast<double*>(c->box_len.p);
+    k_keys<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<double*>(c->pos_w.p), box_first, nb, box_len,
+                                            box_G, kl, keys, perm);
+    SPH_HIP(hipGetLastError());
+    const int key_bits = c->bits_box + c->bits_top + 3 * c->levels;
+    radix_sort(c, keys, perm, keys_alt, perm_alt, n, key_bits, s);
+
+    float* Hs = ensure<float>(c, c->Hs, n);
+    int* leaf_tmp = ensure<int>(c, c->lf_tmp, n);
+    k_sorted_H<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<float*>(c->hguess.p), margin, Hs,
+                                                leaf_tmp);
+    SPH_HIP(hipGetLastError());
+
+    // ---- tree, level by level ---------------------------------------------------------------
+    uint32_t* head = ensure<uint32_t>(c, c->head, n + 1);
+    uint32_t* excl = ensure<uint32_t>(c, c->scan1, n + 1);
+    int* nid = ensure<int>(c, c->nid, n);
+    uint32_t* d_tot = reinterpret_cast<uint32_t*>(&ctr[CT_TOTAL]);
+    int* top = ensure<int>(c, c->top, (size_t)c->n_top);
+    k_fill_int<<<blocks_for(c->n_top, BS), BS, 0, s>>>(c->n_top, top, -1);
+    SPH_HIP(hipGetLastError());
+
+    int64_t node_base = 0, leaf_base = 0, prev_base = 0, prev_M = 0;
+    // level-order leaf id -> node; parked in lf_start's buffer until the leaves
+    // are renumbered in Morton order
+    int* lo2node = ensure<int>(c, c->lf_start, n + 1);
+    for (int level = 0; level <= c->levels; ++level) {
+        const int shift = 3 * (c->levels - level);
+        k_lvl_head<<<blocks_for(n, BS), BS, 0, s>>>(n, keys, leaf_tmp, shift, head);
+        SPH_HIP(hipGetLastError());
+        scan_exclusive(c, head, excl, n, d_tot, s);
+        const int64_t M = read_u32(d_tot, s);
+        if (M == 0) break;
+        const int64_t need = node_base + M;
+        if (need > c->node_cap) {
+            const int64_t cap = std::max<int64_t>(need + need / 2, 1024);
+            grow_keep<int>(c, c->nd_start, cap, node_base, s);
+            grow_keep<int>(c, c->nd_count, cap, node_base, s);
+            grow_keep<unsigned>(c, c->nd_hmax, cap, node_base, s);
+            grow_keep<int>(c, c->nd_child0, cap, node_base, s);
+            grow_keep<int>(c, c->nd_child1, cap, node_base, s);
+            grow_keep<int>(c, c->nd_leaf, cap, node_base, s);
+            grow_keep<int>(c, c->nd_box, cap, node_base, s);
+            grow_keep<int>(c, c->nd_level, cap, node_base, s);
+            grow_keep<int>(c, c->nd_coord, 3 * cap, 3 * node_base, s);
+            c->node_cap = cap;
+        }
+        int* nd_start = static_cast<int*>(c->nd_start.p);
+        int* nd_count = static_cast<int*>(c->nd_count.p);
+        unsigned* nd_hmax = static_cast<unsigned*>(c->nd_hmax.p);
+        int* nd_child0 = static_cast<int*>(c->nd_child0.p);
+        int* nd_child1 = static_cast<int*>(c->nd_child1.p);
+        int* nd_leaf = static_cast<int*>(c->nd_leaf.p);
+        int* nd_box = static_cast<int*>(c->nd_box.p);
+        int* nd_level = static_cast<int*>(c->nd_level.p);
+        int* nd_coord = static_cast<int*>(c->nd_coord.p);
+        SPH_HIP(hipMemsetAsync(nd_count + node_base, 0, (size_t)M * 4, s));
+        SPH_HIP(hipMemsetAsync(nd_hmax + node_base, 0, (size_t)M * 4, s));
+        k_lvl_nodes<<<blocks_for(n, BS), BS, 0, s>>>(n, keys, leaf_tmp, head, excl, Hs, level, kl, node_base,
+                                                     nid, nd_start, nd_count, nd_hmax, nd_box, nd_level,
+                                                     nd_coord, box_G);
+        SPH_HIP(hipGetLastError());
+        if (level == 0) {
+            k_top_table<<<blocks_for(M, BS), BS, 0, s>>>(M, nd_box, nd_coord, box_G, box_top_base, top);
+            SPH_HIP(hipGetLastError());
+        } else {
+            k_lvl_children<<<blocks_for(prev_M, BS), BS, 0, s>>>(prev_M, prev_base, nd_leaf, nd_start,
+                                                                 nd_count, nid, nd_child0, nd_child1);
+            SPH_HIP(hipGetLastError());
+        }
+        uint32_t* nflag = ensure<uint32_t>(c, c->nflag, M + 1);
+        uint32_t* nscan = ensure<uint32_t>(c, c->nscan, M + 1);
+        k_lvl_decide<<<blocks_for(M, BS), BS, 0, s>>>(M, node_base, level, c->levels, c->prm.leaf_target,
+                                                      (float)c->prm.cell_ratio, nd_count, nd_hmax, nd_box,
+                                                      box_len, box_G, nflag, nd_child0, nd_child1);
+        SPH_HIP(hipGetLastError());
+        scan_exclusive(c, nflag, nscan, M, d_tot, s);
+        const int64_t K = read_u32(d_tot, s);
+        k_lvl_leaves<<<blocks_for(M, BS), BS, 0, s>>>(M, node_base, leaf_base, nflag, nscan, nd_leaf,
+                                                      lo2node);
+        SPH_HIP(hipGetLastError());
+        k_lvl_assign<<<blocks_for(n, BS), BS, 0, s>>>(n, nid, nd_leaf, leaf_tmp);
+        SPH_HIP(hipGetLastError());
+        prev_base = node_base;
+        prev_M = M;
+        node_base += M;
+        leaf_base += K;
+        if (K == M) break;  // every node of this level is a leaf
+    }
+    c->n_nodes = node_base;
+
+    // ---- leaves in Morton (particle) order ---------------------------------------------------
+    k_leaf_head<<<blocks_for(n, BS), BS, 0, s>>>(n, leaf_tmp, head);
+    SPH_HIP(hipGetLastError());
+    scan_exclusive(c, head, excl, n, d_tot, s);
+    const int64_t nl = read_u32(d_tot, s);
+    SPH_REQUIRE(nl == leaf_base, SPH_E_HIP, "leaf numbering mismatch");
+    c->n_leaves = nl;
+    int* leaf_of = ensure<int>(c, c->leaf_of, n);
+    // lo2node lives in lf_start's buffer; move it aside before lf_start is written
+    int* lo2 = ensure<int>(c, c->nid, std::max<int64_t>(n, nl));
+    SPH_HIP(hipMemcpyAsync(lo2, lo2node, (size_t)nl * 4, hipMemcpyDeviceToDevice, s));
+    int* lf_start = ensure<int>(c, c->lf_start, nl + 1);
+    int* lf_node = ensure<int>(c, c->lf_node, nl);
+    int* lf_count = ensure<int>(c, c->lf_count, nl);
+    float* lf_hmax = ensure<float>(c, c->lf_hmax, nl);
+    k_leaf_fill<<<blocks_for(n, BS), BS, 0, s>>>(n, head, excl, leaf_tmp, lo2, leaf_of, lf_start, lf_node);
+    SPH_HIP(hipGetLastError());
+    k_leaf_fix<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_node, static_cast<int*>(c->nd_count.p),
+                                                 static_cast<unsigned*>(c->nd_hmax.p),
+                                                 static_cast<int*>(c->nd_leaf.p), lf_count, lf_hmax);
+    SPH_HIP(hipGetLastError());
+
+    // ---- neighbour lists ------------------------------------------------------------------------
+    uint32_t* p_cnt = ensure<uint32_t>(c, c->p_cnt, nl + 1);
+    uint32_t* p_start = ensure<uint32_t>(c, c->p_start, nl + 1);
+    const int* nd_coord = static_cast<int*>(c->nd_coord.p);
+    const int* nd_level = static_cast<int*>(c->nd_level.p);
+    const int* nd_box = static_cast<int*>(c->nd_box.p);
+    const unsigned* nd_hmax = static_cast<unsigned*>(c->nd_hmax.p);
+    const int* nd_leaf = static_cast<int*>(c->nd_leaf.p);
+    const int* nd_child0 = static_cast<int*>(c->nd_child0.p);
+    const int* nd_child1 = static_cast<int*>(c->nd_child1.p);
+    k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 0, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
+                                                 nd_child0, nd_child1, top, box_top_base, box_G, box_len,
+                                                 p_cnt, nullptr, nullptr, nullptr, nullptr, ctr);
+    SPH_HIP(hipGetLastError());
+    scan_exclusive(c, p_cnt, p_start, nl, p_start + nl, s);
+    uint32_t np = 0;
+    int64_t bad2 = 0;
+    SPH_HIP(hipMemcpyAsync(&np, p_start + nl, 4, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(&bad2, &ctr[CT_BAD_INPUT], 8, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    SPH_REQUIRE(bad2 == 0, SPH_E_HIP, "tree walk stack overflow");
+    c->n_pairs = np;
+    int* p_leaf = ensure<int>(c, c->p_leaf, np);
+    float4* p_shift = ensure<float4>(c, c->p_shift, np);
+    int* p_code = ensure<int>(c, c->p_code, np);
+    k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 1, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
+                                                 nd_child0, nd_child1, top, box_top_base, box_G, box_len,
+                                                 p_cnt, p_start, p_leaf, p_shift, p_code, ctr);
+    SPH_HIP(hipGetLastError());
+
+    // ---- sorted particle streams ------------------------------------------------------------------
+    double* pos_s = ensure<double>(c, c->pos_s, 3 * n);
+    float4* xrel = ensure<float4>(c, c->xrel, n);
+    k_sorted_fill<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<double*>(c->pos_w.p), leaf_of, lf_node,
+                                                   nd_coord, nd_level, nd_box, box_G, box_len, pos_s, xrel);
+    SPH_HIP(hipGetLastError());
+    c->built = true;
+    c->density_done = false;
+    c->density64_done = false;
+}
+
+void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len, int64_t n,
+                 const double* pos, const float* h_guess, hipStream_t s)
+{
+    c->built = false;
+    c->density_done = false;
+    c->density64_done = false;
+    c->n = n;
+    c->n_boxes = n_boxes;
+    c->h_box_first.assign(box_first, box_first + n_boxes + 1);
+    c->h_box_len.assign(box_len, box_len + n_boxes);
+    int64_t* bf = ensure<int64_t>(c, c->box_first, n_boxes + 1);
+    double* bl = ensure<double>(c, c->box_len, n_boxes);
+    SPH_HIP(hipMemcpyAsync(bf, box_first, (size_t)(n_boxes + 1) * 8, hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(bl, box_len, (size_t)n_boxes * 8, hipMemcpyHostToDevice, s));
+    ensure<int64_t>(c, c->counters, CT_COUNT);
+    double* pw = ensure<double>(c, c->pos_w, 3 * n);
+    float* hg = ensure<float>(c, c->hguess, n);
+    unsigned* box_hmax = ensure<unsigned>(c, c->box_hmax, n_boxes);
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    SPH_HIP(hipMemsetAsync(box_hmax, 0, (size_t)n_boxes * 4, s));
+    SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
+    k_wrap<<<blocks_for(n, BS), BS, 0, s>>>(n, pos, bf, n_boxes, bl, h_guess, pw, hg, box_hmax,
+                                            (float)c->prm.h_margin, ctr);
+    SPH_HIP(hipGetLastError());
+    c->rebuilds = 0;
+    build_from_wrapped(c, s);
+}
+
+// Rebuild around new smoothing lengths (caller order) keeping the positions.
+void rebuild_cells(sph_ctx* c, const float* h_caller, hipStream_t s)
+{
+    float* hg = static_cast<float*>(c->hguess.p);
+    unsigned* box_hmax = static_cast<unsigned*>(c->box_hmax.p);
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    SPH_HIP(hipMemcpyAsync(hg, h_caller, (size_t)c->n * 4, hipMemcpyDeviceToDevice, s));
+    SPH_HIP(hipMemsetAsync(box_hmax, 0, (size_t)c->n_boxes * 4, s));
+    SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
+    k_box_hmax<<<blocks_for(c->n, BS), BS, 0, s>>>(c->n, static_cast<int64_t*>(c->box_first.p), c->n_boxes, hg,
+                                                   box_hmax, (float)c->prm.h_margin, ctr);
+    SPH_HIP(hipGetLastError());
+    build_from_wrapped(c, s);
+}
+
+}  // namespace sph

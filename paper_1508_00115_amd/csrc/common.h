@@ -1,0 +1,316 @@
+// Internal declarations shared by the library's translation units: the
+// context, device-buffer management, error plumbing and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sph.h"
+
+namespace sph {
+
+// ---- errors ------------------------------------------------------------------
+
+struct Error : std::runtime_error {
+    sph_status code;
+    Error(sph_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPH_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::sph::Error(SPH_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define SPH_REQUIRE(cond, code, msg)                        \
+    do {                                                    \
+        if (!(cond)) throw ::sph::Error((code), (msg));     \
+    } while (0)
+
+// ---- device buffers ----------------------------------------------------------
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace sph
+
+// Per-particle state of one FP32 density solve: flags in the caller's order.
+enum : uint8_t { ST_ACTIVE = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_UNCONVERGED = 3 };
+
+// Device counters (int64 slots) written by the hot kernels.
+enum {
+    CT_DENS_INTER = 0,   // ordered density interactions at the final h
+    CT_DENS_CAND = 1,    // candidate pairs tested by all density sweeps
+    CT_FORCE_INTER = 2,  // ordered force interactions
+    CT_FORCE_CAND = 3,   // candidate pairs tested by the force loop
+    CT_SWEEPS = 4,       // most evaluations any particle needed (max)
+    CT_OVERFLOW = 5,     // particles whose root lies beyond their search radius
+    CT_UNCONV = 6,       // particles that hit max_iter
+    CT_BAD_INPUT = 7,    // non-finite or non-positive inputs seen by a kernel
+    CT_QUEUE = 8,        // 8 work-queue heads (one per XCD) start here
+    CT_TOTAL = 16,       // scratch for device-computed totals read by the host
+    CT_DENS_SWEEP_INTER = 17,  // pairs inside the trial h, summed over every evaluation
+    CT_COUNT = 24
+};
+
+struct sph_ctx {
+    sph_params prm{};
+    int device = 0;
+    std::string err;
+    size_t allocated = 0;
+    std::vector<sph::Buf*> bufs;
+
+    // ---- build (sph_build_cells) ---------------------------------------------
+    bool built = false;
+    bool density_done = false;
+    bool density64_done = false;
+    int64_t n = 0;
+    int32_t n_boxes = 0;
+    std::vector<int64_t> h_box_first;
+    std::vector<double> h_box_len;
+    std::vector<int32_t> h_box_G;          // top-grid cells per side of each box
+    std::vector<int64_t> h_box_top_base;   // offset of each box in the top-cell table
+    int bits_box = 0, bits_top = 0, levels = 0;
+    int64_t n_top = 0;                     // entries of the top-cell table
+    int64_t n_nodes = 0, n_leaves = 0, n_pairs = 0;
+    int32_t rebuilds = 0;
+
+    sph::Buf box_first, box_len, box_G, box_top_base, box_hmax;  // per box
+    sph::Buf pos_w;          // double3 AoS, wrapped, caller order
+    sph::Buf hguess;         // float, caller order (copy of h_guess)
+    sph::Buf keys, keys_alt, perm, perm_alt;  // sort
+    sph::Buf pos_s;          // double3 AoS, sorted
+    sph::Buf xrel;           // float4 (x, y, z, 0) offsets from the leaf centre, sorted
+    sph::Buf Hs;             // float search radius h_margin * h_guess, sorted
+    sph::Buf leaf_of;        // int, sorted particle -> leaf
+    sph::Buf unassigned;     // int flags per particle during the level loop
+    sph::Buf head, scan1;    // uint32 per particle
+    sph::Buf nid;            // int per particle: node at the current level
+    // nodes (all levels, level-major)
+    sph::Buf nd_start, nd_count, nd_hmax, nd_child0, nd_child1, nd_leaf, nd_box, nd_level, nd_coord;
+    int64_t node_cap = 0;
+    sph::Buf nflag, nscan;   // per-node temporaries of one level
+    sph::Buf top;            // int: node of each (box, top cell), -1 if empty
+    // leaves (Morton order)
+    sph::Buf lf_start, lf_count, lf_node, lf_hmax;
+    sph::Buf lf_tmp;         // level-order leaf id per particle
+    // neighbour lists
+    sph::Buf p_start;        // uint32 n_leaves + 1
+    sph::Buf p_cnt;          // uint32 n_leaves
+    sph::Buf p_leaf;         // int
+    sph::Buf p_shift;        // float4 (dx, dy, dz, 0): leaf-centre frame offset
+    sph::Buf p_code;         // int: periodic image code (3 x 2 bits)
+    sph::Buf scan_tmp;       // scan workspace
+    sph::Buf sort_hist;      // radix-sort histograms
+
+    // ---- density / force state (sorted order) ---------------------------------
+    sph::Buf jd;             // float4 (x, y, z, m)
+    sph::Buf hs, rhos, fs;   // float, sorted
+    sph::Buf status;         // uint8, caller order
+    sph::Buf st_s;           // uint8, sorted copy of status
+    sph::Buf jf;             // 3 float4 per particle for the force loop
+    sph::Buf counters;       // int64[CT_COUNT]
+    sph::Buf cons_d;         // double, 4 per box
+    int64_t* h_counters = nullptr;  // pinned mirror
+    double* h_cons = nullptr;       // pinned mirror (4 per box)
+    size_t h_cons_cap = 0;
+
+    // ---- FP64 plain form --------------------------------------------------------
+    sph::Buf h64, rho64, f64, st64;     // sorted state of the FP64 solve
+    sph::Buf m64s;                      // sorted masses of the FP64 solve
+    sph::Buf jf64;                      // per particle: v, m, rho, Phi, c (8 doubles)
+    sph::Buf hf_tmp;                    // FP32 guesses for a rebuild from FP64 h
+
+    // ---- tuning and timing ------------------------------------------------------------
+    int n_cu = 256;
+    hipEvent_t ev[8] = {};
+    sph_timings tm{};
+};
+
+// Event pairs of the timing mode.
+enum { EV_DENS_K0 = 0, EV_DENS_K1 = 1, EV_DENS_C0 = 2, EV_DENS_C1 = 3,
+       EV_FORCE_K0 = 4, EV_FORCE_K1 = 5, EV_FORCE_C0 = 6, EV_FORCE_C1 = 7 };
+
+inline void ev_record(sph_ctx* c, int k, hipStream_t s)
+{
+    if (c->prm.timing) {
+        hipError_t e = hipEventRecord(c->ev[k], s);
+        if (e != hipSuccess) throw sph::Error(SPH_E_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    }
+}
+
+// Milliseconds between two recorded events (waits for the second).
+inline double ev_ms(sph_ctx* c, int k0, int k1)
+{
+    if (!c->prm.timing) return 0.0;
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(c->ev[k1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[k0], c->ev[k1]);
+    if (e != hipSuccess) throw sph::Error(SPH_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+    return (double)ms;
+}
+
+namespace sph {
+
+template <class T>
+T* ensure(sph_ctx* c, Buf& b, size_t count)
+{
+    size_t need = count * sizeof(T);
+    if (need == 0) need = sizeof(T);
+    if (b.bytes >= need) return static_cast<T*>(b.p);
+    if (b.p) {
+        // kernels already enqueued may still read the old buffer
+        SPH_HIP(hipDeviceSynchronize());
+        hipFree(b.p);
+        c->allocated -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = need + need / 8;  // slack for small regrowth
+    if (c->prm.workspace_limit > 0 && c->allocated + want > (size_t)c->prm.workspace_limit) {
+        want = need;
+        if (c->allocated + want > (size_t)c->prm.workspace_limit)
+            throw Error(SPH_E_NOMEM, "workspace_limit exceeded");
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(SPH_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    b.p = p;
+    b.bytes = want;
+    c->allocated += want;
+    return static_cast<T*>(p);
+}
+
+// Grow keeping the first `keep` elements.
+template <class T>
+T* grow_keep(sph_ctx* c, Buf& b, size_t count, size_t keep, hipStream_t s)
+{
+    size_t need = count * sizeof(T);
+    if (b.bytes >= need) return static_cast<T*>(b.p);
+    Buf nb;
+    T* np = ensure<T>(c, nb, count + count / 2);
+    if (b.p && keep) SPH_HIP(hipMemcpyAsync(np, b.p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    if (b.p) {
+        hipFree(b.p);
+        c->allocated -= b.bytes;
+    }
+    b = nb;
+    return np;
+}
+
+inline void free_buf(sph_ctx* c, Buf& b)
+{
+    if (b.p) {
+        hipFree(b.p);
+        c->allocated -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---- host entry points of the other translation units ---------------------------
+
+// Exclusive scan of n uint32 values (in may equal out). If total != nullptr the
+// sum of all inputs is written there (device pointer).
+void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                    hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
+// Results end in keys/vals (the alt buffers are scratch).
+void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                uint32_t* vals_alt, int64_t n, int bits, hipStream_t s);
+
+void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len,
+                 int64_t n, const double* pos, const float* h_guess, hipStream_t s);
+void rebuild_cells(sph_ctx* c, const float* h_guess_caller_order, hipStream_t s);
+
+void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw,
+                 sph_stats* st, hipStream_t s);
+void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt,
+               double* cons, sph_stats* st, hipStream_t s);
+void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double* f, double* nw,
+                 sph_stats* st, hipStream_t s);
+void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, double* dudt,
+               double* cons, sph_stats* st, hipStream_t s);
+
+}  // namespace sph
+
+// ---- device helpers ----------------------------------------------------------------
+
+// Cubic-spline shape w(q) and its derivative on 0 <= q < 1 (callers mask q >= 1).
+// Both branches are evaluated and selected so a wavefront never diverges here.
+__device__ __forceinline__ void spline_w_dw(float q, float& w, float& dw)
+{
+    const float t = 1.0f - q;
+    const float w_in = fmaf(q * q, fmaf(6.0f, q, -6.0f), 1.0f);  // 1 - 6q^2 + 6q^3
+    const float dw_in = q * fmaf(18.0f, q, -12.0f);              // -12q + 18q^2
+    const float w_out = 2.0f * t * t * t;
+    const float dw_out = -6.0f * t * t;
+    const bool inner = q < 0.5f;
+    w = inner ? w_in : w_out;
+    dw = inner ? dw_in : dw_out;
+}
+
+__device__ __forceinline__ float spline_dw(float q)
+{
+    const float t = 1.0f - q;
+    const float dw_in = q * fmaf(18.0f, q, -12.0f);
+    const float dw_out = -6.0f * t * t;
+    return q < 0.5f ? dw_in : dw_out;
+}
+
+__device__ __forceinline__ void spline_w_dw64(double q, double& w, double& dw)
+{
+    const double t = 1.0 - q;
+    if (q < 0.5) {
+        w = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+        dw = -12.0 * q + 18.0 * q * q;
+    } else {
+        w = 2.0 * t * t * t;
+        dw = -6.0 * t * t;
+    }
+}
+
+__device__ __forceinline__ double spline_dw64(double q)
+{
+    const double t = 1.0 - q;
+    return q < 0.5 ? (-12.0 * q + 18.0 * q * q) : (-6.0 * t * t);
+}
+
+__device__ __forceinline__ int box_of(const int64_t* box_first, int n_boxes, int64_t p)
+{
+    int lo = 0, hi = n_boxes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (box_first[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Image code: 2 bits per axis, value 0 -> no shift, 1 -> +L, 2 -> -L.
+__device__ __forceinline__ int image_code(int sx, int sy, int sz)
+{
+    auto e = [](int s) { return s == 0 ? 0 : (s > 0 ? 1 : 2); };
+    return e(sx) | (e(sy) << 2) | (e(sz) << 4);
+}
+__device__ __forceinline__ double image_shift(int code, int axis, double L)
+{
+    int v = (code >> (2 * axis)) & 3;
+    return v == 0 ? 0.0 : (v == 1 ? L : -L);
+}
+
+#define SPH_PI_F 3.14159265358979323846f
+#define SPH_PI_D 3.14159265358979323846

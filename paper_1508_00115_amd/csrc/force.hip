@@ -1,0 +1,255 @@
+// FP32 force loop: the pressure-gradient sum of the Swift paper (section 2,
+// Eq. 2) in the grad-h form of Gadget-2 that Swift implements, with a
+// signal-velocity artificial viscosity, in the internal-energy variable.
+//
+// The ghost step (after the density, section 3.1's dependency) turns rho, f
+// and u into the per-particle pressure term Phi = f P / rho^2 and sound speed,
+// packed with position, velocity, mass and 1/h into three float4 per particle.
+// The loop then runs one wavefront per leaf cell exactly like the density
+// loop: the cell's neighbour particles are staged into LDS in chunks and each
+// particle of the cell (several lanes per particle for small cells) gathers
+// the terms of every pair inside max(h_i, h_j). The gather form evaluates each
+// pair from both sides, so no two waves write the same particle and the result
+// does not depend on scheduling. Per-box momentum and energy rates are summed
+// in FP64 from each wave's particles.
+#include "common.h"
+#include "tiles.h"
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int WAVES = BS / 64;
+constexpr int FCAP = 256;  // candidates per LDS chunk (3 float4 each)
+
+__global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ jd,
+                                 const float* __restrict__ hs, const float* __restrict__ rhos,
+                                 const float* __restrict__ fs, const float* __restrict__ vel,
+                                 const float* __restrict__ u, float gamma, float4* __restrict__ jf,
+                                 int64_t* __restrict__ ctr)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = perm[p];
+    const float4 x = jd[p];
+    const float h = hs[p];
+    const float rho = rhos[p];
+    const float uu = u[o];
+    const float vx = vel[3 * (int64_t)o], vy = vel[3 * (int64_t)o + 1], vz = vel[3 * (int64_t)o + 2];
+    if (!(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz))
+        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+    const float P = (gamma - 1.0f) * rho * uu;
+    const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
+    const float phi = fs[p] * P / (rho * rho);
+    jf[3 * p + 0] = make_float4(x.x, x.y, x.z, 1.0f / h);
+    jf[3 * p + 1] = make_float4(vx, vy, vz, x.w);
+    jf[3 * p + 2] = make_float4(rho, phi, c, 0.0f);
+}
+
+struct ForceArgs {
+    const float4* jf;
+    const int* lf_start;
+    const int* lf_count;
+    const int* lf_node;
+    const int* nd_box;
+    const uint32_t* p_start;
+    const int* p_leaf;
+    const float4* p_shift;
+    const uint32_t* perm;
+    float* acc;
+    float* dudt;
+    double* cons;  // 4 per box, may be null
+    int64_t* ctr;
+    int q_begin[9];
+    float alpha;
+};
+
+__global__ void __launch_bounds__(BS) k_force(ForceArgs A)
+{
+    __shared__ float4 tile[WAVES][3 * FCAP];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    float4* sj = tile[wv];
+    const int xcd = blockIdx.x & 7;
+    int q_skip = 0;
+    int64_t cand_acc = 0, inter_acc = 0;
+    const float K8PI = 8.0f / SPH_PI_F;
+
+    for (;;) {
+        const int a = pop_item(A.ctr, A.q_begin, xcd, q_skip);
+        if (a < 0) break;
+        const int i0 = A.lf_start[a];
+        const int ni = A.lf_count[a];
+        const int pb0 = (int)A.p_start[a];
+        const int np_all = (int)A.p_start[a + 1] - pb0;
+        const int nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        const int lpi = ni <= 8 ? 8 : (ni <= 16 ? 4 : (ni <= 32 ? 2 : 1));
+        const int sub = lane & (lpi - 1);
+        const int per_pass = 64 / lpi;
+        const bool single_tile = nj <= FCAP;
+        bool loaded = false;
+        for (int ib = 0; ib < ni; ib += per_pass) {
+            const int gi = ib + lane / lpi;
+            const bool valid = gi < ni;
+            const int i = i0 + (valid ? gi : 0);
+            const float4 i0v = A.jf[3 * (int64_t)i + 0];
+            const float4 i1v = A.jf[3 * (int64_t)i + 1];
+            const float4 i2v = A.jf[3 * (int64_t)i + 2];
+            const float hinv_i = i0v.w;
+            const float hinv2_i = hinv_i * hinv_i;
+            const float Ki = K8PI * hinv2_i * hinv2_i;
+            const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
+            float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
+            int cnt = 0;
+            for (int c0 = 0; c0 < nj; c0 += FCAP) {
+                const int len = min(FCAP, nj - c0);
+                if (!(single_tile && loaded)) {
+                    stage_tile<3>(sj, A.jf, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len,
+                                  FCAP);
+                    loaded = true;
+                }
+#pragma unroll 2
+                for (int k = sub; k < len; k += lpi) {
+                    const float4 p0 = sj[k];
+                    const float4 p1 = sj[FCAP + k];
+                    const float4 p2 = sj[2 * FCAP + k];
+                    const float dx = i0v.x - p0.x, dy = i0v.y - p0.y, dz = i0v.z - p0.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float hinv_j = p0.w;
+                    const float hinv2_j = hinv_j * hinv_j;
+                    const bool in = (r2 * hinv2_i < 1.0f || r2 * hinv2_j < 1.0f) && r2 > 0.0f;
+                    const float r2s = in ? r2 : 1.0f;
+                    const float rinv = rsqrtf(r2s);
+                    const float r = r2s * rinv;
+                    const float qi = fminf(r * hinv_i, 1.0f);
+                    const float qj = fminf(r * hinv_j, 1.0f);
+                    const float Di = Ki * spline_dw(qi);
+                    const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw(qj);
+                    const float vr = ((i1v.x - p1.x) * dx + (i1v.y - p1.y) * dy + (i1v.z - p1.z) * dz) * rinv;
+                    const float wv_ = fminf(vr, 0.0f);
+                    const float visc = -A.alpha * (c_i + p2.z - 3.0f * wv_) * wv_ / (rho_i + p2.x);
+                    const float Dbar = 0.5f * (Di + Dj);
+                    const float G = fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
+                    const float mj = in ? p1.w : 0.0f;
+                    const float mGr = mj * G * rinv;
+                    ax = fmaf(-mGr, dx, ax);
+                    ay = fmaf(-mGr, dy, ay);
+                    az = fmaf(-mGr, dz, az);
+                    du = fmaf(mj * fmaf(phi_i, Di, 0.5f * visc * Dbar), vr, du);
+                    cnt += in ? 1 : 0;
+                }
+                if (!single_tile) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            ax = group_sum(ax, lpi);
+            ay = group_sum(ay, lpi);
+            az = group_sum(az, lpi);
+            du = group_sum(du, lpi);
+            cnt = group_sum_i(cnt, lpi);
+            const bool leader = valid && sub == 0;
+            int ng = leader ? 1 : 0;
+            for (int o = 32; o >= 1; o >>= 1) ng += __shfl_xor(ng, o, 64);
+            cand_acc += (int64_t)ng * nj;
+            double cm[4] = {0.0, 0.0, 0.0, 0.0};
+            if (leader) {
+                const uint32_t o = A.perm[i];
+                A.acc[3 * (int64_t)o + 0] = ax;
+                A.acc[3 * (int64_t)o + 1] = ay;
+                A.acc[3 * (int64_t)o + 2] = az;
+                A.dudt[o] = du;
+                inter_acc += cnt;
+                const double m = i1v.w;
+                cm[0] = m * ax;
+                cm[1] = m * ay;
+                cm[2] = m * az;
+                cm[3] = m * ((double)i1v.x * ax + (double)i1v.y * ay + (double)i1v.z * az + (double)du);
+            }
+            if (A.cons) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    for (int o = 32; o >= 1; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
+                if (lane == 0) {
+                    const int b = A.nd_box[A.lf_node[a]];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) atomicAdd(&A.cons[4 * b + k], cm[k]);
+                }
+            }
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) inter_acc += __shfl_xor(inter_acc, o, 64);
+    if (lane == 0) {
+        atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_INTER], (unsigned long long)inter_acc);
+        atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_CAND], (unsigned long long)cand_acc);
+    }
+}
+
+}  // namespace
+
+namespace sph {
+
+void queue_bounds(int64_t n_items, int* q_begin);
+int persistent_blocks(sph_ctx* c, int blocks_per_cu, int64_t n_items, int waves_per_block);
+
+void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons,
+               sph_stats* st, hipStream_t s)
+{
+    SPH_REQUIRE(c->built && c->density_done, SPH_E_STATE, "sph_force needs a successful sph_density first");
+    SPH_REQUIRE(vel && u && acc && dudt, SPH_E_ARG, "null vel/u/acc/dudt");
+    const int64_t n = c->n;
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    float4* jf = ensure<float4>(c, c->jf, 3 * n);
+    double* cons_d = nullptr;
+    if (cons) {
+        cons_d = ensure<double>(c, c->cons_d, 4 * (size_t)c->n_boxes);
+        SPH_HIP(hipMemsetAsync(cons_d, 0, 32 * (size_t)c->n_boxes, s));
+    }
+    ev_record(c, EV_FORCE_C0, s);
+    SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
+    k_force_prologue<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                       static_cast<float4*>(c->jd.p), static_cast<float*>(c->hs.p),
+                                                       static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p),
+                                                       vel, u, (float)c->prm.gamma, jf, ctr);
+    SPH_HIP(hipGetLastError());
+    ForceArgs A;
+    A.jf = jf;
+    A.lf_start = static_cast<int*>(c->lf_start.p);
+    A.lf_count = static_cast<int*>(c->lf_count.p);
+    A.lf_node = static_cast<int*>(c->lf_node.p);
+    A.nd_box = static_cast<int*>(c->nd_box.p);
+    A.p_start = static_cast<uint32_t*>(c->p_start.p);
+    A.p_leaf = static_cast<int*>(c->p_leaf.p);
+    A.p_shift = static_cast<float4*>(c->p_shift.p);
+    A.perm = static_cast<uint32_t*>(c->perm.p);
+    A.acc = acc;
+    A.dudt = dudt;
+    A.cons = cons_d;
+    A.ctr = ctr;
+    queue_bounds(c->n_leaves, A.q_begin);
+    A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
+    const int grid = persistent_blocks(c, 3, c->n_leaves, WAVES);
+    ev_record(c, EV_FORCE_K0, s);
+    k_force<<<grid, BS, 0, s>>>(A);
+    SPH_HIP(hipGetLastError());
+    ev_record(c, EV_FORCE_K1, s);
+    if (cons || st) {
+        int64_t hc[CT_COUNT];
+        SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        if (cons) SPH_HIP(hipMemcpyAsync(cons, cons_d, 32 * (size_t)c->n_boxes, hipMemcpyDeviceToHost, s));
+        SPH_HIP(hipStreamSynchronize(s));
+        SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
+        if (st) {
+            st->interactions_force = hc[CT_FORCE_INTER];
+            st->candidates_force = hc[CT_FORCE_CAND];
+            st->n_cells = c->n_leaves;
+            st->n_pairs = c->n_pairs;
+        }
+    }
+    ev_record(c, EV_FORCE_C1, s);
+    if (c->prm.timing) {
+        c->tm.force_kernel_ms = ev_ms(c, EV_FORCE_K0, EV_FORCE_K1);
+        c->tm.force_call_ms = ev_ms(c, EV_FORCE_C0, EV_FORCE_C1);
+    }
+}
+
+}  // namespace sph

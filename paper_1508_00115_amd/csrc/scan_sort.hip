@@ -1,0 +1,255 @@
+// Device-wide exclusive scan and stable LSD radix sort used by the cell build.
+//
+// Both work on wave64 primitives: lane-shuffle scans inside a wavefront and
+// ballot-based digit matching for the sort's stable local ranking.
+#include "common.h"
+
+namespace {
+
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_ITEMS;
+
+// Inclusive scan inside one wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over a 256-thread block; returns the block total in *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, uint32_t& total)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) lds4[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BS / 64; ++k) {
+        uint32_t t = lds4[k];
+        if (k < w) base += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+__global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint32_t* __restrict__ sums)
+{
+    __shared__ uint32_t lds4[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, lds4, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Scans each tile and adds the scanned tile offset. sums may be null when there
+// is a single tile. Writes the grand total from the last tile.
+__global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
+                                                        const uint32_t* __restrict__ sums,
+                                                        uint32_t* __restrict__ total)
+{
+    __shared__ uint32_t lds4[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n) ? in[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, lds4, tot) + (sums ? sums[blockIdx.x] : 0u);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) *total = run;
+}
+
+// ---- radix sort ------------------------------------------------------------------
+
+constexpr int RS_BS = 256;
+constexpr int RS_ROWS = 8;
+constexpr int RS_TILE = RS_BS * RS_ROWS;
+
+__global__ void __launch_bounds__(RS_BS) k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                   uint32_t* __restrict__ hist, int n_tiles)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int r = 0; r < RS_ROWS; ++r) {
+        int64_t i = base + r * RS_BS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];  // digit-major
+}
+
+// Stable scatter: keys of a tile are ranked in position order. Within each row
+// of 256 keys a wavefront finds the lanes holding the same digit with eight
+// ballots; per-wave digit counts in LDS order the four waves; a running
+// per-digit count orders the rows.
+__global__ void __launch_bounds__(RS_BS) k_rs_scatter(const uint64_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals, int64_t n,
+                                                      int shift, const uint32_t* __restrict__ offs,
+                                                      int n_tiles, uint64_t* __restrict__ keys_out,
+                                                      uint32_t* __restrict__ vals_out)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[RS_BS / 64][256];
+    __shared__ uint32_t goff[256];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = t >> 6;
+    run[t] = 0;
+    goff[t] = offs[(int64_t)t * n_tiles + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ROWS; ++r) {
+        const int64_t i = base + r * RS_BS + t;
+        const bool valid = i < n;
+        uint64_t k = valid ? keys[i] : ~0ull;
+        uint32_t v = valid ? vals[i] : 0u;
+        const uint32_t d = valid ? (uint32_t)((k >> shift) & 255u) : 255u;
+#pragma unroll
+        for (int q = 0; q < RS_BS / 64; ++q) wcnt[q][t] = 0;
+        __syncthreads();
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        uint32_t pos = run[d] + rank;
+        for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+        __syncthreads();
+        {
+            uint32_t add = 0;
+#pragma unroll
+            for (int q = 0; q < RS_BS / 64; ++q) add += wcnt[q][t];
+            run[t] += add;
+        }
+        if (valid) {
+            const uint32_t dst = goff[d] + pos;
+            keys_out[dst] = k;
+            vals_out[dst] = v;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+namespace sph {
+
+void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                    hipStream_t s)
+{
+    if (n <= 0) {
+        if (total) SPH_HIP(hipMemsetAsync(total, 0, sizeof(uint32_t), s));
+        return;
+    }
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles == 1) {
+        k_scan_apply<<<1, SCAN_BS, 0, s>>>(in, out, n, nullptr, total);
+        SPH_HIP(hipGetLastError());
+        return;
+    }
+    // one scratch region holds the tile sums of every level, laid out consecutively
+    int64_t need = 0;
+    for (int64_t m = tiles; m > 1; m = (m + SCAN_TILE - 1) / SCAN_TILE) need += m + 64;
+    uint32_t* sums = ensure<uint32_t>(c, c->scan_tmp, (size_t)need + 64);
+    // levels laid out consecutively
+    std::vector<std::pair<uint32_t*, int64_t>> lv;
+    {
+        uint32_t* p = sums;
+        int64_t m = tiles;
+        lv.push_back({p, m});
+        p += m + 64;
+        while (m > 1) {
+            int64_t mm = (m + SCAN_TILE - 1) / SCAN_TILE;
+            if (mm <= 1) break;
+            lv.push_back({p, mm});
+            p += mm + 64;
+            m = mm;
+        }
+    }
+    // reduce down: level 0 sums of `in`, level k sums of level k-1
+    k_scan_reduce<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, lv[0].first);
+    SPH_HIP(hipGetLastError());
+    for (size_t k = 1; k < lv.size(); ++k) {
+        k_scan_reduce<<<(unsigned)lv[k].second, SCAN_BS, 0, s>>>(lv[k - 1].first, lv[k - 1].second,
+                                                                  lv[k].first);
+        SPH_HIP(hipGetLastError());
+    }
+    // scan up: the last level fits one tile
+    {
+        auto& top = lv.back();
+        k_scan_apply<<<1, SCAN_BS, 0, s>>>(top.first, top.first, top.second, nullptr, nullptr);
+        SPH_HIP(hipGetLastError());
+    }
+    for (int k = (int)lv.size() - 2; k >= 0; --k) {
+        k_scan_apply<<<(unsigned)lv[k].second, SCAN_BS, 0, s>>>(lv[k].first, lv[k].first,
+                                                                 lv[k].second, lv[k + 1].first,
+                                                                 nullptr);
+        SPH_HIP(hipGetLastError());
+    }
+    k_scan_apply<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, out, n, lv[0].first, total);
+    SPH_HIP(hipGetLastError());
+}
+
+void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                int64_t n, int bits, hipStream_t s)
+{
+    if (n <= 1 || bits <= 0) return;
+    const int n_tiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int64_t hn = (int64_t)n_tiles * 256;
+    uint32_t* hist = ensure<uint32_t>(c, c->sort_hist, (size_t)hn);
+    uint64_t* ka = keys;
+    uint32_t* va = vals;
+    uint64_t* kb = keys_alt;
+    uint32_t* vb = vals_alt;
+    const int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        k_rs_hist<<<n_tiles, RS_BS, 0, s>>>(ka, n, shift, hist, n_tiles);
+        SPH_HIP(hipGetLastError());
+        scan_exclusive(c, hist, hist, hn, nullptr, s);
+        k_rs_scatter<<<n_tiles, RS_BS, 0, s>>>(ka, va, n, shift, hist, n_tiles, kb, vb);
+        SPH_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        SPH_HIP(hipMemcpyAsync(keys, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        SPH_HIP(hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+}  // namespace sph

@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU path still
+spans many cells, several tiles per cell list and ragged cell sizes. The
+full-size Sedov set is checked on a seeded sample the oracle computes one
+particle at a time.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from parity import TOL32, TOL64, assert_within, errors, oracle_sample
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(sph, d, fp64=False, **params):
+    ctx = sph.Context(0, **params)
+    try:
+        return sph.run_workload(ctx, d, fp64=fp64)
+    finally:
+        ctx.close()
+
+
+def _case(name):
+    if name == "small":
+        return workloads.small()
+    if name == "sedov32":
+        return workloads.sedov(n_side=32, n_hot=32)
+    if name == "lattice_vel":
+        return workloads.lattice_box(20, [1508, 901], jitter=0.3, u=1.0, vel_sigma=0.3)
+    if name == "batched8":
+        return workloads.batched(n_boxes=8, n_min=1000, n_max=8000, side_min=10, side_max=20)
+    if name == "clustered_small":
+        return workloads.clustered(n_uniform=1 << 14, n_spheres=4, per_sphere=4096)
+    if name == "lognormal40":
+        return workloads.lognormal(n_mesh=40, sigma_ln=1.2)
+    raise KeyError(name)
+
+
+CASES = ["small", "sedov32", "lattice_vel", "batched8", "clustered_small", "lognormal40"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp32_matches_oracle(gpu_lib, name):
+    d = _case(name)
+    print("case", name, "N", d["pos"].shape[0], flush=True)
+    g = _gpu(gpu_lib, d)
+    r = oracle.run(d)
+    e = errors(g, r)
+    print(name, e, g["stats_density"], flush=True)
+    assert_within(e, TOL32, name)
+    # interaction counts: equal up to pairs sitting within FP32 rounding of r = h
+    n_d = int(r["nngb"].sum())
+    n_f = int(r["npair"].sum())
+    assert abs(g["stats_density"]["interactions_density"] - n_d) <= 1e-5 * n_d + 2
+    assert abs(g["stats_force"]["interactions_force"] - n_f) <= 1e-5 * n_f + 2
+    # conservation sums, accumulated in FP64 per box
+    for b, (mom, en, mscale, escale) in enumerate(r["cons"]):
+        cg = g["cons"][b]
+        assert np.all(np.abs(cg[:3]) <= 1e-5 * mscale + 1e-300)
+        assert abs(cg[3]) <= 1e-5 * escale + 1e-300
+
+
+@pytest.mark.parametrize("name", ["small", "sedov32", "lattice_vel", "batched8"])
+def test_fp64_plain_matches_oracle(gpu_lib, name):
+    d = _case(name)
+    g = _gpu(gpu_lib, d, fp64=True)
+    r = oracle.run(d)
+    e = errors(g, r)
+    print(name, "fp64", e, flush=True)
+    assert_within(e, TOL64, name + " fp64")
+
+
+def test_perfect_lattice_closed_form(gpu_lib):
+    d = workloads.lattice_box(16, None, jitter=0.0)
+    g = _gpu(gpu_lib, d)
+    a = 1.0 / 16
+    m = float(d["mass"][0])
+    assert np.max(np.abs(g["h"] / a / 2.251489742231818 - 1)) < 1e-5
+    assert np.max(np.abs(g["rho"] * a ** 3 / m / 1.004020800085607 - 1)) < 1e-5
+    assert np.max(np.abs(g["f"] / 1.010015781338927 - 1)) < 1e-5
+    assert g["stats_density"]["interactions_density"] == 56 * 16 ** 3
+    assert np.all(g["dudt"] == 0.0)
+
+
+def test_sedov_full_size(gpu_lib):
+    """The Sedov blast at its full 64^3 size: every particle against the oracle."""
+    d = workloads.sedov()
+    g = _gpu(gpu_lib, d)
+    r = oracle.run(d)
+    e = errors(g, r)
+    print("sedov64", e, g["stats_density"], g["stats_force"], flush=True)
+    assert_within(e, TOL32, "sedov64")
+    assert abs(g["stats_density"]["interactions_density"] - int(r["nngb"].sum())) <= 1e-5 * r["nngb"].sum()
+
+
+def test_clustered_full_size_sampled(gpu_lib):
+    """The clustered set at full size (2^20 particles), checked on a seeded
+    sample of particles the oracle solves one by one."""
+    d = workloads.clustered()
+    n = d["pos"].shape[0]
+    g = _gpu(gpu_lib, d)
+    rng = np.random.default_rng([1508, 2, 7])
+    targets = np.sort(rng.choice(n, 400, replace=False))
+    r = oracle_sample(d, targets, radius=2.0 * 0.03)
+    e = errors(g, r, targets)
+    print("clustered sample", e, g["stats_density"], flush=True)
+    assert_within(e, TOL32, "clustered")
+
+
+@pytest.mark.parametrize("params", [dict(leaf_target=8), dict(leaf_target=256), dict(cell_ratio=0.5),
+                                    dict(h_margin=1.6)])
+def test_results_do_not_depend_on_cells(gpu_lib, params):
+    d = workloads.lattice_box(18, [1508, 902], jitter=0.3, u=1.0, vel_sigma=0.2)
+    g0 = _gpu(gpu_lib, d)
+    g1 = _gpu(gpu_lib, d, **params)
+    for k in ("h", "rho", "f"):
+        assert np.max(np.abs(g1[k] - g0[k]) / g0[k]) < 2e-6, k
+    r = oracle.run(d)
+    assert_within(errors(g1, r), TOL32, str(params))
+
+
+def test_bad_guess_forces_rebuild(gpu_lib):
+    d = workloads.lattice_box(18, [1508, 903], jitter=0.2, u=1.0)
+    d["h0"] = (d["h0"] * 0.3).astype(np.float32)
+    g = _gpu(gpu_lib, d)
+    assert g["stats_density"]["rebuilds"] >= 1
+    r = oracle.run(d)
+    assert_within(errors(g, r), TOL32, "rebuild")
+
+
+def test_large_guess(gpu_lib):
+    d = workloads.lattice_box(18, [1508, 904], jitter=0.2, u=1.0)
+    d["h0"] = (d["h0"] * 1.8).astype(np.float32)
+    g = _gpu(gpu_lib, d)
+    r = oracle.run(d)
+    assert_within(errors(g, r), TOL32, "large guess")
+
+
+def test_permutation_and_translation(gpu_lib):
+    d = workloads.lattice_box(16, [1508, 905], jitter=0.3, u=1.0, vel_sigma=0.2)
+    g0 = _gpu(gpu_lib, d)
+    perm = np.random.default_rng(4).permutation(d["pos"].shape[0])
+    dp = dict(d)
+    for k in ("pos", "vel", "mass", "u", "h0"):
+        dp[k] = np.ascontiguousarray(d[k][perm])
+    gp = _gpu(gpu_lib, dp)
+    for k in ("h", "rho", "f"):
+        assert np.max(np.abs(gp[k] - g0[k][perm]) / g0[k][perm]) < 2e-6
+    dt = dict(d)
+    dt["pos"] = np.mod(d["pos"] + np.array([0.37, -0.21, 0.9]), 1.0)
+    gt = _gpu(gpu_lib, dt)
+    for k in ("h", "rho", "f"):
+        assert np.max(np.abs(gt[k] - g0[k]) / g0[k]) < 1e-5
+
+
+def test_error_paths(gpu_lib):
+    import torch
+    sph = gpu_lib
+    ctx = sph.Context(0)
+    n = 4096
+    d = workloads.small()
+    pos = torch.from_numpy(d["pos"]).cuda()
+    h0 = torch.from_numpy(d["h0"]).cuda()
+    mass = torch.from_numpy(d["mass"]).cuda()
+    vel = torch.zeros((n, 3), device="cuda")
+    u = torch.ones(n, device="cuda")
+    with pytest.raises(sph.SphError) as ei:
+        ctx.density(mass, h0.clone())
+    assert ei.value.code == sph.SPH_E_STATE
+    ctx.build_cells(pos, h0)
+    with pytest.raises(sph.SphError) as ei:
+        ctx.force(vel, u)
+    assert ei.value.code == sph.SPH_E_STATE
+    # h so large a third of the box is exceeded
+    with pytest.raises(sph.SphError) as ei:
+        ctx.build_cells(pos, torch.full((n,), 0.3, device="cuda"))
+    assert ei.value.code == sph.SPH_E_H_TOO_LARGE
+    bad = pos.clone()
+    bad[5, 1] = float("nan")
+    with pytest.raises(sph.SphError) as ei:
+        ctx.build_cells(bad, h0)
+    assert ei.value.code == sph.SPH_E_ARG
+    ctx.close()
+    one = sph.Context(0, max_iter=1)
+    one.build_cells(pos, h0)
+    with pytest.raises(sph.SphError) as ei:
+        one.density(mass, h0.clone())
+    assert ei.value.code == sph.SPH_E_NOT_CONVERGED
+    one.close()
+
+
+def test_empty_box_in_batch(gpu_lib):
+    a = workloads.lattice_box(12, [1508, 906], jitter=0.2, u=1.0, vel_sigma=0.1)
+    b = workloads.lattice_box(10, [1508, 907], jitter=0.2, u=1.0, vel_sigma=0.1)
+    n1, n2 = a["pos"].shape[0], b["pos"].shape[0]
+    d = {k: np.concatenate([a[k], b[k]]) for k in ("pos", "vel", "mass", "u", "h0")}
+    d["box_first"] = np.array([0, n1, n1, n1 + n2], dtype=np.int64)
+    d["box_len"] = np.array([1.0, 1.0, 1.0])
+    g = _gpu(gpu_lib, d)
+    r = oracle.run(d)
+    assert_within(errors(g, r), TOL32, "empty box")
+    assert np.all(g["cons"][1] == 0.0)
