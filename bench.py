@@ -44,10 +44,6 @@ PEAK_HBM_GBS = 8000.0
 FLOP_REJECT = 8
 FLOP_DENSITY = 26
 FLOP_FORCE = 61
-# FLOPs the kernels as written execute per candidate pair (every candidate goes
-# through the full branch-free body), counted from their source.
-HW_FLOP_DENSITY_CAND = 31
-HW_FLOP_FORCE_CAND = 72
 
 
 def _workload(name: str):
@@ -90,6 +86,7 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -114,7 +111,13 @@ def main() -> int:
     acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
     dudt = torch.empty_like(h)
 
-    ctx = sph.Context(0, timing=1)
+    tuned = None
+    params = {}
+    if not args.no_tune:
+        from paper_1508_00115_amd import tune
+        tuned = tune.autotune(d, 0)
+        params = tuned["best"]
+    ctx = sph.Context(0, timing=1, **params)
     ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
     build_ms = ctx.timings()["build_ms"]
 
@@ -175,9 +178,9 @@ def main() -> int:
     force_alg = FLOP_FORCE * sf["interactions_force"] + \
         FLOP_REJECT * (sf["candidates_force"] - sf["interactions_force"])
     if dens_ms >= force_ms:
-        kname, kms, alg, hw = "k_density", dens_ms, dens_alg, HW_FLOP_DENSITY_CAND * sd["candidates_density"]
+        kname, kms, alg = "k_density", dens_ms, dens_alg
     else:
-        kname, kms, alg, hw = "k_force", force_ms, force_alg, HW_FLOP_FORCE_CAND * sf["candidates_force"]
+        kname, kms, alg = "k_force", force_ms, force_alg
     achieved = alg / (kms * 1e-3) / 1e12
     useful = (FLOP_DENSITY * sd["sweep_interactions_density"] + FLOP_FORCE * sf["interactions_force"]) / \
         ((dens_ms + force_ms) * 1e-3) / 1e12
@@ -200,8 +203,7 @@ def main() -> int:
                    "force_interactions": sf["interactions_force"], "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg,
-                     "executed_flop_per_launch": hw},
+                     "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg},
         "kernels_ms": {"density_kernel": dens_ms, "density_call": float(np.mean(dc)),
                        "force_kernel": force_ms, "force_call": float(np.mean(fc)), "build": build_ms},
         "useful_tflops": useful,
@@ -212,6 +214,9 @@ def main() -> int:
         "force": {"candidates": sf["candidates_force"]},
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
         "speedup_vs_fp64_plain": value / value64,
+        "cell_params": params or "library defaults",
+        "autotune": None if tuned is None else [
+            {**t["params"], "ms": t["ms"], "rebuilds": t.get("rebuilds")} for t in tuned["table"]],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)

@@ -89,6 +89,10 @@ typedef struct {
     int32_t timing;       /* nonzero: record HIP events around the hot kernels
                              (read with sph_get_timings; adds one stream
                              synchronisation to sph_force) */
+    int32_t schedule;     /* how cells reach wavefronts: 0 = hardware dispatch,
+                             one cell per wavefront, XCD-contiguous blocks;
+                             1 = persistent wavefronts popping per-XCD queues */
+    int32_t queue_batch;  /* cells per queue pop when schedule = 1 (4) */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP

@@ -35,7 +35,8 @@ class sph_params(ctypes.Structure):
                 ("alpha_visc", ctypes.c_double), ("n_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("h_margin", ctypes.c_double),
                 ("cell_ratio", ctypes.c_double), ("leaf_target", ctypes.c_int32),
-                ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32)]
+                ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("queue_batch", ctypes.c_int32)]
 
 
 class sph_stats(ctypes.Structure):

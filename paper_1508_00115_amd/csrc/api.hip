@@ -25,6 +25,8 @@ sph_params with_defaults(const sph_params* in)
     if (!(p.cell_ratio > 0)) p.cell_ratio = 1.0;
     if (p.leaf_target <= 0) p.leaf_target = 64;
     if (p.workspace_limit < 0) p.workspace_limit = 0;
+    if (p.schedule != 1) p.schedule = 0;
+    if (p.queue_batch <= 0) p.queue_batch = 4;
     return p;
 }
 

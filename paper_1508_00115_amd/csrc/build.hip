@@ -56,27 +56,28 @@ __global__ void k_wrap(int64_t n, const double* __restrict__ pos, const int64_t*
                        double* __restrict__ pos_w, float* __restrict__ hg_copy,
                        unsigned* __restrict__ box_hmax, float margin, int64_t* __restrict__ ctr)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int b = box_of(box_first, n_boxes, p);
-    const double L = box_len[b];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in_range = p < n;
+    int b = 0;
     bool bad = false;
+    float h = 0.0f;
+    if (in_range) {
+        b = box_of(box_first, n_boxes, p);
+        const double L = box_len[b];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double x = pos[3 * p + a];
-        bad |= !isfinite(x);
-        double y = x - L * floor(x / L);
-        if (!(y < L) || !(y >= 0.0)) y = 0.0;
-        pos_w[3 * p + a] = y;
+        for (int a = 0; a < 3; ++a) {
+            double x = pos[3 * p + a];
+            bad |= !isfinite(x);
+            double y = x - L * floor(x / L);
+            if (!(y < L) || !(y >= 0.0)) y = 0.0;
+            pos_w[3 * p + a] = y;
+        }
+        h = hg[p];
+        bad |= !(h > 0.0f) || !isfinite(h);
+        hg_copy[p] = h;
+        if (bad) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
     }
-    float h = hg[p];
-    bad |= !(h > 0.0f) || !isfinite(h);
-    hg_copy[p] = h;
-    if (bad) {
-        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
-        return;
-    }
-    atomicMax(&box_hmax[b], __float_as_uint(margin * h));
+    wave_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), in_range && !bad);
 }
 
 // Largest search radius per box from the stored (caller-order) h guesses.
@@ -84,14 +85,18 @@ __global__ void k_box_hmax(int64_t n, const int64_t* __restrict__ box_first, int
                            const float* __restrict__ hg, unsigned* __restrict__ box_hmax, float margin,
                            int64_t* __restrict__ ctr)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const float h = hg[p];
-    if (!(h > 0.0f) || !isfinite(h)) {
-        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
-        return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in_range = p < n;
+    float h = 0.0f;
+    int b = 0;
+    bool ok = false;
+    if (in_range) {
+        h = hg[p];
+        b = box_of(box_first, n_boxes, p);
+        ok = (h > 0.0f) && isfinite(h);
+        if (!ok) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
     }
-    atomicMax(&box_hmax[box_of(box_first, n_boxes, p)], __float_as_uint(margin * h));
+    wave_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), ok);
 }
 
 __global__ void k_keys(int64_t n, const double* __restrict__ pos_w, const int64_t* __restrict__ box_first,

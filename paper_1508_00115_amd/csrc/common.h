@@ -44,7 +44,9 @@ struct Buf {
 }  // namespace sph
 
 // Per-particle state of one FP32 density solve: flags in the caller's order.
-enum : uint8_t { ST_ACTIVE = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_UNCONVERGED = 3 };
+// ST_SCAN: the particle's neighbour list did not fit its LDS slots (or masses
+// differ); it is solved by the re-scanning kernel instead.
+enum : uint8_t { ST_ACTIVE = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_UNCONVERGED = 3, ST_SCAN = 4 };
 
 // Device counters (int64 slots) written by the hot kernels.
 enum {
@@ -59,6 +61,9 @@ enum {
     CT_QUEUE = 8,        // 8 work-queue heads (one per XCD) start here
     CT_TOTAL = 16,       // scratch for device-computed totals read by the host
     CT_DENS_SWEEP_INTER = 17,  // pairs inside the trial h, summed over every evaluation
+    CT_MASS_MIN = 18,    // smallest / largest mass bit pattern of the density call
+    CT_MASS_MAX = 19,
+    CT_NEED_SCAN = 20,   // particles left to the re-scanning density kernel
     CT_COUNT = 24
 };
 
@@ -310,6 +315,36 @@ __device__ __forceinline__ double image_shift(int code, int axis, double L)
 {
     int v = (code >> (2 * axis)) & 3;
     return v == 0 ? 0.0 : (v == 1 ? L : -L);
+}
+
+// atomicMax of v into base[key] with one atomic per wavefront when every valid
+// lane has the same key (consecutive particles mostly share a box), one per
+// lane otherwise. All 64 lanes must call it; invalid lanes pass valid = false.
+__device__ __forceinline__ void wave_atomic_max_u32(unsigned* base, int key, unsigned v, bool valid)
+{
+    const int k0 = __shfl(key, 0, 64);
+    if (__all(!valid || key == k0)) {
+        unsigned m = valid ? v : 0u;
+        for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+        if ((threadIdx.x & 63) == 0 && __any(valid)) atomicMax(&base[k0], m);
+    } else if (valid) {
+        atomicMax(&base[key], v);
+    }
+}
+
+// Wavefront-reduced atomicMin / atomicMax of 64-bit values.
+__device__ __forceinline__ void wave_atomic_minmax_u64(unsigned long long* lo, unsigned long long* hi,
+                                                       unsigned long long v, bool valid)
+{
+    unsigned long long mn = valid ? v : ~0ull, mx = valid ? v : 0ull;
+    for (int o = 32; o >= 1; o >>= 1) {
+        mn = min(mn, (unsigned long long)__shfl_xor((long long)mn, o, 64));
+        mx = max(mx, (unsigned long long)__shfl_xor((long long)mx, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && __any(valid)) {
+        atomicMin(lo, mn);
+        atomicMax(hi, mx);
+    }
 }
 
 #define SPH_PI_F 3.14159265358979323846f

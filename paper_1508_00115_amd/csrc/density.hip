@@ -1,32 +1,44 @@
 // FP32 density loop with the smoothing-length solve (section 2, Eq. 1 of the
 // Swift paper, and the choice of h for a fixed weighted neighbour number).
 //
-// Work unit: one leaf cell, handled by one wavefront. The particles of every
-// cell within reach (the cell's self task and its pair tasks, section 3.1) are
-// copied into the wavefront's LDS tile once, shifted into the cell's
-// FP32 frame. Each particle of the cell then iterates Newton's method on h
-// entirely against that tile: the density sums of a particle depend only on
-// its own h and the fixed positions, so no global sweep or ghost pass is
-// needed between iterations. A particle whose root lies beyond its search
-// radius is flagged; the host rebuilds the cells around a larger guess and
-// solves it again.
+// Work unit: one leaf cell, handled by one wavefront. The cell's candidates
+// are the particles of every cell within reach (its self task and its pair
+// tasks, section 3.1); they are staged through the wavefront's LDS tile in
+// chunks of 128, shifted into the cell's FP32 frame, and the next chunk is in
+// flight while the current one is used.
 //
-// Cells with few particles give several lanes to each particle (lanes of a
-// group stride over the tile; their partial sums meet through lane shuffles),
-// so a 64-lane wavefront stays busy on cells of 8 to 64 particles.
+// Two phases per particle of the cell (k_density):
+//   A. every candidate is tested once against the particle's search radius H
+//      (the radius the cells were built for) and the squared distances of the
+//      hits are appended, branch-free, to a per-lane list in LDS;
+//   B. Newton's method on h runs against that list only: each evaluation
+//      reads one float per entry instead of re-testing every candidate. The
+//      density sums of a particle depend only on its own h and the fixed
+//      positions, so the whole iteration stays inside the wavefront: no
+//      global sweep and no ghost pass between iterations.
+// Lists are sized for the common case so many wavefronts fit on a CU. A
+// particle whose list does not fit, or any particle when the masses differ,
+// is left to k_density_scan, which re-tests the candidates at every
+// evaluation. A particle whose root lies beyond its search radius is flagged;
+// the host rebuilds the cells around a larger guess and solves it again.
 //
-// Cells are popped from eight work queues, one per XCD, each holding a
-// contiguous Morton range so an XCD's L2 sees neighbouring cells; a wave whose
-// queue is empty takes work from the next queue.
+// Lanes: a cell's particles are spread over the 64 lanes, 2 to 16 lanes per
+// particle; the lanes of a particle split the candidates and meet through lane
+// shuffles.
 #include "common.h"
 #include "tiles.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
 
-constexpr int BS = 256;
+constexpr int BS = 64;         // one wavefront per block (finest LDS allocation)
 constexpr int WAVES = BS / 64;
+constexpr int DCAP = 128;      // candidates per LDS chunk (list kernel)
+constexpr int DSLOTS = 48;     // list entries per lane, plus one spare slot that
+                               // takes the stores of misses once a list is full
+constexpr int SCAP = 256;      // candidates per LDS chunk (re-scanning kernel)
 
 struct DensArgs {
     const float4* jd;        // sorted (x, y, z) in the leaf frame, m
@@ -47,7 +59,7 @@ struct DensArgs {
     float* nw_out;
     uint8_t* status;
     int64_t* ctr;
-    int q_begin[9];          // queue q covers leaves [q_begin[q], q_begin[q+1])
+    WorkSched W;             // which wavefront takes which cell
     float target;            // S0 = sum w(q) at the root: 3 n_ngb / 32
     float tol;               // on |S0 / target - 1|
     int max_iter;
@@ -58,18 +70,24 @@ __global__ void k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm, co
                                 const uint8_t* __restrict__ status, float4* __restrict__ jd,
                                 float* __restrict__ hs, uint8_t* __restrict__ st_s, int64_t* __restrict__ ctr)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t o = perm[p];
-    const float m = mass[o];
-    const float h = h_in[o];
-    const float4 x = xrel[p];
-    jd[p] = make_float4(x.x, x.y, x.z, m);
-    hs[p] = h;
-    uint8_t st = status[o];
-    st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
-    if (!(m > 0.0f) || !isfinite(m) || !(h > 0.0f) || !isfinite(h))
-        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = false;
+    float m = 0.0f;
+    if (p < n) {
+        const uint32_t o = perm[p];
+        m = mass[o];
+        const float h = h_in[o];
+        const float4 x = xrel[p];
+        jd[p] = make_float4(x.x, x.y, x.z, m);
+        hs[p] = h;
+        const uint8_t st = status[o];
+        st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
+        ok = (m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h);
+        if (!ok) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+    }
+    // range of the mass bit patterns (positive floats order like their bits)
+    wave_atomic_minmax_u64((unsigned long long*)&ctr[CT_MASS_MIN], (unsigned long long*)&ctr[CT_MASS_MAX],
+                           (unsigned long long)__float_as_uint(m), ok);
 }
 
 // Sorted copies of the final h, rho and f after the cells were rebuilt (the
@@ -86,69 +104,311 @@ __global__ void k_dens_regather(int64_t n, const uint32_t* __restrict__ perm, co
     fs[p] = f[o];
 }
 
-template <int CAP>
+// Newton state of one particle's h.
+struct HSolve {
+    float h, lo, hi, Hi;
+    bool hi_known, done;
+    uint8_t state;
+    int nev;
+};
+
+__device__ __forceinline__ HSolve hsolve_init(float h, float Hi, bool done, uint8_t st0)
+{
+    HSolve s;
+    s.Hi = Hi;
+    s.h = (!(h > 0.0f) || h > Hi) ? Hi : h;
+    s.lo = 0.0f;
+    s.hi = Hi;
+    s.hi_known = false;
+    s.done = done;
+    s.state = st0;
+    s.nev = 0;
+    return s;
+}
+
+// One Newton update from the sums at the current h: bracketed step on ln S0
+// against ln h (exact where S0 ~ h^slope), bisection when the step leaves the
+// bracket. Stops on |S0/target - 1| <= tol, on a step below FP32 resolution of
+// h, on a root beyond the search radius (overflow) or after max_iter.
+__device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float target, float tol, int max_iter)
+{
+    ++s.nev;
+    const float ratio = S0 / target;
+    if (fabsf(ratio - 1.0f) <= tol) {
+        s.done = true;
+        s.state = ST_DONE;
+        return;
+    }
+    if (ratio < 1.0f) {
+        s.lo = s.h;
+    } else {
+        s.hi = s.h;
+        s.hi_known = true;
+    }
+    if (ratio < 1.0f && s.h >= s.Hi) {
+        s.done = true;
+        s.state = ST_OVERFLOW;
+        return;
+    }
+    const float slope = -S1 / S0;  // d ln S0 / d ln h
+    float hn = slope > 0.05f ? s.h * __expf(-__logf(ratio) / slope) : 2.0f * s.h;
+    if (hn >= s.hi) hn = s.hi_known ? 0.5f * (s.h + s.hi) : s.Hi;
+    if (hn <= s.lo) hn = 0.5f * (s.lo + s.h);
+    if (fabsf(hn - s.h) <= 2.5e-7f * s.h) {
+        s.done = true;  // the next step is below FP32 resolution of h: h is the root
+        s.state = ST_DONE;
+        return;
+    }
+    if (s.nev >= max_iter) {
+        s.done = true;
+        s.state = ST_UNCONVERGED;
+        return;
+    }
+    s.h = hn;
+}
+
+// Outputs of one particle at its final h (sums M0 = sum m w, M1 = sum m q w').
+__device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSolve& s, float S0, float M0,
+                                             float M1, int cnt, int64_t& inter_acc, int64_t& n_over,
+                                             int64_t& n_unconv, int& max_ev)
+{
+    const uint32_t o = A.perm[i];
+    float h_report = s.h;
+    if (s.state == ST_OVERFLOW) {
+        // propose the radius at which a uniform density would hold the target
+        h_report = s.h * fmaxf(cbrtf(A.target / S0), 1.0f) * 1.05f;
+        ++n_over;
+    } else if (s.state == ST_UNCONVERGED) {
+        ++n_unconv;
+    }
+    const float hinv = 1.0f / s.h;
+    const float rho = (8.0f / SPH_PI_F) * M0 * hinv * hinv * hinv;
+    const float f = M1 < 0.0f ? -3.0f * M0 / M1 : 1.0f;
+    A.hs[i] = s.h;
+    A.rhos[i] = rho;
+    A.fs[i] = f;
+    A.st_s[i] = s.state;
+    A.h_out[o] = h_report;
+    A.rho_out[o] = rho;
+    A.f_out[o] = f;
+    if (A.nw_out) A.nw_out[o] = (32.0f / 3.0f) * S0;
+    A.status[o] = s.state;
+    if (s.state == ST_DONE) inter_acc += cnt - 1;
+    max_ev = max(max_ev, s.nev);
+}
+
+__device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_acc, int64_t inter_acc,
+                                               int64_t sweep_acc, int64_t n_over, int64_t n_unconv, int max_ev,
+                                               int64_t n_scan)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        inter_acc += __shfl_xor(inter_acc, o, 64);
+        sweep_acc += __shfl_xor(sweep_acc, o, 64);
+        n_over += __shfl_xor(n_over, o, 64);
+        n_unconv += __shfl_xor(n_unconv, o, 64);
+        n_scan += __shfl_xor(n_scan, o, 64);
+        max_ev = max(max_ev, __shfl_xor(max_ev, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_INTER], (unsigned long long)inter_acc);
+        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_CAND], (unsigned long long)cand_acc);
+        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_SWEEP_INTER], (unsigned long long)sweep_acc);
+        if (n_over) atomicAdd((unsigned long long*)&A.ctr[CT_OVERFLOW], (unsigned long long)n_over);
+        if (n_unconv) atomicAdd((unsigned long long*)&A.ctr[CT_UNCONV], (unsigned long long)n_unconv);
+        if (n_scan) atomicAdd((unsigned long long*)&A.ctr[CT_NEED_SCAN], (unsigned long long)n_scan);
+        atomicMax((unsigned long long*)&A.ctr[CT_SWEEPS], (unsigned long long)max_ev);
+    }
+}
+
+// ---- the list kernel ----------------------------------------------------------------
+
 __global__ void __launch_bounds__(BS) k_density(DensArgs A)
 {
-    __shared__ float4 tile[WAVES][CAP];
+    __shared__ float4 tile[WAVES][DCAP];
+    __shared__ float lists[WAVES][(DSLOTS + 1) * 64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     float4* sj = tile[wv];
-    const int xcd = blockIdx.x & 7;
-    int q_skip = 0;
-    int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0;
+    float* lst = lists[wv] + lane;
+    int wstate = 0, a_cur = 0, a_end = 0;
+    int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0;
     int max_ev = 0;
-    int64_t n_over = 0, n_unconv = 0;
+    const bool uniform_mass = A.ctr[CT_MASS_MIN] == A.ctr[CT_MASS_MAX];
+    const float m0 = __uint_as_float((unsigned)A.ctr[CT_MASS_MIN]);
 
     for (;;) {
-        const int a = pop_item(A.ctr, A.q_begin, xcd, q_skip);
-        if (a < 0) break;
+        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
+        const int a = a_cur++;
         const int i0 = A.lf_start[a];
         const int ni = A.lf_count[a];
         const int pb0 = (int)A.p_start[a];
         const int np_all = (int)A.p_start[a + 1] - pb0;
-
-        const int nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
-        const int lpi = ni <= 8 ? 8 : (ni <= 16 ? 4 : (ni <= 32 ? 2 : 1));
-        const int sub = lane & (lpi - 1);
-        const int per_pass = 64 / lpi;
-        const bool single_tile = nj <= CAP;
+        const Groups G = make_groups(ni);
+        if (!uniform_mass || np_all > 64) {
+            // unequal masses need the mass of every neighbour; very long
+            // neighbour-cell lists take the general staging: both re-scan
+            for (int gi = lane; gi < ni; gi += 64) {
+                if (A.st_s[i0 + gi] == ST_ACTIVE) {
+                    A.st_s[i0 + gi] = ST_SCAN;
+                    ++n_scan;
+                }
+            }
+            continue;
+        }
+        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
+        const int nj = nb.nj;
+        const bool single_tile = nj <= DCAP;
         bool loaded = false;
 
-        for (int ib = 0; ib < ni; ib += per_pass) {
-            const int gi = ib + lane / lpi;
-            const bool valid = gi < ni;
+        for (int ib = 0; ib < ni; ib += G.per_pass) {
+            const int gi = ib + G.g;
+            const bool valid = G.g < G.per_pass && gi < ni;
             const int i = i0 + (valid ? gi : 0);
             const float4 xi = A.jd[i];
-            const float Hi = A.Hs[i];
-            float h = A.hs[i];
             const uint8_t st0 = A.st_s[i];
-            bool done = !valid || st0 != ST_ACTIVE;
-            if (!(h > 0.0f) || h > Hi) h = Hi;
-            float lo = 0.0f, hi = Hi;
-            bool hi_known = false;
-            uint8_t state = st0;
-            int nev = 0;
-            float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
-            int cnt = 0;
-            while (__any(!done)) {
-                const float h2 = h * h;
-                const float hinv = 1.0f / h;
-                S0 = S1 = M0 = M1 = 0.f;
-                cnt = 0;
-                int active_groups = (!done && sub == 0) ? 1 : 0;
-                for (int c0 = 0; c0 < nj; c0 += CAP) {
-                    const int len = min(CAP, nj - c0);
-                    if (!(single_tile && loaded)) {
-                        stage_tile<1>(sj, A.jd, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len);
+            HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_ACTIVE, st0);
+            const int active_groups = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
+            if (active_groups == 0) continue;
+
+            // ---- phase A: squared distances inside the search radius -----------
+            int nl = 0;
+            {
+                const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
+                ChunkRegs<1, DCAP> R;
+                const bool stream_chunks = !(single_tile && loaded);
+                if (stream_chunks) fetch_chunk(R, A.jd, nb, 0, min(DCAP, nj));
+                for (int c0 = 0; c0 < nj; c0 += DCAP) {
+                    const int len = min(DCAP, nj - c0);
+                    if (stream_chunks) {
+                        commit_chunk(sj, R);  // store this chunk, put the next in flight
+                        if (c0 + DCAP < nj) fetch_chunk(R, A.jd, nb, c0 + DCAP, min(DCAP, nj - c0 - DCAP));
                         loaded = true;
                     }
+                    // four tile reads in flight, then branch-free appends: the
+                    // store always happens, the slot only advances on a hit
+                    for (int k0 = G.sub; k0 < len; k0 += 4 * G.lpi) {
+                        float4 pj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) pj[u] = sj[min(k0 + u * G.lpi, len - 1)];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float dx = xi.x - pj[u].x, dy = xi.y - pj[u].y, dz = xi.z - pj[u].z;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                            const bool in = (r2 < H2) & (k0 + u * G.lpi < len);
+                            lst[min(nl, DSLOTS) * 64] = r2;
+                            nl += in ? 1 : 0;
+                        }
+                    }
+                    if (!single_tile) wave_sync_lds();
+                }
+                cand_acc += (int64_t)active_groups * nj;
+            }
+            // a group whose list does not fit goes to the re-scanning kernel
+            const bool fits = gsum_i(nl > DSLOTS ? 1 : 0, G) == 0;
+            if (!s.done && !fits) {
+                s.done = true;
+                if (G.sub == 0) {
+                    A.st_s[i] = ST_SCAN;
+                    ++n_scan;
+                }
+            }
+
+            // ---- phase B: Newton iteration on h over the list --------------------
+            // (fS0, fS1, fcnt: the sums of this particle's last evaluation; a
+            // finished particle skips its list while others still iterate)
+            float S0 = 0.f, S1 = 0.f, fS0 = 0.f, fS1 = 0.f;
+            int cnt = 0, fcnt = 0;
+            while (__any(!s.done)) {
+                const float h2 = s.h * s.h;
+                const float hinv = 1.0f / s.h;
+                S0 = S1 = 0.f;
+                cnt = 0;
+                const int len_l = s.done ? 0 : nl;
 #pragma unroll 4
-                    for (int k = sub; k < len; k += lpi) {
+                for (int e = 0; e < len_l; ++e) {
+                    const float r2 = lst[e * 64];
+                    const bool in = r2 < h2;
+                    const float q = in ? __builtin_amdgcn_sqrtf(r2) * hinv : 1.0f;
+                    float w, dw;
+                    spline_w_dw(q, w, dw);
+                    S0 += w;
+                    S1 = fmaf(q, dw, S1);
+                    cnt += in ? 1 : 0;
+                }
+                cand_acc += wave_sum_i(len_l);
+                S0 = gsum(S0, G);
+                S1 = gsum(S1, G);
+                cnt = gsum_i(cnt, G);
+                if (s.done) continue;
+                if (G.sub == 0) sweep_acc += cnt;
+                fS0 = S0;
+                fS1 = S1;
+                fcnt = cnt;
+                hsolve_step(s, S0, S1, A.target, A.tol, A.max_iter);
+            }
+            if (valid && G.sub == 0 && st0 == ST_ACTIVE && fits)
+                write_result(A, i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
+        }
+    }
+    flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
+}
+
+// ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
+
+__global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
+{
+    __shared__ float4 tile[WAVES][SCAP];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    float4* sj = tile[wv];
+    int wstate = 0, a_cur = 0, a_end = 0;
+    int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
+    int max_ev = 0;
+
+    for (;;) {
+        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
+        const int a = a_cur++;
+        const int i0 = A.lf_start[a];
+        const int ni = A.lf_count[a];
+        const int pb0 = (int)A.p_start[a];
+        const int np_all = (int)A.p_start[a + 1] - pb0;
+        // skip cells without flagged particles
+        int flagged = 0;
+        for (int gi = lane; gi < ni; gi += 64) flagged += A.st_s[i0 + gi] == ST_SCAN ? 1 : 0;
+        if (wave_sum_i(flagged) == 0) continue;
+        const int nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        const Groups G = make_groups(ni);
+        const bool single_tile = nj <= SCAP;
+        bool loaded = false;
+        for (int ib = 0; ib < ni; ib += G.per_pass) {
+            const int gi = ib + G.g;
+            const bool valid = G.g < G.per_pass && gi < ni;
+            const int i = i0 + (valid ? gi : 0);
+            const float4 xi = A.jd[i];
+            const uint8_t st0 = A.st_s[i];
+            HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_SCAN, ST_ACTIVE);
+            if (wave_sum_i((!s.done && G.sub == 0) ? 1 : 0) == 0) continue;
+            float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
+            int cnt = 0;
+            while (__any(!s.done)) {
+                const float h2 = s.h * s.h;
+                const float hinv = 1.0f / s.h;
+                S0 = S1 = M0 = M1 = 0.f;
+                cnt = 0;
+                const int groups_now = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
+                for (int c0 = 0; c0 < nj; c0 += SCAP) {
+                    const int len = min(SCAP, nj - c0);
+                    if (!(single_tile && loaded)) {
+                        stage_tile<1>(sj, A.jd, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0,
+                                      len);
+                        loaded = true;
+                    }
+                    for (int k = G.sub; k < len; k += G.lpi) {
                         const float4 pj = sj[k];
                         const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                         const bool in = r2 < h2;
-                        const float q = in ? sqrtf(r2) * hinv : 1.0f;
+                        const float q = in ? __builtin_amdgcn_sqrtf(r2) * hinv : 1.0f;
                         float w, dw;
                         spline_w_dw(q, w, dw);
                         const float qdw = q * dw;
@@ -158,123 +418,42 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                         M1 = fmaf(pj.w, qdw, M1);
                         cnt += in ? 1 : 0;
                     }
-                    if (!single_tile) {
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                    }
+                    if (!single_tile) wave_sync_lds();
                 }
-                S0 = group_sum(S0, lpi);
-                S1 = group_sum(S1, lpi);
-                M0 = group_sum(M0, lpi);
-                M1 = group_sum(M1, lpi);
-                cnt = group_sum_i(cnt, lpi);
-                // count tested pairs once per group
-                for (int o = 32; o >= 1; o >>= 1) active_groups += __shfl_xor(active_groups, o, 64);
-                cand_acc += (int64_t)active_groups * nj;
-                if (!done && sub == 0) sweep_acc += cnt;
-                if (done) continue;
-                ++nev;
-                const float ratio = S0 / A.target;
-                if (fabsf(ratio - 1.0f) <= A.tol) {
-                    done = true;
-                    state = ST_DONE;
-                    continue;
-                }
-                if (ratio < 1.0f) {
-                    lo = h;
-                } else {
-                    hi = h;
-                    hi_known = true;
-                }
-                if (ratio < 1.0f && h >= Hi) {
-                    // the root lies beyond the search radius: ask for a rebuild,
-                    // proposing the radius at which a uniform density would hold
-                    // the target count
-                    done = true;
-                    state = ST_OVERFLOW;
-                    continue;
-                }
-                const float slope = -S1 / S0;  // d ln S0 / d ln h
-                float hn = slope > 0.05f ? h * __expf(-__logf(ratio) / slope) : 2.0f * h;
-                if (hn >= hi) hn = hi_known ? 0.5f * (h + hi) : Hi;
-                if (hn <= lo) hn = 0.5f * (lo + h);
-                if (fabsf(hn - h) <= 2.5e-7f * h) {
-                    // the next step is below FP32 resolution of h: h is the root
-                    done = true;
-                    state = ST_DONE;
-                    continue;
-                }
-                if (nev >= A.max_iter) {
-                    done = true;
-                    state = ST_UNCONVERGED;
-                    continue;
-                }
-                h = hn;
+                cand_acc += (int64_t)groups_now * nj;
+                S0 = gsum(S0, G);
+                S1 = gsum(S1, G);
+                M0 = gsum(M0, G);
+                M1 = gsum(M1, G);
+                cnt = gsum_i(cnt, G);
+                if (s.done) continue;
+                if (G.sub == 0) sweep_acc += cnt;
+                hsolve_step(s, S0, S1, A.target, A.tol, A.max_iter);
             }
-            // results
-            if (valid && sub == 0 && st0 == ST_ACTIVE) {
-                const uint32_t o = A.perm[i];
-                float h_report = h;
-                if (state == ST_OVERFLOW) {
-                    const float grow = cbrtf(A.target / S0);
-                    h_report = h * fmaxf(grow, 1.0f) * 1.05f;
-                    ++n_over;
-                } else if (state == ST_UNCONVERGED) {
-                    ++n_unconv;
-                }
-                const float hinv = 1.0f / h;
-                const float rho = (8.0f / SPH_PI_F) * M0 * hinv * hinv * hinv;
-                const float f = M1 < 0.0f ? -3.0f * M0 / M1 : 1.0f;
-                A.hs[i] = h;
-                A.rhos[i] = rho;
-                A.fs[i] = f;
-                A.st_s[i] = state;
-                A.h_out[o] = h_report;
-                A.rho_out[o] = rho;
-                A.f_out[o] = f;
-                if (A.nw_out) A.nw_out[o] = (32.0f / 3.0f) * S0;
-                A.status[o] = state;
-                if (state == ST_DONE) inter_acc += cnt - 1;
-                max_ev = max(max_ev, nev);
-            }
+            if (valid && G.sub == 0 && st0 == ST_SCAN)
+                write_result(A, i, s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
         }
     }
-    // per-wave totals
-    for (int o = 32; o >= 1; o >>= 1) {
-        inter_acc += __shfl_xor(inter_acc, o, 64);
-        sweep_acc += __shfl_xor(sweep_acc, o, 64);
-        n_over += __shfl_xor(n_over, o, 64);
-        n_unconv += __shfl_xor(n_unconv, o, 64);
-        max_ev = max(max_ev, __shfl_xor(max_ev, o, 64));
-    }
-    if (lane == 0) {
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_INTER], (unsigned long long)inter_acc);
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_CAND], (unsigned long long)cand_acc);
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_SWEEP_INTER], (unsigned long long)sweep_acc);
-        if (n_over) atomicAdd((unsigned long long*)&A.ctr[CT_OVERFLOW], (unsigned long long)n_over);
-        if (n_unconv) atomicAdd((unsigned long long*)&A.ctr[CT_UNCONV], (unsigned long long)n_unconv);
-        atomicMax((unsigned long long*)&A.ctr[CT_SWEEPS], (unsigned long long)max_ev);
-    }
+    flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
 }
-
-constexpr int DENS_CAP = 768;
 
 }  // namespace
 
 namespace sph {
 
-void queue_bounds(int64_t n_items, int* q_begin)
+// Work schedule of a hot kernel over n_items cells and the grid to launch:
+// one wavefront per cell under hardware dispatch, or a machine-sized grid of
+// persistent wavefronts popping batches from the per-XCD queues.
+int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_cu, WorkSched& W)
 {
-    for (int q = 0; q <= 8; ++q) q_begin[q] = (int)((n_items * q) / 8);
-}
-
-int persistent_blocks(sph_ctx* c, int blocks_per_cu, int64_t n_items, int waves_per_block)
-{
-    int64_t want = (int64_t)c->n_cu * blocks_per_cu;
-    int64_t cap = (n_items + waves_per_block - 1) / waves_per_block;
-    if (want > cap) want = cap;
-    if (want < 1) want = 1;
-    return (int)want;
+    W.persistent = c->prm.schedule == 1 ? 1 : 0;
+    W.batch = c->prm.queue_batch > 0 ? c->prm.queue_batch : 4;
+    W.n_items = (int)n_items;
+    for (int q = 0; q <= 8; ++q) W.q_begin[q] = (int)((n_items * q) / 8);
+    const int64_t all = (n_items + waves_per_block - 1) / waves_per_block;
+    int64_t grid = all;
+    if (W.persistent) grid = std::min<int64_t>(all, (int64_t)c->n_cu * blocks_per_cu);
+    return (int)std::max<int64_t>(grid, 1);
 }
 
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, sph_stats* st,
@@ -286,24 +465,24 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     uint8_t* status = ensure<uint8_t>(c, c->status, n);
     SPH_HIP(hipMemsetAsync(status, ST_ACTIVE, (size_t)n, s));
-    int64_t tot_inter = 0, tot_cand = 0;
+    int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0;
     int32_t sweeps = 0;
     c->rebuilds = 0;
     c->density_done = false;
     c->tm.density_kernel_ms = 0.0;
     c->tm.density_launches = 0;
-    int64_t tot_sweep_inter = 0;
     ev_record(c, EV_DENS_C0, s);
-    for (int pass = 0;; ++pass) {
+    for (;;) {
         float4* jd = ensure<float4>(c, c->jd, n);
         float* hs = ensure<float>(c, c->hs, n);
         float* rhos = ensure<float>(c, c->rhos, n);
         float* fs = ensure<float>(c, c->fs, n);
         uint8_t* st_s = ensure<uint8_t>(c, c->st_s, n);
         SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
-        k_dens_prologue<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
-                                                          static_cast<float4*>(c->xrel.p), mass, h, status, jd,
-                                                          hs, st_s, ctr);
+        SPH_HIP(hipMemsetAsync(&ctr[CT_MASS_MIN], 0xff, 8, s));
+        k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                            static_cast<float4*>(c->xrel.p), mass, h, status, jd,
+                                                            hs, st_s, ctr);
         SPH_HIP(hipGetLastError());
         DensArgs A;
         A.jd = jd;
@@ -324,13 +503,12 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         A.nw_out = nw;
         A.status = status;
         A.ctr = ctr;
-        queue_bounds(c->n_leaves, A.q_begin);
         A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
         A.tol = (float)c->prm.n_tol;
         A.max_iter = c->prm.max_iter;
-        const int grid = persistent_blocks(c, 3, c->n_leaves, WAVES);
+        const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
         ev_record(c, EV_DENS_K0, s);
-        k_density<DENS_CAP><<<grid, BS, 0, s>>>(A);
+        k_density<<<grid, BS, 0, s>>>(A);
         SPH_HIP(hipGetLastError());
         ev_record(c, EV_DENS_K1, s);
         int64_t hc[CT_COUNT];
@@ -338,10 +516,26 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         SPH_HIP(hipStreamSynchronize(s));
         c->tm.density_kernel_ms += ev_ms(c, EV_DENS_K0, EV_DENS_K1);
         c->tm.density_launches += 1;
-        tot_sweep_inter += hc[CT_DENS_SWEEP_INTER];
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "non-positive or non-finite mass or h");
+        if (hc[CT_NEED_SCAN] > 0) {
+            // particles whose lists did not fit (or unequal masses): re-scan them
+            const int64_t keep[] = {hc[CT_DENS_INTER], hc[CT_DENS_CAND], hc[CT_DENS_SWEEP_INTER],
+                                    hc[CT_OVERFLOW], hc[CT_UNCONV], hc[CT_SWEEPS]};
+            SPH_HIP(hipMemsetAsync(&ctr[CT_QUEUE], 0, 8 * 8, s));
+            make_sched(c, c->n_leaves, WAVES, 12, A.W);
+            ev_record(c, EV_DENS_K0, s);
+            k_density_scan<<<grid, BS, 0, s>>>(A);
+            SPH_HIP(hipGetLastError());
+            ev_record(c, EV_DENS_K1, s);
+            SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+            SPH_HIP(hipStreamSynchronize(s));
+            c->tm.density_kernel_ms += ev_ms(c, EV_DENS_K0, EV_DENS_K1);
+            c->tm.density_launches += 1;
+            (void)keep;
+        }
         tot_inter += hc[CT_DENS_INTER];
         tot_cand += hc[CT_DENS_CAND];
+        tot_sweep_inter += hc[CT_DENS_SWEEP_INTER];
         sweeps = std::max<int32_t>(sweeps, (int32_t)hc[CT_SWEEPS]);
         if (hc[CT_OVERFLOW] == 0) {
             if (st) {
@@ -357,8 +551,8 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
                 st->n_pairs = c->n_pairs;
             }
             if (c->rebuilds > 0) {
-                k_dens_regather<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p), h, rho, f,
-                                                                  hs, rhos, fs);
+                k_dens_regather<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p), h, rho,
+                                                                    f, hs, rhos, fs);
                 SPH_HIP(hipGetLastError());
             }
             ev_record(c, EV_DENS_C1, s);

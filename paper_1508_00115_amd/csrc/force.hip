@@ -17,9 +17,10 @@
 
 namespace {
 
-constexpr int BS = 256;
+constexpr int BS = 128;
 constexpr int WAVES = BS / 64;
-constexpr int FCAP = 256;  // candidates per LDS chunk (3 float4 each)
+constexpr int FCAP = 128;  // candidates per LDS chunk (3 float4 each)
+constexpr int FSLOTS = FCAP / 2;  // a lane (2+ lanes per particle) tests at most every second candidate
 
 __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ jd,
                                  const float* __restrict__ hs, const float* __restrict__ rhos,
@@ -59,37 +60,46 @@ struct ForceArgs {
     float* dudt;
     double* cons;  // 4 per box, may be null
     int64_t* ctr;
-    int q_begin[9];
+    WorkSched W;
     float alpha;
 };
 
 __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
 {
     __shared__ float4 tile[WAVES][3 * FCAP];
+    __shared__ uint8_t lists[WAVES][FSLOTS * 64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     float4* sj = tile[wv];
-    const int xcd = blockIdx.x & 7;
-    int q_skip = 0;
+    uint8_t* lst = lists[wv];
+    int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0;
     const float K8PI = 8.0f / SPH_PI_F;
 
     for (;;) {
-        const int a = pop_item(A.ctr, A.q_begin, xcd, q_skip);
-        if (a < 0) break;
+        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
+        const int a = a_cur++;
         const int i0 = A.lf_start[a];
         const int ni = A.lf_count[a];
         const int pb0 = (int)A.p_start[a];
         const int np_all = (int)A.p_start[a + 1] - pb0;
-        const int nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
-        const int lpi = ni <= 8 ? 8 : (ni <= 16 ? 4 : (ni <= 32 ? 2 : 1));
-        const int sub = lane & (lpi - 1);
-        const int per_pass = 64 / lpi;
+        const bool fastnb = np_all <= 64;
+        NbrLanes nb;
+        int nj;
+        if (fastnb) {
+            nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
+            nj = nb.nj;
+        } else {
+            nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        }
+        const Groups G = make_groups(ni);
+        const int lpi = G.lpi;
+        const int sub = G.sub;
         const bool single_tile = nj <= FCAP;
         bool loaded = false;
-        for (int ib = 0; ib < ni; ib += per_pass) {
-            const int gi = ib + lane / lpi;
-            const bool valid = gi < ni;
+        for (int ib = 0; ib < ni; ib += G.per_pass) {
+            const int gi = ib + G.g;
+            const bool valid = G.g < G.per_pass && gi < ni;
             const int i = i0 + (valid ? gi : 0);
             const float4 i0v = A.jf[3 * (int64_t)i + 0];
             const float4 i1v = A.jf[3 * (int64_t)i + 1];
@@ -100,15 +110,47 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
             float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
             int cnt = 0;
+            ChunkRegs<3, FCAP> R;
+            const bool stream_chunks = !(single_tile && loaded);
+            if (fastnb && stream_chunks) fetch_chunk(R, A.jf, nb, 0, min(FCAP, nj));
             for (int c0 = 0; c0 < nj; c0 += FCAP) {
                 const int len = min(FCAP, nj - c0);
-                if (!(single_tile && loaded)) {
-                    stage_tile<3>(sj, A.jf, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len,
-                                  FCAP);
+                if (stream_chunks) {
+                    if (fastnb) {
+                        // store this chunk, then put the next one in flight while
+                        // this one is computed
+                        commit_chunk(sj, R);
+                        if (c0 + FCAP < nj) fetch_chunk(R, A.jf, nb, c0 + FCAP, min(FCAP, nj - c0 - FCAP));
+                    } else {
+                        stage_tile<3>(sj, A.jf, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len,
+                                      FCAP);
+                    }
                     loaded = true;
                 }
+                // phase A: compact the candidates inside max(h_i, h_j) of this chunk
+                // (four tile reads in flight, branch-free appends: the store always
+                // happens and the slot only advances on a hit)
+                int nl = 0;
+                for (int k0 = sub; k0 < len; k0 += 4 * lpi) {
+                    float4 pj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pj[u] = sj[min(k0 + u * lpi, len - 1)];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = k0 + u * lpi;
+                        const float dx = i0v.x - pj[u].x, dy = i0v.y - pj[u].y, dz = i0v.z - pj[u].z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float hinv2_j = pj[u].w * pj[u].w;
+                        const bool in = ((r2 * hinv2_i < 1.0f) | (r2 * hinv2_j < 1.0f)) & (r2 > 0.0f) & (k < len);
+                        lst[nl * 64 + lane] = (uint8_t)k;
+                        nl += in ? 1 : 0;
+                    }
+                }
+                cnt += nl;
+                // phase B: the pair terms of the compacted neighbours only
 #pragma unroll 2
-                for (int k = sub; k < len; k += lpi) {
+                for (int e = 0; e < nl; ++e) {
+                    const int k = lst[e * 64 + lane];
                     const float4 p0 = sj[k];
                     const float4 p1 = sj[FCAP + k];
                     const float4 p2 = sj[2 * FCAP + k];
@@ -116,37 +158,33 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const float hinv_j = p0.w;
                     const float hinv2_j = hinv_j * hinv_j;
-                    const bool in = (r2 * hinv2_i < 1.0f || r2 * hinv2_j < 1.0f) && r2 > 0.0f;
-                    const float r2s = in ? r2 : 1.0f;
-                    const float rinv = rsqrtf(r2s);
-                    const float r = r2s * rinv;
+                    const float rinv = rsqrtf(r2);
+                    const float r = r2 * rinv;
                     const float qi = fminf(r * hinv_i, 1.0f);
                     const float qj = fminf(r * hinv_j, 1.0f);
                     const float Di = Ki * spline_dw(qi);
                     const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw(qj);
                     const float vr = ((i1v.x - p1.x) * dx + (i1v.y - p1.y) * dy + (i1v.z - p1.z) * dz) * rinv;
                     const float wv_ = fminf(vr, 0.0f);
-                    const float visc = -A.alpha * (c_i + p2.z - 3.0f * wv_) * wv_ / (rho_i + p2.x);
+                    const float visc = -A.alpha * (c_i + p2.z - 3.0f * wv_) * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
                     const float Dbar = 0.5f * (Di + Dj);
                     const float G = fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
-                    const float mj = in ? p1.w : 0.0f;
-                    const float mGr = mj * G * rinv;
+                    const float mGr = p1.w * G * rinv;
                     ax = fmaf(-mGr, dx, ax);
                     ay = fmaf(-mGr, dy, ay);
                     az = fmaf(-mGr, dz, az);
-                    du = fmaf(mj * fmaf(phi_i, Di, 0.5f * visc * Dbar), vr, du);
-                    cnt += in ? 1 : 0;
+                    du = fmaf(p1.w * fmaf(phi_i, Di, 0.5f * visc * Dbar), vr, du);
                 }
                 if (!single_tile) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                 }
             }
-            ax = group_sum(ax, lpi);
-            ay = group_sum(ay, lpi);
-            az = group_sum(az, lpi);
-            du = group_sum(du, lpi);
-            cnt = group_sum_i(cnt, lpi);
+            ax = gsum(ax, G);
+            ay = gsum(ay, G);
+            az = gsum(az, G);
+            du = gsum(du, G);
+            cnt = gsum_i(cnt, G);
             const bool leader = valid && sub == 0;
             int ng = leader ? 1 : 0;
             for (int o = 32; o >= 1; o >>= 1) ng += __shfl_xor(ng, o, 64);
@@ -188,8 +226,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
 
 namespace sph {
 
-void queue_bounds(int64_t n_items, int* q_begin);
-int persistent_blocks(sph_ctx* c, int blocks_per_cu, int64_t n_items, int waves_per_block);
+int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_cu, WorkSched& W);
 
 void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons,
                sph_stats* st, hipStream_t s)
@@ -225,9 +262,8 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     A.dudt = dudt;
     A.cons = cons_d;
     A.ctr = ctr;
-    queue_bounds(c->n_leaves, A.q_begin);
+    const int grid = make_sched(c, c->n_leaves, WAVES, 4, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
-    const int grid = persistent_blocks(c, 3, c->n_leaves, WAVES);
     ev_record(c, EV_FORCE_K0, s);
     k_force<<<grid, BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());

@@ -4,6 +4,63 @@
 
 #include "common.h"
 
+// Work sources of the hot kernels. Items (cells) are in Morton order.
+//   hardware dispatch: one item per wavefront; consecutive workgroups are
+//     placed round-robin on the 8 XCDs, so workgroup b is remapped to run a
+//     contiguous block of items on its XCD and each XCD's L2 sees neighbouring
+//     cells;
+//   persistent: a grid sized to the machine pops batches of items from eight
+//     per-XCD queues (one atomic per batch) and steals from the other queues
+//     when its own is empty.
+struct WorkSched {
+    int persistent;   // 0: hardware dispatch, 1: per-XCD queues
+    int batch;        // items per pop (persistent)
+    int n_items;
+    int q_begin[9];   // queue q covers items [q_begin[q], q_begin[q+1])
+};
+
+// Workgroup index with the XCD round-robin undone: blocks that land on the
+// same XCD get consecutive indices.
+__device__ __forceinline__ int xcd_block_index()
+{
+    const int nb = gridDim.x;
+    const int q = nb / 8, r = nb % 8;
+    const int x = blockIdx.x % 8, l = blockIdx.x / 8;
+    return x * q + min(x, r) + l;
+}
+
+// Next item range [a, a_end) of this wavefront; false when the work is done.
+__device__ __forceinline__ bool next_items(const WorkSched& W, int64_t* ctr, int waves_per_block, int& state,
+                                           int& a, int& a_end)
+{
+    if (!W.persistent) {
+        if (state) return false;
+        state = 1;
+        a = xcd_block_index() * waves_per_block + (int)(threadIdx.x >> 6);
+        a_end = min(a + 1, W.n_items);
+        return a < a_end;
+    }
+    int lo = -1, hi = -1;
+    if ((threadIdx.x & 63) == 0) {
+        const int xcd = blockIdx.x & 7;
+        while (state < 8) {
+            const int q = (xcd + state) & 7;
+            const int size = W.q_begin[q + 1] - W.q_begin[q];
+            const int64_t k = atomicAdd((unsigned long long*)&ctr[CT_QUEUE + q], (unsigned long long)W.batch);
+            if (k < size) {
+                lo = W.q_begin[q] + (int)k;
+                hi = W.q_begin[q] + (int)min<int64_t>(k + W.batch, size);
+                break;
+            }
+            ++state;
+        }
+    }
+    a = __shfl(lo, 0, 64);
+    a_end = __shfl(hi, 0, 64);
+    state = __shfl(state, 0, 64);
+    return a >= 0;
+}
+
 // Pop the next cell for this wavefront; -1 when all queues are drained.
 __device__ __forceinline__ int pop_item(int64_t* ctr, const int* q_begin, int xcd, int& q_skip)
 {
@@ -23,6 +80,52 @@ __device__ __forceinline__ int pop_item(int64_t* ctr, const int* q_begin, int xc
     item = __shfl(item, 0, 64);
     q_skip = __shfl(q_skip, 0, 64);
     return item;
+}
+
+// Lanes of a wavefront split among the particles of a cell: lpi lanes per
+// particle (2 to 16, any size), consecutive lanes forming a group. Lanes past
+// the last full group stay idle.
+struct Groups {
+    int lpi, per_pass, g, sub, base;
+};
+
+__device__ __forceinline__ Groups make_groups(int ni)
+{
+    Groups G;
+    const int lane = threadIdx.x & 63;
+    G.lpi = min(16, max(2, 64 / max(ni, 1)));
+    G.per_pass = 64 / G.lpi;
+    G.g = lane / G.lpi;
+    G.sub = lane - G.g * G.lpi;
+    G.base = G.g * G.lpi;
+    return G;
+}
+
+// Sum over the lanes of this lane's group, returned to every lane of it.
+__device__ __forceinline__ float gsum(float v, const Groups& G)
+{
+    float s = 0.0f;
+    for (int o = 0; o < G.lpi; ++o) s += __shfl(v, min(G.base + o, 63), 64);
+    return s;
+}
+__device__ __forceinline__ int gsum_i(int v, const Groups& G)
+{
+    int s = 0;
+    for (int o = 0; o < G.lpi; ++o) s += __shfl(v, min(G.base + o, 63), 64);
+    return s;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ float group_sum(float v, int lpi)
@@ -95,6 +198,158 @@ __device__ __forceinline__ void stage_tile(float4* sj, const float4* __restrict_
                 }
             }
             off += bck;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Neighbour-cell records of a cell with at most 64 neighbour cells, one per
+// lane: first particle, count, exclusive prefix of the counts (the cell's
+// offset in the flattened candidate list) and the shift into the cell frame.
+struct NbrLanes {
+    int bs, bc, off;
+    float sx, sy, sz;
+    int np, nj;
+};
+
+__device__ __forceinline__ NbrLanes load_nbr(const int* __restrict__ p_leaf, const float4* __restrict__ p_shift,
+                                             const int* __restrict__ lf_start, const int* __restrict__ lf_count,
+                                             int pb0, int np)
+{
+    const int lane = threadIdx.x & 63;
+    NbrLanes nb;
+    nb.bs = 0;
+    nb.bc = 0;
+    nb.sx = nb.sy = nb.sz = 0.f;
+    if (lane < np) {
+        const int bl = p_leaf[pb0 + lane];
+        const float4 sh = p_shift[pb0 + lane];
+        nb.bs = lf_start[bl];
+        nb.bc = lf_count[bl];
+        nb.sx = sh.x;
+        nb.sy = sh.y;
+        nb.sz = sh.z;
+    }
+    int inc = nb.bc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    nb.off = inc - nb.bc;
+    nb.nj = __shfl(inc, 63, 64);
+    nb.np = np;
+    return nb;
+}
+
+// A chunk of candidates in flight: the loads of stage_fast split from the LDS
+// stores, so a kernel can fetch chunk c + 1 while it computes chunk c.
+template <int NF, int CAP>
+struct ChunkRegs {
+    float4 v[CAP / 64][NF];
+    float s[CAP / 64][3];
+    int len;
+};
+
+template <int NF, int CAP>
+__device__ __forceinline__ void fetch_chunk(ChunkRegs<NF, CAP>& R, const float4* __restrict__ jd,
+                                            const NbrLanes& nb, int c0, int len)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+    R.len = len;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        const int kg = c0 + (t < len ? t : 0);
+        int q = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = q + step;
+            const int v = __shfl(nb.off, cand < nb.np ? cand : nb.np - 1, 64);
+            if (cand < nb.np && v <= kg) q = cand;
+        }
+        const int src = __shfl(nb.bs, q, 64) + (kg - __shfl(nb.off, q, 64));
+        R.s[r][0] = __shfl(nb.sx, q, 64);
+        R.s[r][1] = __shfl(nb.sy, q, 64);
+        R.s[r][2] = __shfl(nb.sz, q, 64);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) R.v[r][f] = jd[(int64_t)NF * src + f];
+    }
+}
+
+template <int NF, int CAP>
+__device__ __forceinline__ void commit_chunk(float4* sj, const ChunkRegs<NF, CAP>& R)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        if (t < R.len) {
+            float4 a = R.v[r][0];
+            a.x += R.s[r][0];
+            a.y += R.s[r][1];
+            a.z += R.s[r][2];
+            sj[t] = a;
+#pragma unroll
+            for (int f = 1; f < NF; ++f) sj[f * CAP + t] = R.v[r][f];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
+// the neighbour cell of each of its candidates by a binary search over the
+// lane-held prefix offsets, so all global loads of the chunk are independent
+// and issue back to back.
+template <int NF, int CAP>
+__device__ __forceinline__ void stage_fast(float4* sj, const float4* __restrict__ jd, const NbrLanes& nb, int c0,
+                                           int len)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+    int src[PER];
+    float s3[PER][3];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        const int kg = c0 + (t < len ? t : 0);
+        int q = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = q + step;
+            const int v = __shfl(nb.off, cand < nb.np ? cand : nb.np - 1, 64);
+            if (cand < nb.np && v <= kg) q = cand;
+        }
+        src[r] = __shfl(nb.bs, q, 64) + (kg - __shfl(nb.off, q, 64));
+        s3[r][0] = __shfl(nb.sx, q, 64);
+        s3[r][1] = __shfl(nb.sy, q, 64);
+        s3[r][2] = __shfl(nb.sz, q, 64);
+    }
+    float4 v[PER][NF];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        if (lane + 64 * r < len) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[r][f] = jd[(int64_t)NF * src[r] + f];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        if (t < len) {
+            float4 a = v[r][0];
+            a.x += s3[r][0];
+            a.y += s3[r][1];
+            a.z += s3[r][2];
+            sj[t] = a;
+#pragma unroll
+            for (int f = 1; f < NF; ++f) sj[f * CAP + t] = v[r][f];
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

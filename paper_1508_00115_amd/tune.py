@@ -1,0 +1,101 @@
+"""Autotuner for the cell parameters of the library.
+
+The parameters it searches change only how the work is cut, never the
+result (h is the unique root, and every pair within reach is found for any
+legal cell layout):
+
+    h_margin     search radius over the starting h: candidates per particle
+                 grow like h_margin^3, but h may grow by this factor before
+                 the cells must be rebuilt
+    cell_ratio   smallest cell width below the top grid, in search radii
+    leaf_target  cells holding more particles than this are split
+
+Each setting is timed on the caller's particles with the library's own HIP
+events (density + force, after a warm-up); the fastest wins. Results can be
+cached in a JSON file keyed by a signature of the particle set.
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+DEFAULT_GRID = [
+    {"h_margin": m, "cell_ratio": cr, "leaf_target": lt, "schedule": s}
+    for m in (1.05, 1.1, 1.18, 1.26)
+    for cr in (1.0, 0.5)
+    for lt in (64, 32)
+    for s in (0, 1)
+]
+
+
+def signature(d: dict) -> str:
+    """Key of a particle set: sizes, box layout and summary statistics of h0."""
+    h = np.asarray(d["h0"], dtype=np.float64)
+    parts = [d["pos"].shape[0], len(d["box_len"]), float(h.min()), float(h.max()), float(h.mean()),
+             hashlib.sha1(np.ascontiguousarray(d["box_first"]).tobytes()).hexdigest()[:12]]
+    return json.dumps(parts)
+
+
+def autotune(d: dict, device: int = 0, grid=None, reps: int = 3, cache: str | None = None) -> dict:
+    """Time every setting of ``grid`` on workload ``d`` (a dict as produced by
+    the ``workloads`` package) and return {"best": params, "table": [...]}."""
+    import torch
+
+    from . import Context
+
+    grid = DEFAULT_GRID if grid is None else grid
+    key = signature(d)
+    if cache and os.path.exists(cache):
+        try:
+            store = json.load(open(cache))
+            if key in store:
+                return store[key]
+        except (OSError, ValueError):
+            pass
+    dev = torch.device("cuda", device)
+    pos = torch.from_numpy(d["pos"]).to(dev)
+    h0 = torch.from_numpy(d["h0"]).to(dev)
+    mass = torch.from_numpy(d["mass"]).to(dev)
+    vel = torch.from_numpy(d["vel"]).to(dev)
+    u = torch.from_numpy(d["u"]).to(dev)
+    n = pos.shape[0]
+    h = h0.clone()
+    rho, f = torch.empty_like(h), torch.empty_like(h)
+    acc, dudt = torch.empty((n, 3), dtype=torch.float32, device=dev), torch.empty_like(h)
+    table = []
+    for params in grid:
+        ctx = Context(device, timing=1, **params)
+        try:
+            ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
+            times = []
+            for r in range(reps + 1):
+                h.copy_(h0)
+                st = ctx.density(mass, h, rho, f)["stats"]
+                ctx.force(vel, u, acc, dudt, cons=False)
+                t = ctx.timings()
+                if r > 0:  # first pass warms up
+                    times.append(t["density_call_ms"] + t["force_call_ms"])
+            table.append({"params": params, "ms": float(np.median(times)), "rebuilds": st["rebuilds"],
+                          "cells": st["n_cells"]})
+        except RuntimeError as e:  # e.g. a margin too large for a small box
+            table.append({"params": params, "ms": None, "error": str(e)})
+        finally:
+            ctx.close()
+    ok = [t for t in table if t["ms"] is not None]
+    if not ok:
+        raise RuntimeError("no cell setting ran: %s" % table)
+    best = min(ok, key=lambda t: t["ms"])
+    out = {"best": best["params"], "best_ms": best["ms"], "table": table}
+    if cache:
+        try:
+            store = json.load(open(cache)) if os.path.exists(cache) else {}
+        except (OSError, ValueError):
+            store = {}
+        store[key] = out
+        with open(cache, "w") as fh:
+            json.dump(store, fh)
+    return out

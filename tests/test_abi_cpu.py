@@ -44,8 +44,8 @@ def test_status_strings_and_version(lib):
 
 
 def test_struct_layouts_match_header():
-    # sph_params: 4 doubles, int32 (+pad), 2 doubles, int32 (+pad), int64, int32 (+pad)
-    assert ctypes.sizeof(sph.sph_params) == 80
+    # sph_params: 4 doubles, int32 (+pad), 2 doubles, int32 (+pad), int64, 3 int32 (+pad)
+    assert ctypes.sizeof(sph.sph_params) == 88
     assert ctypes.sizeof(sph.sph_stats) == 72
     assert ctypes.sizeof(sph.sph_timings) == 48
 
