@@ -66,7 +66,7 @@ def _workload(name: str):
 def cpu_baseline(d: dict, min_seconds: float) -> dict:
     import oracle
     reps, t_tot, inter = 0, 0.0, 0
-    while reps < 1 or (t_tot < min_seconds and reps < 20):
+    while reps < 1 or (t_tot < min_seconds and reps < 200):
         r = oracle.run(d)
         t_tot += r["t_density"] + r["t_force"]
         inter = int(r["nngb"].sum() + r["npair"].sum())
@@ -77,6 +77,45 @@ def cpu_baseline(d: dict, min_seconds: float) -> dict:
                       "%d repetition(s), %.1f s" % (reps, t_tot)}
 
 
+KERNEL_SOURCES = {
+    "k_density": ["density.hip", "tiles.h", "common.h"],
+    "k_force": ["force.hip", "tiles.h", "common.h"],
+}
+
+
+def _kernel_hash(kname: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kname]:
+        with open(os.path.join(ROOT, "paper_1508_00115_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(kname: str, params: dict):
+    """HBM bytes per launch of kernel kname from its committed counter profile
+    (FETCH_SIZE and WRITE_SIZE, each divided by the factor the same counter
+    reads for a device copy of known size), or None when there is no profile,
+    or the kernel sources or cell parameters changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_sedov64_traffic.txt" % kname)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "\t", "#", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv["kernel_sources_sha256"] != _kernel_hash(kname) or json.loads(kv["params"]) != params:
+            return None
+        fetch = float(kv["fetch_bytes_per_launch"]) / float(kv["copy_factor_fetch"])
+        write = float(kv["write_bytes_per_launch"]) / float(kv["copy_factor_write"])
+    except (KeyError, ValueError):
+        return None
+    return {"bytes": fetch + write}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,20 +124,37 @@ def main() -> int:
     ap.add_argument("--workload", default="sedov")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner")
+    ap.add_argument("--tune", action="store_true", help="re-run the autotuner instead of the stored table")
+    ap.add_argument("--tune-out", default=None, help="merge a fresh tuning result into this JSON file")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="MiB of an untimed device copy to calibrate hardware byte counters")
+    ap.add_argument("--params", default=None,
+                    help='cell parameters as JSON instead of the autotuner, e.g. '
+                         '\'{"h_margin": 1.18, "cell_ratio": 0.5, "leaf_target": 32, "schedule": 1}\'')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus %d requested): the library "
+              "has no multi-GPU path" % args.gpus, file=sys.stderr)
         return 2
 
     import torch
     import paper_1508_00115_amd as sph
 
+    dev = torch.device("cuda:0")
+    if args.copy_probe > 0:
+        # a device-to-device copy of known size, outside the timed region: the
+        # hardware byte counters of its kernel calibrate those of the others
+        words = int(args.copy_probe * 2 ** 20) // 4
+        src = torch.ones(words, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     d, desc = _workload(args.workload)
     n = d["pos"].shape[0]
-    dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     pos = torch.from_numpy(d["pos"]).to(dev)
     h0 = torch.from_numpy(d["h0"]).to(dev)
@@ -113,9 +169,19 @@ def main() -> int:
 
     tuned = None
     params = {}
-    if not args.no_tune:
+    tune_source = "library defaults"
+    if args.params:
+        params = json.loads(args.params)
+        tune_source = "--params"
+    elif not args.no_tune:
         from paper_1508_00115_amd import tune
-        tuned = tune.autotune(d, 0)
+        tuned = None if args.tune else tune.lookup(d)
+        tune_source = "stored tuning table"
+        if tuned is None:
+            tuned = tune.autotune(d, 0)
+            tune_source = "autotuned in this run"
+            if args.tune_out:
+                tune.save(d, tuned, args.tune_out)
         params = tuned["best"]
     ctx = sph.Context(0, timing=1, **params)
     ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
@@ -133,11 +199,12 @@ def main() -> int:
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    dk, fk, dc, fc = [], [], [], []
+    dk, dl, fk, dc, fc = [], [], [], [], []
     e0.record(stream)
     for _ in range(args.steps):
         sd, sf, t = step()
         dk.append(t["density_kernel_ms"])
+        dl.append(t["density_kernel_ms"] - t["density_rescan_ms"])
         fk.append(t["force_kernel_ms"])
         dc.append(t["density_call_ms"])
         fc.append(t["force_call_ms"])
@@ -171,7 +238,7 @@ def main() -> int:
     value64 = inter / (ms_step64 * 1e-3)
 
     # ---- roofline of the dominant kernel ------------------------------------------------
-    dens_ms = float(np.mean(dk))
+    dens_ms = float(np.mean(dl))  # the list kernel alone (the re-scan kernel is timed apart)
     force_ms = float(np.mean(fk))
     dens_alg = FLOP_DENSITY * sd["sweep_interactions_density"] + \
         FLOP_REJECT * (sd["candidates_density"] - sd["sweep_interactions_density"])
@@ -182,6 +249,7 @@ def main() -> int:
     else:
         kname, kms, alg = "k_force", force_ms, force_alg
     achieved = alg / (kms * 1e-3) / 1e12
+    traffic = _traffic(kname, params)
     useful = (FLOP_DENSITY * sd["sweep_interactions_density"] + FLOP_FORCE * sf["interactions_force"]) / \
         ((dens_ms + force_ms) * 1e-3) / 1e12
 
@@ -202,9 +270,13 @@ def main() -> int:
                    "density_interactions": sd["interactions_density"],
                    "force_interactions": sf["interactions_force"], "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None if traffic is None else traffic["bytes"],
+                     "traffic_unit": "bytes per launch (HBM, from hardware counters)",
+                     "traffic_gbs": None if traffic is None else traffic["bytes"] / (kms * 1e-3) / 1e9,
                      "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg},
-        "kernels_ms": {"density_kernel": dens_ms, "density_call": float(np.mean(dc)),
+        "kernels_ms": {"density_kernel": dens_ms, "density_rescan_kernel": float(np.mean(dk)) - dens_ms,
+                       "density_call": float(np.mean(dc)),
                        "force_kernel": force_ms, "force_call": float(np.mean(fc)), "build": build_ms},
         "useful_tflops": useful,
         "density": {"sweeps": sd["sweeps"], "rebuilds": sd["rebuilds"],
@@ -215,6 +287,7 @@ def main() -> int:
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
         "speedup_vs_fp64_plain": value / value64,
         "cell_params": params or "library defaults",
+        "cell_params_from": tune_source,
         "autotune": None if tuned is None else [
             {**t["params"], "ms": t["ms"], "rebuilds": t.get("rebuilds")} for t in tuned["table"]],
     }

@@ -98,12 +98,15 @@ typedef struct {
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP
  * events on the caller's stream (zero unless sph_params.timing was set). */
 typedef struct {
-    double density_kernel_ms;  /* FP32 density kernel, summed over rebuild passes */
+    double density_kernel_ms;  /* FP32 density kernels (list and re-scan), summed
+                                  over rebuild passes */
     double density_call_ms;    /* whole sph_density: prologues, kernels, copies */
     double force_kernel_ms;    /* FP32 force kernel */
     double force_call_ms;      /* whole sph_force: ghost step, kernel, copies */
     double build_ms;           /* host wall time of the last sph_build_cells */
-    int32_t density_launches;  /* density kernel launches of the last sph_density */
+    int32_t density_launches;  /* density kernel launches of the last sph_density
+                                  (two per pass: list kernel, re-scan kernel) */
+    double density_rescan_ms;  /* the re-scan kernel's share of density_kernel_ms */
 } sph_timings;
 
 typedef struct {
@@ -118,6 +121,9 @@ typedef struct {
     int64_t n_pairs;            /* (cell, neighbour cell) entries, self included */
     int64_t sweep_interactions_density; /* pairs inside the trial h, summed over
                                            every Newton evaluation */
+    int64_t rescanned_density;  /* particles whose solve re-tested every candidate
+                                   at each evaluation (unequal masses or a
+                                   neighbour list too long for its slots) */
 } sph_stats;
 
 /* Create a context on HIP device `hip_device`. `params` (host) may be NULL
@@ -212,6 +218,11 @@ const char* sph_last_error(const sph_ctx* ctx);
 
 /* Library version string. */
 const char* sph_version(void);
+
+/* sizeof of the structs above as this library was compiled, for bindings that
+ * lay them out by hand: which = 0 sph_params, 1 sph_stats, 2 sph_timings;
+ * -1 for any other value. */
+int32_t sph_struct_size(int32_t which);
 
 #ifdef __cplusplus
 }

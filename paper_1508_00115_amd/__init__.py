@@ -27,7 +27,7 @@ SPH_E_STATE = 6
 
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
-           "sph_last_error", "sph_version")
+           "sph_last_error", "sph_version", "sph_struct_size")
 
 
 class sph_params(ctypes.Structure):
@@ -44,7 +44,8 @@ class sph_stats(ctypes.Structure):
                 ("unconverged", ctypes.c_int64), ("interactions_density", ctypes.c_int64),
                 ("interactions_force", ctypes.c_int64), ("candidates_density", ctypes.c_int64),
                 ("candidates_force", ctypes.c_int64), ("n_cells", ctypes.c_int64),
-                ("n_pairs", ctypes.c_int64), ("sweep_interactions_density", ctypes.c_int64)]
+                ("n_pairs", ctypes.c_int64), ("sweep_interactions_density", ctypes.c_int64),
+                ("rescanned_density", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -53,7 +54,8 @@ class sph_stats(ctypes.Structure):
 class sph_timings(ctypes.Structure):
     _fields_ = [("density_kernel_ms", ctypes.c_double), ("density_call_ms", ctypes.c_double),
                 ("force_kernel_ms", ctypes.c_double), ("force_call_ms", ctypes.c_double),
-                ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32)]
+                ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32),
+                ("density_rescan_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_last_error.restype = ctypes.c_char_p
     lib.sph_version.argtypes = []
     lib.sph_version.restype = ctypes.c_char_p
+    lib.sph_struct_size.argtypes = [ctypes.c_int32]
+    lib.sph_struct_size.restype = ctypes.c_int32
     _lib = lib
     return lib
 

@@ -92,6 +92,7 @@ sph_status sph_create(const sph_params* params, int hip_device, sph_ctx** out)
         if (c->prm.timing)
             for (auto& e : c->ev) SPH_HIP(hipEventCreate(&e));
         sph::ensure<int64_t>(c, c->counters, CT_COUNT);
+        SPH_HIP(hipHostMalloc((void**)&c->h_counters, CT_COUNT * sizeof(int64_t), hipHostMallocDefault));
     });
     if (st != SPH_OK) {
         g_create_error = c->err;
@@ -115,10 +116,11 @@ void sph_destroy(sph_ctx* c)
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->status,
                        &c->st_s, &c->jf, &c->counters, &c->cons_d, &c->h64, &c->rho64, &c->f64, &c->st64,
-                       &c->m64s, &c->jf64, &c->hf_tmp};
+                       &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
+    if (c->h_counters) hipHostFree(c->h_counters);
     delete c;
 }
 
@@ -224,5 +226,15 @@ const char* sph_last_error(const sph_ctx* c)
 }
 
 const char* sph_version(void) { return "sph-mi355x 0.1 (gfx950)"; }
+
+int32_t sph_struct_size(int32_t which)
+{
+    switch (which) {
+        case 0: return (int32_t)sizeof(sph_params);
+        case 1: return (int32_t)sizeof(sph_stats);
+        case 2: return (int32_t)sizeof(sph_timings);
+        default: return -1;
+    }
+}
 
 }  // extern "C"

@@ -61,8 +61,8 @@ enum {
     CT_QUEUE = 8,        // 8 work-queue heads (one per XCD) start here
     CT_TOTAL = 16,       // scratch for device-computed totals read by the host
     CT_DENS_SWEEP_INTER = 17,  // pairs inside the trial h, summed over every evaluation
-    CT_MASS_MIN = 18,    // smallest / largest mass bit pattern of the density call
-    CT_MASS_MAX = 19,
+    CT_SCAN_CELLS = 18,  // cells queued for the re-scanning density kernel
+    CT_SCAN_POP = 19,    // next queued cell to take
     CT_NEED_SCAN = 20,   // particles left to the re-scanning density kernel
     CT_COUNT = 24
 };
@@ -122,12 +122,11 @@ struct sph_ctx {
     sph::Buf hs, rhos, fs;   // float, sorted
     sph::Buf status;         // uint8, caller order
     sph::Buf st_s;           // uint8, sorted copy of status
+    sph::Buf scan_cells;     // int: leaves holding particles left to the re-scan
     sph::Buf jf;             // 3 float4 per particle for the force loop
     sph::Buf counters;       // int64[CT_COUNT]
     sph::Buf cons_d;         // double, 4 per box
-    int64_t* h_counters = nullptr;  // pinned mirror
-    double* h_cons = nullptr;       // pinned mirror (4 per box)
-    size_t h_cons_cap = 0;
+    int64_t* h_counters = nullptr;  // pinned host mirror of counters
 
     // ---- FP64 plain form --------------------------------------------------------
     sph::Buf h64, rho64, f64, st64;     // sorted state of the FP64 solve
@@ -137,13 +136,13 @@ struct sph_ctx {
 
     // ---- tuning and timing ------------------------------------------------------------
     int n_cu = 256;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[9] = {};
     sph_timings tm{};
 };
 
 // Event pairs of the timing mode.
 enum { EV_DENS_K0 = 0, EV_DENS_K1 = 1, EV_DENS_C0 = 2, EV_DENS_C1 = 3,
-       EV_FORCE_K0 = 4, EV_FORCE_K1 = 5, EV_FORCE_C0 = 6, EV_FORCE_C1 = 7 };
+       EV_FORCE_K0 = 4, EV_FORCE_K1 = 5, EV_FORCE_C0 = 6, EV_FORCE_C1 = 7, EV_DENS_KM = 8 };
 
 inline void ev_record(sph_ctx* c, int k, hipStream_t s)
 {
@@ -226,6 +225,15 @@ inline void free_buf(sph_ctx* c, Buf& b)
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Copy the device counters into the pinned mirror once the stream reaches
+// this point, and wait for them.
+inline const int64_t* read_counters(sph_ctx* c, hipStream_t s)
+{
+    SPH_HIP(hipMemcpyAsync(c->h_counters, c->counters.p, CT_COUNT * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    return c->h_counters;
+}
 
 // ---- host entry points of the other translation units ---------------------------
 
@@ -329,21 +337,6 @@ __device__ __forceinline__ void wave_atomic_max_u32(unsigned* base, int key, uns
         if ((threadIdx.x & 63) == 0 && __any(valid)) atomicMax(&base[k0], m);
     } else if (valid) {
         atomicMax(&base[key], v);
-    }
-}
-
-// Wavefront-reduced atomicMin / atomicMax of 64-bit values.
-__device__ __forceinline__ void wave_atomic_minmax_u64(unsigned long long* lo, unsigned long long* hi,
-                                                       unsigned long long v, bool valid)
-{
-    unsigned long long mn = valid ? v : ~0ull, mx = valid ? v : 0ull;
-    for (int o = 32; o >= 1; o >>= 1) {
-        mn = min(mn, (unsigned long long)__shfl_xor((long long)mn, o, 64));
-        mx = max(mx, (unsigned long long)__shfl_xor((long long)mx, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0 && __any(valid)) {
-        atomicMin(lo, mn);
-        atomicMax(hi, mx);
     }
 }
 

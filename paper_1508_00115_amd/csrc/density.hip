@@ -16,11 +16,15 @@
 //      density sums of a particle depend only on its own h and the fixed
 //      positions, so the whole iteration stays inside the wavefront: no
 //      global sweep and no ghost pass between iterations.
-// Lists are sized for the common case so many wavefronts fit on a CU. A
-// particle whose list does not fit, or any particle when the masses differ,
-// is left to k_density_scan, which re-tests the candidates at every
-// evaluation. A particle whose root lies beyond its search radius is flagged;
-// the host rebuilds the cells around a larger guess and solves it again.
+// Lists hold distances only, so they serve cells whose candidates all share
+// one mass (checked on the staged chunks); they are sized for the common case
+// so many wavefronts fit on a CU. A particle whose list does not fit, or every
+// particle of a cell with mixed masses or more than 64 neighbour cells, is
+// left to k_density_scan: k_density queues such cells, and the re-scanning
+// kernel (launched after it on the same stream, idle when the queue is empty)
+// re-tests their candidates at every evaluation. A particle whose root lies
+// beyond its search radius is flagged; the host rebuilds the cells around a
+// larger guess and solves it again.
 //
 // Lanes: a cell's particles are spread over the 64 lanes, 2 to 16 lanes per
 // particle; the lanes of a particle split the candidates and meet through lane
@@ -38,7 +42,7 @@ constexpr int WAVES = BS / 64;
 constexpr int DCAP = 128;      // candidates per LDS chunk (list kernel)
 constexpr int DSLOTS = 48;     // list entries per lane, plus one spare slot that
                                // takes the stores of misses once a list is full
-constexpr int SCAP = 256;      // candidates per LDS chunk (re-scanning kernel)
+constexpr int SCAP = 512;      // candidates per LDS chunk (re-scanning kernel)
 
 struct DensArgs {
     const float4* jd;        // sorted (x, y, z) in the leaf frame, m
@@ -59,35 +63,38 @@ struct DensArgs {
     float* nw_out;
     uint8_t* status;
     int64_t* ctr;
+    int* scan_cells;         // cells queued for k_density_scan (ctr[CT_SCAN_CELLS] of them)
     WorkSched W;             // which wavefront takes which cell
     float target;            // S0 = sum w(q) at the root: 3 n_ngb / 32
     float tol;               // on |S0 / target - 1|
     int max_iter;
+    int lpi_min;             // fewest lanes per particle: spreads a list over enough slots
 };
 
-__global__ void k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ xrel,
-                                const float* __restrict__ mass, const float* __restrict__ h_in,
-                                const uint8_t* __restrict__ status, float4* __restrict__ jd,
-                                float* __restrict__ hs, uint8_t* __restrict__ st_s, int64_t* __restrict__ ctr)
+__global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm,
+                                                       const float4* __restrict__ xrel,
+                                                       const float* __restrict__ mass,
+                                                       const float* __restrict__ h_in,
+                                                       const uint8_t* __restrict__ status, float4* __restrict__ jd,
+                                                       float* __restrict__ hs, uint8_t* __restrict__ st_s,
+                                                       int64_t* __restrict__ ctr)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = false;
-    float m = 0.0f;
+    bool bad = false;
     if (p < n) {
         const uint32_t o = perm[p];
-        m = mass[o];
+        const float m = mass[o];
         const float h = h_in[o];
         const float4 x = xrel[p];
         jd[p] = make_float4(x.x, x.y, x.z, m);
         hs[p] = h;
         const uint8_t st = status[o];
         st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
-        ok = (m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h);
-        if (!ok) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+        bad = !((m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h));
     }
-    // range of the mass bit patterns (positive floats order like their bits)
-    wave_atomic_minmax_u64((unsigned long long*)&ctr[CT_MASS_MIN], (unsigned long long*)&ctr[CT_MASS_MAX],
-                           (unsigned long long)__float_as_uint(m), ok);
+    // one count per block instead of per-particle atomics on a shared counter
+    const int n_bad = __syncthreads_count(bad);
+    if (threadIdx.x == 0 && n_bad) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], (unsigned long long)n_bad);
 }
 
 // Sorted copies of the final h, rho and f after the cells were rebuilt (the
@@ -220,6 +227,29 @@ __device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_a
     }
 }
 
+// Flag the still-active particles [first, ni) of the cell starting at i0 for
+// the re-scanning kernel; returns how many of them this lane flagged.
+__device__ __forceinline__ int flag_for_scan(const DensArgs& A, int i0, int first, int ni)
+{
+    int n = 0;
+    for (int gi = first + (int)(threadIdx.x & 63); gi < ni; gi += 64) {
+        if (A.st_s[i0 + gi] == ST_ACTIVE) {
+            A.st_s[i0 + gi] = ST_SCAN;
+            ++n;
+        }
+    }
+    return n;
+}
+
+// Queue cell a for the re-scanning kernel when any lane flagged a particle of it.
+__device__ __forceinline__ void enqueue_scan(const DensArgs& A, int a, int n_flag)
+{
+    if (wave_sum_i(n_flag) > 0 && (threadIdx.x & 63) == 0) {
+        const int64_t k = (int64_t)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_CELLS], 1ull);
+        A.scan_cells[k] = a;
+    }
+}
+
 // ---- the list kernel ----------------------------------------------------------------
 
 __global__ void __launch_bounds__(BS) k_density(DensArgs A)
@@ -233,8 +263,6 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0;
     int max_ev = 0;
-    const bool uniform_mass = A.ctr[CT_MASS_MIN] == A.ctr[CT_MASS_MAX];
-    const float m0 = __uint_as_float((unsigned)A.ctr[CT_MASS_MIN]);
 
     for (;;) {
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
@@ -243,22 +271,23 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
         const int ni = A.lf_count[a];
         const int pb0 = (int)A.p_start[a];
         const int np_all = (int)A.p_start[a + 1] - pb0;
-        const Groups G = make_groups(ni);
-        if (!uniform_mass || np_all > 64) {
-            // unequal masses need the mass of every neighbour; very long
-            // neighbour-cell lists take the general staging: both re-scan
-            for (int gi = lane; gi < ni; gi += 64) {
-                if (A.st_s[i0 + gi] == ST_ACTIVE) {
-                    A.st_s[i0 + gi] = ST_SCAN;
-                    ++n_scan;
-                }
-            }
+        const Groups G = make_groups(ni, A.lpi_min);
+        // the cell's own particles are among its candidates: when every
+        // candidate has this mass, so has every particle of the cell
+        const float m0 = ni > 0 ? A.jd[i0].w : 0.0f;
+        int n_flag = 0;  // this lane's particles of the cell left to the re-scan
+        if (np_all > 64) {
+            // very long neighbour-cell lists take the general staging
+            n_flag = flag_for_scan(A, i0, 0, ni);
+            enqueue_scan(A, a, n_flag);
+            n_scan += n_flag;
             continue;
         }
         const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
         const int nj = nb.nj;
         const bool single_tile = nj <= DCAP;
         bool loaded = false;
+        bool mixed = false;  // a candidate with another mass was staged
 
         for (int ib = 0; ib < ni; ib += G.per_pass) {
             const int gi = ib + G.g;
@@ -280,6 +309,7 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                 for (int c0 = 0; c0 < nj; c0 += DCAP) {
                     const int len = min(DCAP, nj - c0);
                     if (stream_chunks) {
+                        mixed |= chunk_mass_differs(R, m0);
                         commit_chunk(sj, R);  // store this chunk, put the next in flight
                         if (c0 + DCAP < nj) fetch_chunk(R, A.jd, nb, c0 + DCAP, min(DCAP, nj - c0 - DCAP));
                         loaded = true;
@@ -303,13 +333,20 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                 }
                 cand_acc += (int64_t)active_groups * nj;
             }
+            if (mixed) {
+                // lists hold no masses: the cell's remaining particles re-scan
+                // (every candidate is staged in the first pass that streams,
+                // and earlier passes had no active particle)
+                n_flag += flag_for_scan(A, i0, ib, ni);
+                break;
+            }
             // a group whose list does not fit goes to the re-scanning kernel
             const bool fits = gsum_i(nl > DSLOTS ? 1 : 0, G) == 0;
             if (!s.done && !fits) {
                 s.done = true;
                 if (G.sub == 0) {
                     A.st_s[i] = ST_SCAN;
-                    ++n_scan;
+                    ++n_flag;
                 }
             }
 
@@ -349,11 +386,16 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
             if (valid && G.sub == 0 && st0 == ST_ACTIVE && fits)
                 write_result(A, i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
         }
+        enqueue_scan(A, a, n_flag);
+        n_scan += n_flag;
     }
     flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
 }
 
 // ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
+// Persistent wavefronts take the queued cells one at a time; a wavefront with
+// no queued cell left exits at once, so the launch costs little when nothing
+// was queued.
 
 __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
 {
@@ -361,22 +403,25 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     float4* sj = tile[wv];
-    int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
     int max_ev = 0;
+    const int n_queued = (int)A.ctr[CT_SCAN_CELLS];  // final: written by the list kernel
+    if ((int)blockIdx.x * WAVES + wv >= n_queued) return;
 
     for (;;) {
-        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
-        const int a = a_cur++;
+        int k = 0;
+        if (lane == 0) k = (int)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_POP], 1ull);
+        k = __shfl(k, 0, 64);
+        if (k >= n_queued) break;
+        const int a = A.scan_cells[k];
         const int i0 = A.lf_start[a];
         const int ni = A.lf_count[a];
         const int pb0 = (int)A.p_start[a];
         const int np_all = (int)A.p_start[a + 1] - pb0;
-        // skip cells without flagged particles
-        int flagged = 0;
-        for (int gi = lane; gi < ni; gi += 64) flagged += A.st_s[i0 + gi] == ST_SCAN ? 1 : 0;
-        if (wave_sum_i(flagged) == 0) continue;
-        const int nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        // up to 64 neighbour cells: one per lane, chunks staged with independent loads
+        const bool few = np_all <= 64;
+        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, min(np_all, 64));
+        const int nj = few ? nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
         const Groups G = make_groups(ni);
         const bool single_tile = nj <= SCAP;
         bool loaded = false;
@@ -399,8 +444,11 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                 for (int c0 = 0; c0 < nj; c0 += SCAP) {
                     const int len = min(SCAP, nj - c0);
                     if (!(single_tile && loaded)) {
-                        stage_tile<1>(sj, A.jd, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0,
-                                      len);
+                        if (few)
+                            stage_fast<1, SCAP>(sj, A.jd, nb, c0, len);
+                        else
+                            stage_tile<1>(sj, A.jd, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0,
+                                          len);
                         loaded = true;
                     }
                     for (int k = G.sub; k < len; k += G.lpi) {
@@ -465,11 +513,12 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     uint8_t* status = ensure<uint8_t>(c, c->status, n);
     SPH_HIP(hipMemsetAsync(status, ST_ACTIVE, (size_t)n, s));
-    int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0;
+    int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;
     int32_t sweeps = 0;
     c->rebuilds = 0;
     c->density_done = false;
     c->tm.density_kernel_ms = 0.0;
+    c->tm.density_rescan_ms = 0.0;
     c->tm.density_launches = 0;
     ev_record(c, EV_DENS_C0, s);
     for (;;) {
@@ -479,7 +528,6 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         float* fs = ensure<float>(c, c->fs, n);
         uint8_t* st_s = ensure<uint8_t>(c, c->st_s, n);
         SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
-        SPH_HIP(hipMemsetAsync(&ctr[CT_MASS_MIN], 0xff, 8, s));
         k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
                                                             static_cast<float4*>(c->xrel.p), mass, h, status, jd,
                                                             hs, st_s, ctr);
@@ -506,33 +554,27 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
         A.tol = (float)c->prm.n_tol;
         A.max_iter = c->prm.max_iter;
+        // a particle with a good guess finds about n_ngb * h_margin^3 candidates
+        // inside its search radius; give its lanes room for 35% more
+        const double expect = c->prm.n_ngb * c->prm.h_margin * c->prm.h_margin * c->prm.h_margin;
+        A.lpi_min = std::min(16, std::max(2, (int)std::ceil(1.35 * expect / DSLOTS)));
+        A.scan_cells = ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
         const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
+        // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
+        const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
         ev_record(c, EV_DENS_K0, s);
         k_density<<<grid, BS, 0, s>>>(A);
         SPH_HIP(hipGetLastError());
+        ev_record(c, EV_DENS_KM, s);
+        k_density_scan<<<scan_grid, BS, 0, s>>>(A);
+        SPH_HIP(hipGetLastError());
         ev_record(c, EV_DENS_K1, s);
-        int64_t hc[CT_COUNT];
-        SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
-        SPH_HIP(hipStreamSynchronize(s));
+        const int64_t* hc = read_counters(c, s);
         c->tm.density_kernel_ms += ev_ms(c, EV_DENS_K0, EV_DENS_K1);
-        c->tm.density_launches += 1;
+        c->tm.density_rescan_ms += ev_ms(c, EV_DENS_KM, EV_DENS_K1);
+        c->tm.density_launches += 2;
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "non-positive or non-finite mass or h");
-        if (hc[CT_NEED_SCAN] > 0) {
-            // particles whose lists did not fit (or unequal masses): re-scan them
-            const int64_t keep[] = {hc[CT_DENS_INTER], hc[CT_DENS_CAND], hc[CT_DENS_SWEEP_INTER],
-                                    hc[CT_OVERFLOW], hc[CT_UNCONV], hc[CT_SWEEPS]};
-            SPH_HIP(hipMemsetAsync(&ctr[CT_QUEUE], 0, 8 * 8, s));
-            make_sched(c, c->n_leaves, WAVES, 12, A.W);
-            ev_record(c, EV_DENS_K0, s);
-            k_density_scan<<<grid, BS, 0, s>>>(A);
-            SPH_HIP(hipGetLastError());
-            ev_record(c, EV_DENS_K1, s);
-            SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
-            SPH_HIP(hipStreamSynchronize(s));
-            c->tm.density_kernel_ms += ev_ms(c, EV_DENS_K0, EV_DENS_K1);
-            c->tm.density_launches += 1;
-            (void)keep;
-        }
+        tot_scan += hc[CT_NEED_SCAN];
         tot_inter += hc[CT_DENS_INTER];
         tot_cand += hc[CT_DENS_CAND];
         tot_sweep_inter += hc[CT_DENS_SWEEP_INTER];
@@ -547,6 +589,7 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
                 st->candidates_density = tot_cand;
                 st->candidates_force = 0;
                 st->sweep_interactions_density = tot_sweep_inter;
+                st->rescanned_density = tot_scan;
                 st->n_cells = c->n_leaves;
                 st->n_pairs = c->n_pairs;
             }

@@ -269,10 +269,8 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     SPH_HIP(hipGetLastError());
     ev_record(c, EV_FORCE_K1, s);
     if (cons || st) {
-        int64_t hc[CT_COUNT];
-        SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
         if (cons) SPH_HIP(hipMemcpyAsync(cons, cons_d, 32 * (size_t)c->n_boxes, hipMemcpyDeviceToHost, s));
-        SPH_HIP(hipStreamSynchronize(s));
+        const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {
             st->interactions_force = hc[CT_FORCE_INTER];

@@ -323,9 +323,7 @@ void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double*
         A.max_iter = std::max(c->prm.max_iter, 100);
         k_density64<<<blocks_for(n, BS), BS, 0, s>>>(A);
         SPH_HIP(hipGetLastError());
-        int64_t hc[CT_COUNT];
-        SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
-        SPH_HIP(hipStreamSynchronize(s));
+        const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "non-positive or non-finite mass or h");
         tot_inter += hc[CT_DENS_INTER];
         tot_cand += hc[CT_DENS_CAND];
@@ -417,10 +415,8 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     k_force64<<<blocks_for(n, BS), BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     if (cons || st) {
-        int64_t hc[CT_COUNT];
-        SPH_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
         if (cons) SPH_HIP(hipMemcpyAsync(cons, cons_d, 32 * (size_t)c->n_boxes, hipMemcpyDeviceToHost, s));
-        SPH_HIP(hipStreamSynchronize(s));
+        const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {
             st->interactions_force = hc[CT_FORCE_INTER];

@@ -89,11 +89,11 @@ struct Groups {
     int lpi, per_pass, g, sub, base;
 };
 
-__device__ __forceinline__ Groups make_groups(int ni)
+__device__ __forceinline__ Groups make_groups(int ni, int lpi_min = 2)
 {
     Groups G;
     const int lane = threadIdx.x & 63;
-    G.lpi = min(16, max(2, 64 / max(ni, 1)));
+    G.lpi = min(16, max(lpi_min, 64 / max(ni, 1)));
     G.per_pass = 64 / G.lpi;
     G.g = lane / G.lpi;
     G.sub = lane - G.g * G.lpi;
@@ -278,6 +278,18 @@ __device__ __forceinline__ void fetch_chunk(ChunkRegs<NF, CAP>& R, const float4*
 #pragma unroll
         for (int f = 0; f < NF; ++f) R.v[r][f] = jd[(int64_t)NF * src + f];
     }
+}
+
+// True on every lane when a candidate of the fetched chunk has a mass other
+// than m.
+template <int NF, int CAP>
+__device__ __forceinline__ bool chunk_mass_differs(const ChunkRegs<NF, CAP>& R, float m)
+{
+    const int lane = threadIdx.x & 63;
+    bool d = false;
+#pragma unroll
+    for (int r = 0; r < CAP / 64; ++r) d |= (lane + 64 * r < R.len) && (R.v[r][0].w != m);
+    return __any(d);
 }
 
 template <int NF, int CAP>

@@ -11,8 +11,13 @@ legal cell layout):
     leaf_target  cells holding more particles than this are split
 
 Each setting is timed on the caller's particles with the library's own HIP
-events (density + force, after a warm-up); the fastest wins. Results can be
-cached in a JSON file keyed by a signature of the particle set.
+events (density + force, after a warm-up); the fastest wins. Results are
+kept in a JSON file keyed by a signature of the particle set; ``tuned.json``
+beside this module holds the results shipped with the library.
+
+    python -m paper_1508_00115_amd.tune --workload sedov --out FILE
+
+re-tunes a named synthetic workload on GPU 0 and merges the result into FILE.
 """
 
 from __future__ import annotations
@@ -32,6 +37,9 @@ DEFAULT_GRID = [
 ]
 
 
+STORE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
 def signature(d: dict) -> str:
     """Key of a particle set: sizes, box layout and summary statistics of h0."""
     h = np.asarray(d["h0"], dtype=np.float64)
@@ -40,7 +48,28 @@ def signature(d: dict) -> str:
     return json.dumps(parts)
 
 
-def autotune(d: dict, device: int = 0, grid=None, reps: int = 3, cache: str | None = None) -> dict:
+def lookup(d: dict, store: str = STORE) -> dict | None:
+    """The stored tuning result of particle set ``d``, or None."""
+    try:
+        with open(store) as fh:
+            return json.load(fh).get(signature(d))
+    except (OSError, ValueError):
+        return None
+
+
+def save(d: dict, result: dict, store: str) -> None:
+    """Merge a tuning result for particle set ``d`` into the JSON file ``store``."""
+    try:
+        with open(store) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        table = {}
+    table[signature(d)] = result
+    with open(store, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+
+
+def autotune(d: dict, device: int = 0, grid=None, reps: int = 5, cache: str | None = None) -> dict:
     """Time every setting of ``grid`` on workload ``d`` (a dict as produced by
     the ``workloads`` package) and return {"best": params, "table": [...]}."""
     import torch
@@ -48,14 +77,10 @@ def autotune(d: dict, device: int = 0, grid=None, reps: int = 3, cache: str | No
     from . import Context
 
     grid = DEFAULT_GRID if grid is None else grid
-    key = signature(d)
-    if cache and os.path.exists(cache):
-        try:
-            store = json.load(open(cache))
-            if key in store:
-                return store[key]
-        except (OSError, ValueError):
-            pass
+    if cache:
+        hit = lookup(d, cache)
+        if hit is not None:
+            return hit
     dev = torch.device("cuda", device)
     pos = torch.from_numpy(d["pos"]).to(dev)
     h0 = torch.from_numpy(d["h0"]).to(dev)
@@ -91,11 +116,29 @@ def autotune(d: dict, device: int = 0, grid=None, reps: int = 3, cache: str | No
     best = min(ok, key=lambda t: t["ms"])
     out = {"best": best["params"], "best_ms": best["ms"], "table": table}
     if cache:
-        try:
-            store = json.load(open(cache)) if os.path.exists(cache) else {}
-        except (OSError, ValueError):
-            store = {}
-        store[key] = out
-        with open(cache, "w") as fh:
-            json.dump(store, fh)
+        save(d, out, cache)
     return out
+
+
+def _main() -> int:
+    import argparse
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import workloads
+
+    ap = argparse.ArgumentParser(description="tune the cell parameters for a synthetic workload")
+    ap.add_argument("--workload", default="sedov")
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    d = workloads.make(args.workload)
+    res = autotune(d, 0)
+    save(d, res, args.out)
+    print(json.dumps({"workload": args.workload, "best": res["best"], "best_ms": res["best_ms"]}))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())

@@ -43,11 +43,12 @@ def test_status_strings_and_version(lib):
     assert "gfx950" in sph.sph_version()
 
 
-def test_struct_layouts_match_header():
-    # sph_params: 4 doubles, int32 (+pad), 2 doubles, int32 (+pad), int64, 3 int32 (+pad)
-    assert ctypes.sizeof(sph.sph_params) == 88
-    assert ctypes.sizeof(sph.sph_stats) == 72
-    assert ctypes.sizeof(sph.sph_timings) == 48
+def test_struct_layouts_match_header(lib):
+    # the ctypes mirrors must have the sizes the C compiler gave the structs
+    for which, mirror in enumerate((sph.sph_params, sph.sph_stats, sph.sph_timings)):
+        assert lib.sph_struct_size(which) == ctypes.sizeof(mirror), mirror.__name__
+    assert lib.sph_struct_size(3) == -1
+    assert ctypes.sizeof(sph.sph_stats) == 80
 
 
 def test_create_rejects_null_out_and_bad_params(lib):

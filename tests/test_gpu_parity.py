@@ -37,10 +37,16 @@ def _case(name):
         return workloads.clustered(n_uniform=1 << 14, n_spheres=4, per_sphere=4096)
     if name == "lognormal40":
         return workloads.lognormal(n_mesh=40, sigma_ln=1.2)
+    if name == "mixed_mass":
+        # masses U(0.5, 1.5) times the mean: every cell takes the re-scanning path
+        d = workloads.lattice_box(16, [1508, 906], jitter=0.3, u=1.0, vel_sigma=0.2)
+        f = np.random.default_rng([1508, 906, 1]).uniform(0.5, 1.5, size=d["mass"].shape[0])
+        d["mass"] = (d["mass"] * f).astype(np.float32)
+        return d
     raise KeyError(name)
 
 
-CASES = ["small", "sedov32", "lattice_vel", "batched8", "clustered_small", "lognormal40"]
+CASES = ["small", "sedov32", "lattice_vel", "batched8", "clustered_small", "lognormal40", "mixed_mass"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -57,6 +63,12 @@ def test_fp32_matches_oracle(gpu_lib, name):
     n_f = int(r["npair"].sum())
     assert abs(g["stats_density"]["interactions_density"] - n_d) <= 1e-5 * n_d + 2
     assert abs(g["stats_force"]["interactions_force"] - n_f) <= 1e-5 * n_f + 2
+    n = d["pos"].shape[0]
+    if name == "mixed_mass":
+        assert g["stats_density"]["rescanned_density"] == n
+    if name == "batched8":
+        # masses differ between boxes only: the distance lists still serve
+        assert g["stats_density"]["rescanned_density"] <= n // 100
     # conservation sums, accumulated in FP64 per box
     for b, (mom, en, mscale, escale) in enumerate(r["cons"]):
         cg = g["cons"][b]
@@ -137,6 +149,9 @@ def test_large_guess(gpu_lib):
     d = workloads.lattice_box(18, [1508, 904], jitter=0.2, u=1.0)
     d["h0"] = (d["h0"] * 1.8).astype(np.float32)
     g = _gpu(gpu_lib, d)
+    # ~6x more candidates inside the search radius than a good guess gives:
+    # the lists overflow and the re-scanning kernel solves those particles
+    assert g["stats_density"]["rescanned_density"] > 0
     r = oracle.run(d)
     assert_within(errors(g, r), TOL32, "large guess")
 
