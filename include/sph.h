@@ -93,6 +93,9 @@ typedef struct {
                              one cell per wavefront, XCD-contiguous blocks;
                              1 = persistent wavefronts popping per-XCD queues */
     int32_t queue_batch;  /* cells per queue pop when schedule = 1 (4) */
+    int32_t tile_cap;     /* candidates of a cell the density kernel keeps in LDS
+                             for all its passes: 128, 256 or 512 (128); a larger
+                             tile means fewer reloads but fewer wavefronts per CU */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP

@@ -27,6 +27,7 @@ sph_params with_defaults(const sph_params* in)
     if (p.workspace_limit < 0) p.workspace_limit = 0;
     if (p.schedule != 1) p.schedule = 0;
     if (p.queue_batch <= 0) p.queue_batch = 4;
+    if (p.tile_cap != 256 && p.tile_cap != 512) p.tile_cap = 128;
     return p;
 }
 
@@ -68,7 +69,8 @@ sph_status sph_create(const sph_params* params, int hip_device, sph_ctx** out)
         if (!std::isfinite(p.n_ngb) || p.n_ngb < 0 || !std::isfinite(p.gamma) || !std::isfinite(p.alpha_visc) ||
             !std::isfinite(p.n_tol) || p.n_tol < 0 || !std::isfinite(p.h_margin) || p.h_margin < 0 ||
             (p.h_margin > 0 && p.h_margin <= 1.0) || !std::isfinite(p.cell_ratio) || p.cell_ratio < 0 ||
-            p.max_iter < 0 || p.leaf_target < 0 || p.workspace_limit < 0 || (p.gamma != 0 && p.gamma <= 1.0)) {
+            p.max_iter < 0 || p.leaf_target < 0 || p.workspace_limit < 0 || (p.gamma != 0 && p.gamma <= 1.0) ||
+            (p.tile_cap != 0 && p.tile_cap != 128 && p.tile_cap != 256 && p.tile_cap != 512)) {
             g_create_error = "invalid sph_params field";
             return SPH_E_ARG;
         }
@@ -116,7 +118,8 @@ void sph_destroy(sph_ctx* c)
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->status,
                        &c->st_s, &c->jf, &c->counters, &c->cons_d, &c->h64, &c->rho64, &c->f64, &c->st64,
-                       &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells};
+                       &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux,
+                       &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);

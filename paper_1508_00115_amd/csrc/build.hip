@@ -385,6 +385,34 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
 }
 
 // Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
+// Cost of each leaf's cell tasks (particles x candidates) as a sort key that
+// orders by decreasing cost (positive floats order like their bit patterns).
+__global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
+                            const int* __restrict__ p_leaf, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nl) return;
+    int nj = 0;
+    for (uint32_t p = p_start[a]; p < p_start[a + 1]; ++p) nj += lf_count[p_leaf[p]];
+    const float cost = (float)lf_count[a] * (float)nj;
+    keys[a] = 0xffffffffull - __float_as_uint(cost);
+    vals[a] = (uint32_t)a;
+}
+
+// Schedule slots: the leaf of cost rank r goes to slot xcd_start(nl, r % 8) + r / 8.
+__global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, const int* __restrict__ lf_start,
+                             const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
+                             const int* __restrict__ lf_node, const int* __restrict__ nd_box, int4* __restrict__ cells,
+                             int2* __restrict__ cell_aux)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nl) return;
+    const int a = (int)by_cost[r];
+    const int64_t slot = sph::xcd_start(nl, (int)(r & 7)) + (r >> 3);
+    cells[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)(p_start[a + 1] - p_start[a]));
+    cell_aux[slot] = make_int2(a, nd_box[lf_node[a]]);
+}
+
 __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ pos_w,
                               const int* __restrict__ leaf_of, const int* __restrict__ lf_node,
                               const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
@@ -625,6 +653,22 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
                                                  nd_child0, nd_child1, top, box_top_base, box_G, box_len,
                                                  p_cnt, p_start, p_leaf, p_shift, p_code, ctr);
     SPH_HIP(hipGetLastError());
+
+    // ---- work schedule: leaves by decreasing cost, dealt out to the XCDs -----------------------------
+    {
+        uint64_t* sk = ensure<uint64_t>(c, c->sched_key, nl);
+        uint64_t* ska = ensure<uint64_t>(c, c->sched_key_alt, nl);
+        uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
+        uint32_t* sva = ensure<uint32_t>(c, c->sched_val_alt, nl);
+        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv);
+        SPH_HIP(hipGetLastError());
+        radix_sort(c, sk, sv, ska, sva, nl, 32, s);
+        int4* cells = ensure<int4>(c, c->cells, nl);
+        int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
+        k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, sv, lf_start, lf_count, p_start, lf_node, nd_box, cells,
+                                                       cell_aux);
+        SPH_HIP(hipGetLastError());
+    }
 
     // ---- sorted particle streams ------------------------------------------------------------------
     double* pos_s = ensure<double>(c, c->pos_s, 3 * n);

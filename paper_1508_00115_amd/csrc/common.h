@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -48,8 +49,11 @@ struct Buf {
 // differ); it is solved by the re-scanning kernel instead.
 enum : uint8_t { ST_ACTIVE = 0, ST_DONE = 1, ST_OVERFLOW = 2, ST_UNCONVERGED = 3, ST_SCAN = 4 };
 
-// Device counters (int64 slots) written by the hot kernels.
+// Device counters (int64 entries) written by the kernels.
 enum {
+    // sums (CT_SWEEPS: a maximum) that every wavefront adds to; the hot
+    // kernels add into a spread slot (ctr_slot) and read_counters folds the
+    // slots into these entries
     CT_DENS_INTER = 0,   // ordered density interactions at the final h
     CT_DENS_CAND = 1,    // candidate pairs tested by all density sweeps
     CT_FORCE_INTER = 2,  // ordered force interactions
@@ -58,14 +62,55 @@ enum {
     CT_OVERFLOW = 5,     // particles whose root lies beyond their search radius
     CT_UNCONV = 6,       // particles that hit max_iter
     CT_BAD_INPUT = 7,    // non-finite or non-positive inputs seen by a kernel
-    CT_QUEUE = 8,        // 8 work-queue heads (one per XCD) start here
+    CT_DENS_SWEEP_INTER = 8,  // pairs inside the trial h, summed over every evaluation
+    CT_NEED_SCAN = 9,    // particles left to the re-scanning density kernel
+    CT_SUMS = 16,        // entries [0, CT_SUMS) have spread slots
+    // single entries
     CT_TOTAL = 16,       // scratch for device-computed totals read by the host
-    CT_DENS_SWEEP_INTER = 17,  // pairs inside the trial h, summed over every evaluation
-    CT_SCAN_CELLS = 18,  // cells queued for the re-scanning density kernel
-    CT_SCAN_POP = 19,    // next queued cell to take
-    CT_NEED_SCAN = 20,   // particles left to the re-scanning density kernel
-    CT_COUNT = 24
+    CT_SCAN_CELLS = 17,  // cells queued for the re-scanning density kernel
+    CT_SCAN_POP = 18,    // next queued cell to take
+    CT_QUEUE = 32,       // 8 work-queue heads (one per XCD), one 64-byte line each: CT_QUEUE + 8 q
+    CT_SPREAD = 96,      // CT_SPREAD_SLOTS copies of the sums, CT_SUMS entries each
+    CT_SPREAD_SLOTS = 64,
+    CT_COUNT = CT_SPREAD + CT_SPREAD_SLOTS * CT_SUMS
 };
+
+// Spread slot of this workgroup's sums. Atomics on one address serialise at
+// the L2 (about 10 ns each): a single counter that every wavefront of a
+// launch adds to costs 0.1 to 1 ms, 64 copies on separate cache lines do not.
+__device__ inline int64_t* ctr_slot(int64_t* ctr)
+{
+    return ctr + CT_SPREAD + (int64_t)(blockIdx.x % CT_SPREAD_SLOTS) * CT_SUMS;
+}
+
+// Add v (the same on every lane) to sum k once per wavefront.
+__device__ inline void ctr_add_uniform(int64_t* ctr, int k, int64_t v)
+{
+    if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long*)&ctr_slot(ctr)[k], (unsigned long long)v);
+}
+
+// Sum v over the 64 lanes of the wavefront (all active) and add it to sum k.
+__device__ inline void ctr_wave_add(int64_t* ctr, int k, int64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    ctr_add_uniform(ctr, k, v);
+}
+
+// Per-box conservation sums (4 doubles per box) are kept in CONS_SLOTS copies,
+// picked by workgroup, for the same reason as the counters' spread slots.
+constexpr int CONS_SLOTS = 16;
+
+__device__ inline double* cons_slot(double* cons, int n_boxes)
+{
+    return cons + (int64_t)(blockIdx.x % CONS_SLOTS) * 4 * n_boxes;
+}
+
+// Raise CT_SWEEPS to the largest v of the wavefront (all lanes active).
+__device__ inline void ctr_wave_max_sweeps(int64_t* ctr, int64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, (int64_t)__shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctr_slot(ctr)[CT_SWEEPS], (unsigned long long)v);
+}
 
 struct sph_ctx {
     sph_params prm{};
@@ -114,6 +159,10 @@ struct sph_ctx {
     sph::Buf p_leaf;         // int
     sph::Buf p_shift;        // float4 (dx, dy, dz, 0): leaf-centre frame offset
     sph::Buf p_code;         // int: periodic image code (3 x 2 bits)
+    // work schedule of the hot kernels (one slot per leaf, see xcd_start)
+    sph::Buf cells;          // int4 per slot: first particle, count, first neighbour entry, neighbour entries
+    sph::Buf cell_aux;       // int2 per slot: leaf index, box
+    sph::Buf sched_key, sched_key_alt, sched_val, sched_val_alt;  // cost sort
     sph::Buf scan_tmp;       // scan workspace
     sph::Buf sort_hist;      // radix-sort histograms
 
@@ -226,13 +275,44 @@ inline void free_buf(sph_ctx* c, Buf& b)
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// First schedule slot of XCD x when n slots are dealt out to the 8 XCDs:
+// XCD x owns n / 8 slots, plus one if x < n % 8. Cells are ranked by
+// decreasing cost and rank r goes to slot xcd_start(n, r % 8) + r / 8, so
+// every XCD owns a cost-descending run and the runs are equally loaded. A
+// hardware-dispatched workgroup b lands on XCD b % 8 and (after the remap
+// of xcd_block_index) takes slot xcd_start(n, b % 8) + b / 8: rank b. The
+// persistent queues use the same runs.
+__host__ __device__ inline int64_t xcd_start(int64_t n, int x)
+{
+    return (int64_t)x * (n / 8) + (x < n % 8 ? x : n % 8);
+}
+
+// Sum the copies of the conservation sums (device, CONS_SLOTS x 4 x n_boxes)
+// into out (host, 4 x n_boxes) once the stream reaches this point.
+inline void read_cons(const double* cons_d, double* out, int n_boxes, hipStream_t s)
+{
+    std::vector<double> h((size_t)CONS_SLOTS * 4 * n_boxes);
+    SPH_HIP(hipMemcpyAsync(h.data(), cons_d, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 4 * n_boxes; ++k) {
+        double v = 0.0;
+        for (int sl = 0; sl < CONS_SLOTS; ++sl) v += h[(size_t)sl * 4 * n_boxes + k];
+        out[k] = v;
+    }
+}
+
 // Copy the device counters into the pinned mirror once the stream reaches
-// this point, and wait for them.
+// this point, wait for them and fold the spread slots into the sums.
 inline const int64_t* read_counters(sph_ctx* c, hipStream_t s)
 {
     SPH_HIP(hipMemcpyAsync(c->h_counters, c->counters.p, CT_COUNT * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
-    return c->h_counters;
+    int64_t* h = c->h_counters;
+    for (int sl = 0; sl < CT_SPREAD_SLOTS; ++sl) {
+        const int64_t* p = h + CT_SPREAD + sl * CT_SUMS;
+        for (int k = 0; k < CT_SUMS; ++k) h[k] = k == CT_SWEEPS ? std::max(h[k], p[k]) : h[k] + p[k];
+    }
+    return h;
 }
 
 // ---- host entry points of the other translation units ---------------------------

@@ -39,9 +39,11 @@ namespace {
 
 constexpr int BS = 64;         // one wavefront per block (finest LDS allocation)
 constexpr int WAVES = BS / 64;
-constexpr int DCAP = 128;      // candidates per LDS chunk (list kernel)
-constexpr int DSLOTS = 48;     // list entries per lane, plus one spare slot that
+constexpr int DCH = 128;       // candidates per staged chunk (list kernel)
+constexpr int DSLOTS = 30;     // list entries per lane, plus one spare slot that
                                // takes the stores of misses once a list is full
+                               // (with a 128-candidate tile: < 10 KB of LDS per
+                               // wavefront, 16 wavefronts per CU)
 constexpr int SCAP = 512;      // candidates per LDS chunk (re-scanning kernel)
 
 struct DensArgs {
@@ -51,9 +53,9 @@ struct DensArgs {
     float* rhos;
     float* fs;
     uint8_t* st_s;           // sorted state
+    const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, entries
     const int* lf_start;
     const int* lf_count;
-    const uint32_t* p_start;
     const int* p_leaf;
     const float4* p_shift;
     const uint32_t* perm;
@@ -63,12 +65,13 @@ struct DensArgs {
     float* nw_out;
     uint8_t* status;
     int64_t* ctr;
-    int* scan_cells;         // cells queued for k_density_scan (ctr[CT_SCAN_CELLS] of them)
+    int* scan_cells;         // schedule slots queued for k_density_scan (ctr[CT_SCAN_CELLS] of them)
     WorkSched W;             // which wavefront takes which cell
     float target;            // S0 = sum w(q) at the root: 3 n_ngb / 32
     float tol;               // on |S0 / target - 1|
     int max_iter;
-    int lpi_min;             // fewest lanes per particle: spreads a list over enough slots
+    int lpi_min;             // fewest lanes per particle (a power of two): spreads a list over enough slots
+    float nl_est;            // expected list length of a particle: n_ngb * h_margin^3
 };
 
 __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm,
@@ -94,7 +97,7 @@ __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t
     }
     // one count per block instead of per-particle atomics on a shared counter
     const int n_bad = __syncthreads_count(bad);
-    if (threadIdx.x == 0 && n_bad) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], (unsigned long long)n_bad);
+    if (threadIdx.x == 0 && n_bad) atomicAdd((unsigned long long*)&ctr_slot(ctr)[CT_BAD_INPUT], (unsigned long long)n_bad);
 }
 
 // Sorted copies of the final h, rho and f after the cells were rebuilt (the
@@ -175,19 +178,21 @@ __device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float
 }
 
 // Outputs of one particle at its final h (sums M0 = sum m w, M1 = sum m q w').
+template <class I>
 __device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSolve& s, float S0, float M0,
-                                             float M1, int cnt, int64_t& inter_acc, int64_t& n_over,
-                                             int64_t& n_unconv, int& max_ev)
+                                             float M1, int cnt, I& inter_acc, I& n_over, I& n_unconv,
+                                             int& max_ev)
 {
     const uint32_t o = A.perm[i];
     float h_report = s.h;
     if (s.state == ST_OVERFLOW) {
         // propose the radius at which a uniform density would hold the target
         h_report = s.h * fmaxf(cbrtf(A.target / S0), 1.0f) * 1.05f;
-        ++n_over;
-    } else if (s.state == ST_UNCONVERGED) {
-        ++n_unconv;
     }
+    // (selects, not branches: a branch here makes the compiler keep the two
+    // counters in a scratch array behind a pointer select)
+    n_over += s.state == ST_OVERFLOW ? 1 : 0;
+    n_unconv += s.state == ST_UNCONVERGED ? 1 : 0;
     const float hinv = 1.0f / s.h;
     const float rho = (8.0f / SPH_PI_F) * M0 * hinv * hinv * hinv;
     const float f = M1 < 0.0f ? -3.0f * M0 / M1 : 1.0f;
@@ -208,23 +213,13 @@ __device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_a
                                                int64_t sweep_acc, int64_t n_over, int64_t n_unconv, int max_ev,
                                                int64_t n_scan)
 {
-    for (int o = 32; o >= 1; o >>= 1) {
-        inter_acc += __shfl_xor(inter_acc, o, 64);
-        sweep_acc += __shfl_xor(sweep_acc, o, 64);
-        n_over += __shfl_xor(n_over, o, 64);
-        n_unconv += __shfl_xor(n_unconv, o, 64);
-        n_scan += __shfl_xor(n_scan, o, 64);
-        max_ev = max(max_ev, __shfl_xor(max_ev, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_INTER], (unsigned long long)inter_acc);
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_CAND], (unsigned long long)cand_acc);
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_SWEEP_INTER], (unsigned long long)sweep_acc);
-        if (n_over) atomicAdd((unsigned long long*)&A.ctr[CT_OVERFLOW], (unsigned long long)n_over);
-        if (n_unconv) atomicAdd((unsigned long long*)&A.ctr[CT_UNCONV], (unsigned long long)n_unconv);
-        if (n_scan) atomicAdd((unsigned long long*)&A.ctr[CT_NEED_SCAN], (unsigned long long)n_scan);
-        atomicMax((unsigned long long*)&A.ctr[CT_SWEEPS], (unsigned long long)max_ev);
-    }
+    ctr_add_uniform(A.ctr, CT_DENS_CAND, cand_acc);  // already a wavefront total
+    ctr_wave_add(A.ctr, CT_DENS_INTER, inter_acc);
+    ctr_wave_add(A.ctr, CT_DENS_SWEEP_INTER, sweep_acc);
+    ctr_wave_add(A.ctr, CT_OVERFLOW, n_over);
+    ctr_wave_add(A.ctr, CT_UNCONV, n_unconv);
+    ctr_wave_add(A.ctr, CT_NEED_SCAN, n_scan);
+    ctr_wave_max_sweeps(A.ctr, max_ev);
 }
 
 // Flag the still-active particles [first, ni) of the cell starting at i0 for
@@ -241,37 +236,66 @@ __device__ __forceinline__ int flag_for_scan(const DensArgs& A, int i0, int firs
     return n;
 }
 
-// Queue cell a for the re-scanning kernel when any lane flagged a particle of it.
-__device__ __forceinline__ void enqueue_scan(const DensArgs& A, int a, int n_flag)
+// Queue schedule slot `slot` for the re-scanning kernel when any lane flagged
+// a particle of its cell.
+__device__ __forceinline__ void enqueue_scan(const DensArgs& A, int slot, int n_flag)
 {
     if (wave_sum_i(n_flag) > 0 && (threadIdx.x & 63) == 0) {
         const int64_t k = (int64_t)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_CELLS], 1ull);
-        A.scan_cells[k] = a;
+        A.scan_cells[k] = slot;
     }
 }
 
 // ---- the list kernel ----------------------------------------------------------------
 
-__global__ void __launch_bounds__(BS) k_density(DensArgs A)
+// Lanes per particle for a cell of ni particles and nj candidates: the power
+// of two (at least lpi_min) that minimises passes x (candidate tests, list
+// work and fixed work of a pass, per lane), plus the re-staging of every pass
+// when the candidates cannot stay resident in LDS. The weights are the VALU
+// costs of a candidate test (1), of a list entry over ~3 Newton evaluations
+// (~5) and of a pass (~25).
+__device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float nl_est, bool resident)
 {
-    __shared__ float4 tile[WAVES][DCAP];
-    __shared__ float lists[WAVES][(DSLOTS + 1) * 64];
+    const int nchunks = (nj + DCH - 1) / DCH;
+    int best = 16;
+    float best_cost = 3.0e38f;
+    for (int l = lpi_min; l <= 16; l <<= 1) {
+        const int per = 64 / l;
+        const float passes = (float)((ni + per - 1) / per);
+        float cost = passes * (((float)nj + 5.0f * nl_est) / (float)l + 25.0f);
+        if (!resident) cost += passes * (float)nchunks * 20.0f;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = l;
+        }
+    }
+    return best;
+}
+
+// One wavefront per cell. TCAP: candidates the LDS tile holds; a cell with at
+// most TCAP candidates stages them once and keeps them for all its passes,
+// a larger one streams them through the first DCH slots in every pass.
+// At most 128 VGPRs: four wavefronts per SIMD (the kernel waits on memory
+// more than it computes, so resident wavefronts matter more than registers).
+template <int TCAP>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_density(DensArgs A)
+{
+    __shared__ float4 tile[TCAP];
+    __shared__ float lists[(DSLOTS + 1) * 64];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    float4* sj = tile[wv];
-    float* lst = lists[wv] + lane;
+    float4* sj = tile;
+    float* lst = lists + lane;
     int wstate = 0, a_cur = 0, a_end = 0;
-    int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0;
+    int64_t cand_acc = 0;  // wave-uniform
+    // per-lane counts (far below 2^31 for any particle count that fits a GPU)
+    int inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0;
     int max_ev = 0;
 
     for (;;) {
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
-        const int a = a_cur++;
-        const int i0 = A.lf_start[a];
-        const int ni = A.lf_count[a];
-        const int pb0 = (int)A.p_start[a];
-        const int np_all = (int)A.p_start[a + 1] - pb0;
-        const Groups G = make_groups(ni, A.lpi_min);
+        const int slot = a_cur++;
+        const int4 ci = A.cells[slot];
+        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         // the cell's own particles are among its candidates: when every
         // candidate has this mass, so has every particle of the cell
         const float m0 = ni > 0 ? A.jd[i0].w : 0.0f;
@@ -279,58 +303,64 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
         if (np_all > 64) {
             // very long neighbour-cell lists take the general staging
             n_flag = flag_for_scan(A, i0, 0, ni);
-            enqueue_scan(A, a, n_flag);
+            enqueue_scan(A, slot, n_flag);
             n_scan += n_flag;
             continue;
         }
         const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
         const int nj = nb.nj;
-        const bool single_tile = nj <= DCAP;
-        bool loaded = false;
-        bool mixed = false;  // a candidate with another mass was staged
+        const bool resident = nj <= TCAP;
+        const int lpi = choose_lpi(ni, nj, A.lpi_min, A.nl_est, resident);
+        const int per_pass = 64 / lpi;
+        const int g = lane / lpi;
+        const int sub = lane & (lpi - 1);
+        bool loaded = false;  // (resident) every candidate is in the tile
+        bool mixed = false;   // a candidate with another mass was staged
 
-        for (int ib = 0; ib < ni; ib += G.per_pass) {
-            const int gi = ib + G.g;
-            const bool valid = G.g < G.per_pass && gi < ni;
+        for (int ib = 0; ib < ni; ib += per_pass) {
+            const int gi = ib + g;
+            const bool valid = gi < ni;
             const int i = i0 + (valid ? gi : 0);
             const float4 xi = A.jd[i];
             const uint8_t st0 = A.st_s[i];
             HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_ACTIVE, st0);
-            const int active_groups = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
+            const int active_groups = wave_sum_i((!s.done && sub == 0) ? 1 : 0);
             if (active_groups == 0) continue;
 
             // ---- phase A: squared distances inside the search radius -----------
             int nl = 0;
             {
                 const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
-                ChunkRegs<1, DCAP> R;
-                const bool stream_chunks = !(single_tile && loaded);
-                if (stream_chunks) fetch_chunk(R, A.jd, nb, 0, min(DCAP, nj));
-                for (int c0 = 0; c0 < nj; c0 += DCAP) {
-                    const int len = min(DCAP, nj - c0);
-                    if (stream_chunks) {
+                const bool stream = !(resident && loaded);
+                ChunkRegs<1, DCH> R;
+                if (stream) fetch_chunk(R, A.jd, nb, 0, min(DCH, nj));
+                for (int c0 = 0; c0 < nj; c0 += DCH) {
+                    const int len = min(DCH, nj - c0);
+                    const float4* tc = resident ? sj + c0 : sj;
+                    if (stream) {
                         mixed |= chunk_mass_differs(R, m0);
-                        commit_chunk(sj, R);  // store this chunk, put the next in flight
-                        if (c0 + DCAP < nj) fetch_chunk(R, A.jd, nb, c0 + DCAP, min(DCAP, nj - c0 - DCAP));
-                        loaded = true;
+                        commit_chunk(sj + (resident ? c0 : 0), R);  // store this chunk, put the next in flight
+                        if (c0 + DCH < nj) fetch_chunk(R, A.jd, nb, c0 + DCH, min(DCH, nj - c0 - DCH));
                     }
-                    // four tile reads in flight, then branch-free appends: the
-                    // store always happens, the slot only advances on a hit
-                    for (int k0 = G.sub; k0 < len; k0 += 4 * G.lpi) {
-                        float4 pj[4];
+                    // four tile reads (x, y, z only) in flight, then branch-free
+                    // appends: the store always happens, the slot only advances on a hit
+                    for (int k0 = sub; k0 < len; k0 += 4 * lpi) {
+                        float3 pj[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) pj[u] = sj[min(k0 + u * G.lpi, len - 1)];
+                        for (int u = 0; u < 4; ++u)
+                            pj[u] = *reinterpret_cast<const float3*>(tc + min(k0 + u * lpi, len - 1));
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const float dx = xi.x - pj[u].x, dy = xi.y - pj[u].y, dz = xi.z - pj[u].z;
                             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            const bool in = (r2 < H2) & (k0 + u * G.lpi < len);
+                            const bool in = (r2 < H2) & (k0 + u * lpi < len);
                             lst[min(nl, DSLOTS) * 64] = r2;
                             nl += in ? 1 : 0;
                         }
                     }
-                    if (!single_tile) wave_sync_lds();
+                    if (!resident) wave_sync_lds();
                 }
+                loaded = true;
                 cand_acc += (int64_t)active_groups * nj;
             }
             if (mixed) {
@@ -341,10 +371,10 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                 break;
             }
             // a group whose list does not fit goes to the re-scanning kernel
-            const bool fits = gsum_i(nl > DSLOTS ? 1 : 0, G) == 0;
+            const bool fits = group_sum_i(nl > DSLOTS ? 1 : 0, lpi) == 0;
             if (!s.done && !fits) {
                 s.done = true;
-                if (G.sub == 0) {
+                if (sub == 0) {
                     A.st_s[i] = ST_SCAN;
                     ++n_flag;
                 }
@@ -361,7 +391,7 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                 S0 = S1 = 0.f;
                 cnt = 0;
                 const int len_l = s.done ? 0 : nl;
-#pragma unroll 4
+#pragma unroll 2
                 for (int e = 0; e < len_l; ++e) {
                     const float r2 = lst[e * 64];
                     const bool in = r2 < h2;
@@ -373,20 +403,20 @@ __global__ void __launch_bounds__(BS) k_density(DensArgs A)
                     cnt += in ? 1 : 0;
                 }
                 cand_acc += wave_sum_i(len_l);
-                S0 = gsum(S0, G);
-                S1 = gsum(S1, G);
-                cnt = gsum_i(cnt, G);
+                S0 = group_sum(S0, lpi);
+                S1 = group_sum(S1, lpi);
+                cnt = group_sum_i(cnt, lpi);
                 if (s.done) continue;
-                if (G.sub == 0) sweep_acc += cnt;
+                if (sub == 0) sweep_acc += cnt;
                 fS0 = S0;
                 fS1 = S1;
                 fcnt = cnt;
                 hsolve_step(s, S0, S1, A.target, A.tol, A.max_iter);
             }
-            if (valid && G.sub == 0 && st0 == ST_ACTIVE && fits)
+            if (valid && sub == 0 && st0 == ST_ACTIVE && fits)
                 write_result(A, i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
         }
-        enqueue_scan(A, a, n_flag);
+        enqueue_scan(A, slot, n_flag);
         n_scan += n_flag;
     }
     flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
@@ -413,11 +443,8 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         if (lane == 0) k = (int)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_POP], 1ull);
         k = __shfl(k, 0, 64);
         if (k >= n_queued) break;
-        const int a = A.scan_cells[k];
-        const int i0 = A.lf_start[a];
-        const int ni = A.lf_count[a];
-        const int pb0 = (int)A.p_start[a];
-        const int np_all = (int)A.p_start[a + 1] - pb0;
+        const int4 ci = A.cells[A.scan_cells[k]];
+        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         // up to 64 neighbour cells: one per lane, chunks staged with independent loads
         const bool few = np_all <= 64;
         const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, min(np_all, 64));
@@ -497,7 +524,7 @@ int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_
     W.persistent = c->prm.schedule == 1 ? 1 : 0;
     W.batch = c->prm.queue_batch > 0 ? c->prm.queue_batch : 4;
     W.n_items = (int)n_items;
-    for (int q = 0; q <= 8; ++q) W.q_begin[q] = (int)((n_items * q) / 8);
+    for (int q = 0; q <= 8; ++q) W.q_begin[q] = (int)xcd_start(n_items, q);
     const int64_t all = (n_items + waves_per_block - 1) / waves_per_block;
     int64_t grid = all;
     if (W.persistent) grid = std::min<int64_t>(all, (int64_t)c->n_cu * blocks_per_cu);
@@ -527,7 +554,7 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         float* rhos = ensure<float>(c, c->rhos, n);
         float* fs = ensure<float>(c, c->fs, n);
         uint8_t* st_s = ensure<uint8_t>(c, c->st_s, n);
-        SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
+        SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));  // sums, spread slots, queue heads
         k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
                                                             static_cast<float4*>(c->xrel.p), mass, h, status, jd,
                                                             hs, st_s, ctr);
@@ -539,9 +566,9 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         A.rhos = rhos;
         A.fs = fs;
         A.st_s = st_s;
+        A.cells = static_cast<int4*>(c->cells.p);
         A.lf_start = static_cast<int*>(c->lf_start.p);
         A.lf_count = static_cast<int*>(c->lf_count.p);
-        A.p_start = static_cast<uint32_t*>(c->p_start.p);
         A.p_leaf = static_cast<int*>(c->p_leaf.p);
         A.p_shift = static_cast<float4*>(c->p_shift.p);
         A.perm = static_cast<uint32_t*>(c->perm.p);
@@ -555,15 +582,23 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         A.tol = (float)c->prm.n_tol;
         A.max_iter = c->prm.max_iter;
         // a particle with a good guess finds about n_ngb * h_margin^3 candidates
-        // inside its search radius; give its lanes room for 35% more
+        // inside its search radius; a lane takes every lpi-th candidate, so
+        // give the lanes room for 70% more than their share
         const double expect = c->prm.n_ngb * c->prm.h_margin * c->prm.h_margin * c->prm.h_margin;
-        A.lpi_min = std::min(16, std::max(2, (int)std::ceil(1.35 * expect / DSLOTS)));
+        A.nl_est = (float)expect;
+        A.lpi_min = 2;
+        while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
         A.scan_cells = ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
         const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
         // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
         const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
         ev_record(c, EV_DENS_K0, s);
-        k_density<<<grid, BS, 0, s>>>(A);
+        if (c->prm.tile_cap == 512)
+            k_density<512><<<grid, BS, 0, s>>>(A);
+        else if (c->prm.tile_cap == 256)
+            k_density<256><<<grid, BS, 0, s>>>(A);
+        else
+            k_density<128><<<grid, BS, 0, s>>>(A);
         SPH_HIP(hipGetLastError());
         ev_record(c, EV_DENS_KM, s);
         k_density_scan<<<scan_grid, BS, 0, s>>>(A);

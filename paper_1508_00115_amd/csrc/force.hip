@@ -48,17 +48,17 @@ __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, c
 
 struct ForceArgs {
     const float4* jf;
+    const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
+    const int2* cell_aux;  // per schedule slot: leaf, box
     const int* lf_start;
     const int* lf_count;
-    const int* lf_node;
-    const int* nd_box;
-    const uint32_t* p_start;
     const int* p_leaf;
     const float4* p_shift;
     const uint32_t* perm;
     float* acc;
     float* dudt;
-    double* cons;  // 4 per box, may be null
+    double* cons;  // CONS_SLOTS copies of 4 per box, may be null
+    int n_boxes;
     int64_t* ctr;
     WorkSched W;
     float alpha;
@@ -78,11 +78,9 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
 
     for (;;) {
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
-        const int a = a_cur++;
-        const int i0 = A.lf_start[a];
-        const int ni = A.lf_count[a];
-        const int pb0 = (int)A.p_start[a];
-        const int np_all = (int)A.p_start[a + 1] - pb0;
+        const int slot = a_cur++;
+        const int4 ci = A.cells[slot];
+        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         const bool fastnb = np_all <= 64;
         NbrLanes nb;
         int nj;
@@ -208,18 +206,15 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                 for (int k = 0; k < 4; ++k)
                     for (int o = 32; o >= 1; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
                 if (lane == 0) {
-                    const int b = A.nd_box[A.lf_node[a]];
+                    const int b = A.cell_aux[slot].y;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) atomicAdd(&A.cons[4 * b + k], cm[k]);
+                    for (int k = 0; k < 4; ++k) atomicAdd(&cons_slot(A.cons, A.n_boxes)[4 * b + k], cm[k]);
                 }
             }
         }
     }
-    for (int o = 32; o >= 1; o >>= 1) inter_acc += __shfl_xor(inter_acc, o, 64);
-    if (lane == 0) {
-        atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_INTER], (unsigned long long)inter_acc);
-        atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_CAND], (unsigned long long)cand_acc);
-    }
+    ctr_wave_add(A.ctr, CT_FORCE_INTER, inter_acc);
+    ctr_add_uniform(A.ctr, CT_FORCE_CAND, cand_acc);  // already a wavefront total
 }
 
 }  // namespace
@@ -238,8 +233,8 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     float4* jf = ensure<float4>(c, c->jf, 3 * n);
     double* cons_d = nullptr;
     if (cons) {
-        cons_d = ensure<double>(c, c->cons_d, 4 * (size_t)c->n_boxes);
-        SPH_HIP(hipMemsetAsync(cons_d, 0, 32 * (size_t)c->n_boxes, s));
+        cons_d = ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes);
+        SPH_HIP(hipMemsetAsync(cons_d, 0, (size_t)CONS_SLOTS * 32 * c->n_boxes, s));
     }
     ev_record(c, EV_FORCE_C0, s);
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
@@ -250,17 +245,17 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     SPH_HIP(hipGetLastError());
     ForceArgs A;
     A.jf = jf;
+    A.cells = static_cast<int4*>(c->cells.p);
+    A.cell_aux = static_cast<int2*>(c->cell_aux.p);
     A.lf_start = static_cast<int*>(c->lf_start.p);
     A.lf_count = static_cast<int*>(c->lf_count.p);
-    A.lf_node = static_cast<int*>(c->lf_node.p);
-    A.nd_box = static_cast<int*>(c->nd_box.p);
-    A.p_start = static_cast<uint32_t*>(c->p_start.p);
     A.p_leaf = static_cast<int*>(c->p_leaf.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.perm = static_cast<uint32_t*>(c->perm.p);
     A.acc = acc;
     A.dudt = dudt;
     A.cons = cons_d;
+    A.n_boxes = c->n_boxes;
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 4, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
@@ -269,7 +264,7 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     SPH_HIP(hipGetLastError());
     ev_record(c, EV_FORCE_K1, s);
     if (cons || st) {
-        if (cons) SPH_HIP(hipMemcpyAsync(cons, cons_d, 32 * (size_t)c->n_boxes, hipMemcpyDeviceToHost, s));
+        if (cons) read_cons(cons_d, cons, c->n_boxes, s);
         const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {

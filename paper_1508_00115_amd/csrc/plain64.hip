@@ -60,10 +60,13 @@ __global__ void k_d64_prologue(int64_t n, const uint32_t* __restrict__ perm, con
         atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
 }
 
-__global__ void __launch_bounds__(BS) k_density64(D64Args A)
+// Counts of one particle's solve, summed per wavefront by the kernel.
+struct D64Count {
+    int64_t inter = 0, cand = 0, over = 0, unconv = 0, nev = 0;
+};
+
+__device__ __forceinline__ void density64_one(const D64Args& A, int64_t i, D64Count& ct)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n || A.st_s[i] != ST_ACTIVE) return;
     const int a = A.leaf_of[i];
     const double L = A.box_len[A.nd_box[A.lf_node[a]]];
     const double xi = A.pos_s[3 * i], yi = A.pos_s[3 * i + 1], zi = A.pos_s[3 * i + 2];
@@ -121,16 +124,12 @@ __global__ void __launch_bounds__(BS) k_density64(D64Args A)
     }
     const uint32_t o = A.perm[i];
     double h_report = h;
-    if (state == ST_OVERFLOW) {
-        h_report = h * fmax(cbrt(A.target / S0), 1.0) * 1.05;
-        atomicAdd((unsigned long long*)&A.ctr[CT_OVERFLOW], 1ull);
-    } else if (state == ST_UNCONVERGED) {
-        atomicAdd((unsigned long long*)&A.ctr[CT_UNCONV], 1ull);
-    } else {
-        atomicAdd((unsigned long long*)&A.ctr[CT_DENS_INTER], (unsigned long long)(cnt - 1));
-    }
-    atomicAdd((unsigned long long*)&A.ctr[CT_DENS_CAND], (unsigned long long)cand);
-    atomicMax((unsigned long long*)&A.ctr[CT_SWEEPS], (unsigned long long)nev);
+    if (state == ST_OVERFLOW) h_report = h * fmax(cbrt(A.target / S0), 1.0) * 1.05;
+    ct.over = state == ST_OVERFLOW ? 1 : 0;
+    ct.unconv = state == ST_UNCONVERGED ? 1 : 0;
+    ct.inter = state == ST_DONE ? cnt - 1 : 0;
+    ct.cand = cand;
+    ct.nev = nev;
     const double rho = 8.0 / (SPH_PI_D * h * h * h) * M0;
     const double f = M1 < 0.0 ? -3.0 * M0 / M1 : 1.0;
     A.hs[i] = h;
@@ -142,6 +141,19 @@ __global__ void __launch_bounds__(BS) k_density64(D64Args A)
     A.f_out[o] = f;
     if (A.nw_out) A.nw_out[o] = 32.0 / 3.0 * S0;
     A.status[o] = state;
+}
+
+// One thread per particle; the counts go to the counters once per wavefront.
+__global__ void __launch_bounds__(BS) k_density64(D64Args A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    D64Count ct;
+    if (i < A.n && A.st_s[i] == ST_ACTIVE) density64_one(A, i, ct);
+    ctr_wave_add(A.ctr, CT_DENS_INTER, ct.inter);
+    ctr_wave_add(A.ctr, CT_DENS_CAND, ct.cand);
+    ctr_wave_add(A.ctr, CT_OVERFLOW, ct.over);
+    ctr_wave_add(A.ctr, CT_UNCONV, ct.unconv);
+    ctr_wave_max_sweeps(A.ctr, ct.nev);
 }
 
 __global__ void k_d64_regather(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ h,
@@ -198,16 +210,22 @@ struct F64Args {
     const uint32_t* perm;
     double* acc;
     double* dudt;
-    double* cons;
+    double* cons;  // CONS_SLOTS copies of 4 per box, may be null
     int64_t* ctr;
     int64_t n;
     double alpha;
+    int n_boxes;
 };
 
-__global__ void __launch_bounds__(BS) k_force64(F64Args A)
+// Counts and conservation terms of one particle, summed per wavefront by the kernel.
+struct F64Out {
+    int64_t inter = 0, cand = 0;
+    int box = -1;
+    double cm[4] = {0.0, 0.0, 0.0, 0.0};
+};
+
+__device__ __forceinline__ void force64_one(const F64Args& A, int64_t i, F64Out& out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
     const int a = A.leaf_of[i];
     const int box = A.nd_box[A.lf_node[a]];
     const double L = A.box_len[box];
@@ -255,13 +273,38 @@ __global__ void __launch_bounds__(BS) k_force64(F64Args A)
     A.acc[3 * (int64_t)o + 1] = ay;
     A.acc[3 * (int64_t)o + 2] = az;
     A.dudt[o] = du;
-    atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_INTER], (unsigned long long)cnt);
-    atomicAdd((unsigned long long*)&A.ctr[CT_FORCE_CAND], (unsigned long long)cand);
+    out.inter = cnt;
+    out.cand = cand;
+    out.box = box;
+    out.cm[0] = mi * ax;
+    out.cm[1] = mi * ay;
+    out.cm[2] = mi * az;
+    out.cm[3] = mi * (vxi * ax + vyi * ay + vzi * az + du);
+}
+
+// One thread per particle. Counts go to the counters once per wavefront; the
+// conservation terms are summed over the wavefront when all its particles
+// share a box (the usual case: particles are sorted by box).
+__global__ void __launch_bounds__(BS) k_force64(F64Args A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    F64Out out;
+    if (i < A.n) force64_one(A, i, out);
+    ctr_wave_add(A.ctr, CT_FORCE_INTER, out.inter);
+    ctr_wave_add(A.ctr, CT_FORCE_CAND, out.cand);
     if (A.cons) {
-        atomicAdd(&A.cons[4 * box + 0], mi * ax);
-        atomicAdd(&A.cons[4 * box + 1], mi * ay);
-        atomicAdd(&A.cons[4 * box + 2], mi * az);
-        atomicAdd(&A.cons[4 * box + 3], mi * (vxi * ax + vyi * ay + vzi * az + du));
+        const int b0 = __shfl(out.box, 0, 64);
+        if (__all(out.box < 0 || out.box == b0)) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double v = out.cm[k];
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((threadIdx.x & 63) == 0 && b0 >= 0) atomicAdd(&cons_slot(A.cons, A.n_boxes)[4 * b0 + k], v);
+            }
+        } else if (out.box >= 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) atomicAdd(&cons_slot(A.cons, A.n_boxes)[4 * out.box + k], out.cm[k]);
+        }
     }
 }
 
@@ -384,8 +427,8 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     double* jf = ensure<double>(c, c->jf64, 8 * n);
     double* cons_d = nullptr;
     if (cons) {
-        cons_d = ensure<double>(c, c->cons_d, 4 * (size_t)c->n_boxes);
-        SPH_HIP(hipMemsetAsync(cons_d, 0, 32 * (size_t)c->n_boxes, s));
+        cons_d = ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes);
+        SPH_HIP(hipMemsetAsync(cons_d, 0, (size_t)CONS_SLOTS * 32 * c->n_boxes, s));
     }
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
     k_f64_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p), m_s,
@@ -409,13 +452,14 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     A.acc = acc;
     A.dudt = dudt;
     A.cons = cons_d;
+    A.n_boxes = c->n_boxes;
     A.ctr = ctr;
     A.n = n;
     A.alpha = c->prm.alpha_visc > 0 ? c->prm.alpha_visc : 0.0;
     k_force64<<<blocks_for(n, BS), BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     if (cons || st) {
-        if (cons) SPH_HIP(hipMemcpyAsync(cons, cons_d, 32 * (size_t)c->n_boxes, hipMemcpyDeviceToHost, s));
+        if (cons) read_cons(cons_d, cons, c->n_boxes, s);
         const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {

@@ -4,11 +4,13 @@
 
 #include "common.h"
 
-// Work sources of the hot kernels. Items (cells) are in Morton order.
+// Work sources of the hot kernels. Items are schedule slots: cells ranked by
+// decreasing cost (particles x candidates) and dealt out to the 8 XCDs
+// (xcd_start), so the longest cells start first and every XCD gets an equal
+// share of each cost class.
 //   hardware dispatch: one item per wavefront; consecutive workgroups are
-//     placed round-robin on the 8 XCDs, so workgroup b is remapped to run a
-//     contiguous block of items on its XCD and each XCD's L2 sees neighbouring
-//     cells;
+//     placed round-robin on the 8 XCDs and workgroup b is remapped to the next
+//     slot of its XCD's run, which is rank b;
 //   persistent: a grid sized to the machine pops batches of items from eight
 //     per-XCD queues (one atomic per batch) and steals from the other queues
 //     when its own is empty.
@@ -46,7 +48,7 @@ __device__ __forceinline__ bool next_items(const WorkSched& W, int64_t* ctr, int
         while (state < 8) {
             const int q = (xcd + state) & 7;
             const int size = W.q_begin[q + 1] - W.q_begin[q];
-            const int64_t k = atomicAdd((unsigned long long*)&ctr[CT_QUEUE + q], (unsigned long long)W.batch);
+            const int64_t k = atomicAdd((unsigned long long*)&ctr[CT_QUEUE + 8 * q], (unsigned long long)W.batch);
             if (k < size) {
                 lo = W.q_begin[q] + (int)k;
                 hi = W.q_begin[q] + (int)min<int64_t>(k + W.batch, size);
@@ -59,27 +61,6 @@ __device__ __forceinline__ bool next_items(const WorkSched& W, int64_t* ctr, int
     a_end = __shfl(hi, 0, 64);
     state = __shfl(state, 0, 64);
     return a >= 0;
-}
-
-// Pop the next cell for this wavefront; -1 when all queues are drained.
-__device__ __forceinline__ int pop_item(int64_t* ctr, const int* q_begin, int xcd, int& q_skip)
-{
-    int item = -1;
-    if ((threadIdx.x & 63) == 0) {
-        while (q_skip < 8) {
-            const int q = (xcd + q_skip) & 7;
-            const int size = q_begin[q + 1] - q_begin[q];
-            const int64_t k = atomicAdd((unsigned long long*)&ctr[CT_QUEUE + q], 1ull);
-            if (k < size) {
-                item = q_begin[q] + (int)k;
-                break;
-            }
-            ++q_skip;
-        }
-    }
-    item = __shfl(item, 0, 64);
-    q_skip = __shfl(q_skip, 0, 64);
-    return item;
 }
 
 // Lanes of a wavefront split among the particles of a cell: lpi lanes per
