@@ -110,6 +110,7 @@ typedef struct {
     int32_t density_launches;  /* density kernel launches of the last sph_density
                                   (two per pass: list kernel, re-scan kernel) */
     double density_rescan_ms;  /* the re-scan kernel's share of density_kernel_ms */
+    double pass_call_ms;       /* whole sph_pass */
 } sph_timings;
 
 typedef struct {
@@ -197,6 +198,26 @@ sph_status sph_density(sph_ctx* ctx, const float* mass, float* h, float* rho, fl
  */
 sph_status sph_force(sph_ctx* ctx, const float* vel, const float* u, float* acc, float* dudt,
                      double* cons, sph_stats* stats, void* stream);
+
+/*
+ * One density + force pass (section 3.1: density tasks, then the ghost, then
+ * the force tasks) as a single launch sequence: the same results as
+ * sph_density followed by sph_force with the same arguments, with one host
+ * synchronisation instead of one per step. The sequence is captured into a
+ * HIP graph on first use and replayed while the buffers (this call's pointers
+ * and the context's own) stay the same; with sph_params.timing it runs
+ * uncaptured and records kernel timings. When a smoothing length outgrows its
+ * cell, the pass falls back to sph_density's rebuild loop and repeats the
+ * force.
+ *   mass, h, rho, f_gradh, n_weighted: as for sph_density
+ *   vel, u, acc, dudt, cons: as for sph_force
+ *   stats  host, may be NULL: density and force counts of this pass
+ * Errors: those of sph_density and sph_force. Synchronises `stream` once (more
+ * after a rebuild).
+ */
+sph_status sph_pass(sph_ctx* ctx, const float* mass, float* h, float* rho, float* f_gradh,
+                    float* n_weighted, const float* vel, const float* u, float* acc, float* dudt,
+                    double* cons, sph_stats* stats, void* stream);
 
 /*
  * The same density solve and force in plain FP64: one thread per particle

@@ -27,7 +27,7 @@ SPH_E_STATE = 6
 
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
-           "sph_last_error", "sph_version", "sph_struct_size")
+           "sph_last_error", "sph_version", "sph_struct_size", "sph_pass")
 
 
 class sph_params(ctypes.Structure):
@@ -56,7 +56,7 @@ class sph_timings(ctypes.Structure):
     _fields_ = [("density_kernel_ms", ctypes.c_double), ("density_call_ms", ctypes.c_double),
                 ("force_kernel_ms", ctypes.c_double), ("force_call_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32),
-                ("density_rescan_ms", ctypes.c_double)]
+                ("density_rescan_ms", ctypes.c_double), ("pass_call_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_density.restype = S
     lib.sph_force.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
     lib.sph_force.restype = S
+    lib.sph_pass.argtypes = [P] * 11 + [ctypes.POINTER(sph_stats), P]
+    lib.sph_pass.restype = S
     lib.sph_density_f64.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
     lib.sph_density_f64.restype = S
     lib.sph_force_f64.argtypes = [P, P, P, P, P, P, ctypes.POINTER(sph_stats), P]
@@ -154,6 +156,10 @@ def sph_density(ctx, mass, h, rho, f, nw, stats, stream) -> int:
 
 def sph_force(ctx, vel, u, acc, dudt, cons, stats, stream) -> int:
     return load_library().sph_force(ctx, vel, u, acc, dudt, cons, stats, stream)
+
+
+def sph_pass(ctx, mass, h, rho, f, nw, vel, u, acc, dudt, cons, stats, stream) -> int:
+    return load_library().sph_pass(ctx, mass, h, rho, f, nw, vel, u, acc, dudt, cons, stats, stream)
 
 
 def sph_density_f64(ctx, mass, h, rho, f, nw, stats, stream) -> int:
@@ -264,6 +270,28 @@ class Context:
                        _stream(stream))
         _check(rc, self.ctx)
         return {"acc": acc, "dudt": dudt, "cons": cb, "stats": st.as_dict()}
+
+    def pass_(self, mass, h, vel, u, rho=None, f=None, acc=None, dudt=None, nw=None, cons=False,
+              stream=None) -> dict:
+        """sph_pass: density then force in one launch sequence; h is updated in place."""
+        import torch
+        n = self.n or mass.shape[0]
+        rho = torch.empty(n, dtype=torch.float32, device=h.device) if rho is None else rho
+        f = torch.empty(n, dtype=torch.float32, device=h.device) if f is None else f
+        acc = torch.empty((n, 3), dtype=torch.float32, device=h.device) if acc is None else acc
+        dudt = torch.empty(n, dtype=torch.float32, device=h.device) if dudt is None else dudt
+        cb = np.zeros((self.n_boxes, 4)) if cons else None
+        st = sph_stats()
+        rc = sph_pass(self.ctx, _dev(mass, torch.float32, (n,), "mass"), _dev(h, torch.float32, (n,), "h"),
+                      _dev(rho, torch.float32, (n,), "rho"), _dev(f, torch.float32, (n,), "f"),
+                      None if nw is None else _dev(nw, torch.float32, (n,), "nw"),
+                      _dev(vel, torch.float32, (n, 3), "vel"), _dev(u, torch.float32, (n,), "u"),
+                      _dev(acc, torch.float32, (n, 3), "acc"), _dev(dudt, torch.float32, (n,), "dudt"),
+                      None if cb is None else cb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                      _stream(stream))
+        _check(rc, self.ctx)
+        return {"h": h, "rho": rho, "f": f, "nw": nw, "acc": acc, "dudt": dudt, "cons": cb,
+                "stats": st.as_dict()}
 
     def density_f64(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
         import torch

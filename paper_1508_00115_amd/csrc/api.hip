@@ -124,6 +124,8 @@ void sph_destroy(sph_ctx* c)
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     if (c->h_counters) hipHostFree(c->h_counters);
+    if (c->pass_exec) hipGraphExecDestroy(c->pass_exec);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -171,6 +173,20 @@ sph_status sph_force(sph_ctx* c, const float* vel, const float* u, float* acc, f
         set_device(c);
         if (stats) *stats = sph_stats{};
         sph::force_f32(c, vel, u, acc, dudt, cons, stats, (hipStream_t)stream);
+    });
+}
+
+sph_status sph_pass(sph_ctx* c, const float* mass, float* h, float* rho, float* f_gradh, float* n_weighted,
+                    const float* vel, const float* u, float* acc, float* dudt, double* cons, sph_stats* stats,
+                    void* stream)
+{
+    if (!c) return SPH_E_ARG;
+    return guarded(c, [&] {
+        SPH_REQUIRE(mass && h && rho && f_gradh && vel && u && acc && dudt, SPH_E_ARG, "null argument");
+        SPH_REQUIRE(c->built, SPH_E_STATE, "sph_pass before sph_build_cells");
+        set_device(c);
+        if (stats) *stats = sph_stats{};
+        sph::pass_f32(c, mass, h, rho, f_gradh, n_weighted, vel, u, acc, dudt, cons, stats, (hipStream_t)stream);
     });
 }
 

@@ -677,6 +677,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
                                                    nd_coord, nd_level, nd_box, box_G, box_len, pos_s, xrel);
     SPH_HIP(hipGetLastError());
     c->built = true;
+    ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
     c->density64_done = false;
 }

@@ -187,6 +187,12 @@ struct sph_ctx {
     int n_cu = 256;
     hipEvent_t ev[9] = {};
     sph_timings tm{};
+
+    // ---- the captured density + force pass (sph_pass) -----------------------------
+    int64_t layout_serial = 0;           // bumped by every reallocation and every build
+    hipStream_t cap_stream = nullptr;    // private stream the pass is captured on
+    hipGraphExec_t pass_exec = nullptr;  // instantiated pass for pass_key
+    std::vector<uint64_t> pass_key;      // pointers and sizes the captured pass was built for
 };
 
 // Event pairs of the timing mode.
@@ -242,6 +248,7 @@ T* ensure(sph_ctx* c, Buf& b, size_t count)
     b.p = p;
     b.bytes = want;
     c->allocated += want;
+    ++c->layout_serial;
     return static_cast<T*>(p);
 }
 
@@ -330,10 +337,25 @@ void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const do
                  int64_t n, const double* pos, const float* h_guess, hipStream_t s);
 void rebuild_cells(sph_ctx* c, const float* h_guess_caller_order, hipStream_t s);
 
+// Fill n 32-bit words with v by a kernel (not a memset node, so that the
+// call may be captured into a HIP graph).
+void fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
+
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw,
                  sph_stats* st, hipStream_t s);
 void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt,
                double* cons, sph_stats* st, hipStream_t s);
+// Allocate what one density pass / force pass needs (never under capture).
+void density_buffers(sph_ctx* c);
+double* force_buffers(sph_ctx* c, bool cons);
+// Kernel launches only: no allocation, memset or host synchronisation, so
+// they may run under stream capture. events: record the timing events.
+void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, bool fresh,
+                     bool events, hipStream_t s);
+void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons_d,
+                   bool clear_all, bool events, hipStream_t s);
+void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, const float* vel,
+              const float* u, float* acc, float* dudt, double* cons, sph_stats* st, hipStream_t s);
 void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double* f, double* nw,
                  sph_stats* st, hipStream_t s);
 void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, double* dudt,

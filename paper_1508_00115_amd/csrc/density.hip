@@ -74,11 +74,15 @@ struct DensArgs {
     float nl_est;            // expected list length of a particle: n_ngb * h_margin^3
 };
 
+// Sorted copies of position (cell frame), mass, h and state. fresh: every
+// particle starts active; otherwise the caller-order state of the previous
+// pass is kept (an overflowed particle starts again).
 __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm,
                                                        const float4* __restrict__ xrel,
                                                        const float* __restrict__ mass,
                                                        const float* __restrict__ h_in,
-                                                       const uint8_t* __restrict__ status, float4* __restrict__ jd,
+                                                       const uint8_t* __restrict__ status, int fresh,
+                                                       float4* __restrict__ jd,
                                                        float* __restrict__ hs, uint8_t* __restrict__ st_s,
                                                        int64_t* __restrict__ ctr)
 {
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t
         const float4 x = xrel[p];
         jd[p] = make_float4(x.x, x.y, x.z, m);
         hs[p] = h;
-        const uint8_t st = status[o];
+        const uint8_t st = fresh ? (uint8_t)ST_ACTIVE : status[o];
         st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
         bad = !((m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h));
     }
@@ -248,28 +252,30 @@ __device__ __forceinline__ void enqueue_scan(const DensArgs& A, int slot, int n_
 
 // ---- the list kernel ----------------------------------------------------------------
 
-// Lanes per particle for a cell of ni particles and nj candidates: the power
-// of two (at least lpi_min) that minimises passes x (candidate tests, list
-// work and fixed work of a pass, per lane), plus the re-staging of every pass
-// when the candidates cannot stay resident in LDS. The weights are the VALU
-// costs of a candidate test (1), of a list entry over ~3 Newton evaluations
-// (~5) and of a pass (~25).
-__device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float nl_est, bool resident)
+// Phase A over one staged chunk for the lanes of one particle: the lane with
+// index sub in its group tests candidates sub, sub + LPI, ... (tc points at
+// candidate sub) and appends the squared distance of every hit inside H to
+// its list. The chunk is padded with far positions up to a multiple of the
+// group's stride (commit_chunk_padded), so there is no bounds test; four tile
+// reads (x, y, z only) are in flight at once and the appends are branch-free
+// (the store always happens, the slot only advances on a hit).
+template <int LPI>
+__device__ __forceinline__ void scan_chunk(const float4* tc, int len, float xx, float xy, float xz, float H2,
+                                           float* lst, int& nl)
 {
-    const int nchunks = (nj + DCH - 1) / DCH;
-    int best = 16;
-    float best_cost = 3.0e38f;
-    for (int l = lpi_min; l <= 16; l <<= 1) {
-        const int per = 64 / l;
-        const float passes = (float)((ni + per - 1) / per);
-        float cost = passes * (((float)nj + 5.0f * nl_est) / (float)l + 25.0f);
-        if (!resident) cost += passes * (float)nchunks * 20.0f;
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = l;
+    const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
+    for (int k0 = 0; k0 < len_pad; k0 += 4 * LPI, tc += 4 * LPI) {
+        float3 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = *reinterpret_cast<const float3*>(tc + u * LPI);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            lst[min(nl, DSLOTS) * 64] = r2;
+            nl += r2 < H2 ? 1 : 0;
         }
     }
-    return best;
 }
 
 // One wavefront per cell. TCAP: candidates the LDS tile holds; a cell with at
@@ -310,7 +316,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
         const int nj = nb.nj;
         const bool resident = nj <= TCAP;
-        const int lpi = choose_lpi(ni, nj, A.lpi_min, A.nl_est, resident);
+        const int lpi = choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH);
         const int per_pass = 64 / lpi;
         const int g = lane / lpi;
         const int sub = lane & (lpi - 1);
@@ -339,25 +345,18 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float4* tc = resident ? sj + c0 : sj;
                     if (stream) {
                         mixed |= chunk_mass_differs(R, m0);
-                        commit_chunk(sj + (resident ? c0 : 0), R);  // store this chunk, put the next in flight
+                        // store this chunk (padded to DCH), put the next in flight
+                        commit_chunk_padded(sj + (resident ? c0 : 0), R);
                         if (c0 + DCH < nj) fetch_chunk(R, A.jd, nb, c0 + DCH, min(DCH, nj - c0 - DCH));
                     }
-                    // four tile reads (x, y, z only) in flight, then branch-free
-                    // appends: the store always happens, the slot only advances on a hit
-                    for (int k0 = sub; k0 < len; k0 += 4 * lpi) {
-                        float3 pj[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            pj[u] = *reinterpret_cast<const float3*>(tc + min(k0 + u * lpi, len - 1));
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const float dx = xi.x - pj[u].x, dy = xi.y - pj[u].y, dz = xi.z - pj[u].z;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            const bool in = (r2 < H2) & (k0 + u * lpi < len);
-                            lst[min(nl, DSLOTS) * 64] = r2;
-                            nl += in ? 1 : 0;
-                        }
-                    }
+                    if (lpi == 2)
+                        scan_chunk<2>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                    else if (lpi == 4)
+                        scan_chunk<4>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                    else if (lpi == 8)
+                        scan_chunk<8>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                    else
+                        scan_chunk<16>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
                     if (!resident) wave_sync_lds();
                 }
                 loaded = true;
@@ -385,17 +384,18 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             // finished particle skips its list while others still iterate)
             float S0 = 0.f, S1 = 0.f, fS0 = 0.f, fS1 = 0.f;
             int cnt = 0, fcnt = 0;
+            // r^2 -> r once, so that no evaluation takes a square root
+            for (int e = 0, len_l = s.done ? 0 : nl; e < len_l; ++e) lst[e * 64] = __builtin_amdgcn_sqrtf(lst[e * 64]);
             while (__any(!s.done)) {
-                const float h2 = s.h * s.h;
                 const float hinv = 1.0f / s.h;
                 S0 = S1 = 0.f;
                 cnt = 0;
                 const int len_l = s.done ? 0 : nl;
 #pragma unroll 2
                 for (int e = 0; e < len_l; ++e) {
-                    const float r2 = lst[e * 64];
-                    const bool in = r2 < h2;
-                    const float q = in ? __builtin_amdgcn_sqrtf(r2) * hinv : 1.0f;
+                    const float r = lst[e * 64];
+                    const bool in = r < s.h;
+                    const float q = in ? r * hinv : 1.0f;
                     float w, dw;
                     spline_w_dw(q, w, dw);
                     S0 += w;
@@ -531,15 +531,87 @@ int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_
     return (int)std::max<int64_t>(grid, 1);
 }
 
+void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, bool fresh,
+                     bool events, hipStream_t s)
+{
+    const int64_t n = c->n;
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    uint8_t* status = static_cast<uint8_t*>(c->status.p);
+    float4* jd = static_cast<float4*>(c->jd.p);
+    float* hs = static_cast<float*>(c->hs.p);
+    float* rhos = static_cast<float*>(c->rhos.p);
+    float* fs = static_cast<float*>(c->fs.p);
+    uint8_t* st_s = static_cast<uint8_t*>(c->st_s.p);
+    fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);  // sums, spread slots, queue heads
+    k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                        static_cast<float4*>(c->xrel.p), mass, h, status, fresh ? 1 : 0,
+                                                        jd, hs, st_s, ctr);
+    SPH_HIP(hipGetLastError());
+    DensArgs A;
+    A.jd = jd;
+    A.Hs = static_cast<float*>(c->Hs.p);
+    A.hs = hs;
+    A.rhos = rhos;
+    A.fs = fs;
+    A.st_s = st_s;
+    A.cells = static_cast<int4*>(c->cells.p);
+    A.lf_start = static_cast<int*>(c->lf_start.p);
+    A.lf_count = static_cast<int*>(c->lf_count.p);
+    A.p_leaf = static_cast<int*>(c->p_leaf.p);
+    A.p_shift = static_cast<float4*>(c->p_shift.p);
+    A.perm = static_cast<uint32_t*>(c->perm.p);
+    A.h_out = h;
+    A.rho_out = rho;
+    A.f_out = f;
+    A.nw_out = nw;
+    A.status = status;
+    A.ctr = ctr;
+    A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
+    A.tol = (float)c->prm.n_tol;
+    A.max_iter = c->prm.max_iter;
+    // a particle with a good guess finds about n_ngb * h_margin^3 candidates
+    // inside its search radius; a lane takes every lpi-th candidate, so give
+    // the lanes room for 70% more than their share
+    const double expect = c->prm.n_ngb * c->prm.h_margin * c->prm.h_margin * c->prm.h_margin;
+    A.nl_est = (float)expect;
+    A.lpi_min = 2;
+    while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
+    A.scan_cells = static_cast<int*>(c->scan_cells.p);
+    const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
+    // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
+    const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
+    if (events) ev_record(c, EV_DENS_K0, s);
+    if (c->prm.tile_cap == 512)
+        k_density<512><<<grid, BS, 0, s>>>(A);
+    else if (c->prm.tile_cap == 256)
+        k_density<256><<<grid, BS, 0, s>>>(A);
+    else
+        k_density<128><<<grid, BS, 0, s>>>(A);
+    SPH_HIP(hipGetLastError());
+    if (events) ev_record(c, EV_DENS_KM, s);
+    k_density_scan<<<scan_grid, BS, 0, s>>>(A);
+    SPH_HIP(hipGetLastError());
+    if (events) ev_record(c, EV_DENS_K1, s);
+}
+
+void density_buffers(sph_ctx* c)
+{
+    const int64_t n = c->n;
+    ensure<uint8_t>(c, c->status, n);
+    ensure<float4>(c, c->jd, n);
+    ensure<float>(c, c->hs, n);
+    ensure<float>(c, c->rhos, n);
+    ensure<float>(c, c->fs, n);
+    ensure<uint8_t>(c, c->st_s, n);
+    ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
+}
+
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, sph_stats* st,
                  hipStream_t s)
 {
     SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
     const int64_t n = c->n;
-    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
-    uint8_t* status = ensure<uint8_t>(c, c->status, n);
-    SPH_HIP(hipMemsetAsync(status, ST_ACTIVE, (size_t)n, s));
     int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;
     int32_t sweeps = 0;
     c->rebuilds = 0;
@@ -549,61 +621,10 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     c->tm.density_launches = 0;
     ev_record(c, EV_DENS_C0, s);
     for (;;) {
-        float4* jd = ensure<float4>(c, c->jd, n);
-        float* hs = ensure<float>(c, c->hs, n);
-        float* rhos = ensure<float>(c, c->rhos, n);
-        float* fs = ensure<float>(c, c->fs, n);
-        uint8_t* st_s = ensure<uint8_t>(c, c->st_s, n);
-        SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));  // sums, spread slots, queue heads
-        k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
-                                                            static_cast<float4*>(c->xrel.p), mass, h, status, jd,
-                                                            hs, st_s, ctr);
-        SPH_HIP(hipGetLastError());
-        DensArgs A;
-        A.jd = jd;
-        A.Hs = static_cast<float*>(c->Hs.p);
-        A.hs = hs;
-        A.rhos = rhos;
-        A.fs = fs;
-        A.st_s = st_s;
-        A.cells = static_cast<int4*>(c->cells.p);
-        A.lf_start = static_cast<int*>(c->lf_start.p);
-        A.lf_count = static_cast<int*>(c->lf_count.p);
-        A.p_leaf = static_cast<int*>(c->p_leaf.p);
-        A.p_shift = static_cast<float4*>(c->p_shift.p);
-        A.perm = static_cast<uint32_t*>(c->perm.p);
-        A.h_out = h;
-        A.rho_out = rho;
-        A.f_out = f;
-        A.nw_out = nw;
-        A.status = status;
-        A.ctr = ctr;
-        A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
-        A.tol = (float)c->prm.n_tol;
-        A.max_iter = c->prm.max_iter;
-        // a particle with a good guess finds about n_ngb * h_margin^3 candidates
-        // inside its search radius; a lane takes every lpi-th candidate, so
-        // give the lanes room for 70% more than their share
-        const double expect = c->prm.n_ngb * c->prm.h_margin * c->prm.h_margin * c->prm.h_margin;
-        A.nl_est = (float)expect;
-        A.lpi_min = 2;
-        while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
-        A.scan_cells = ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
-        const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
-        // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
-        const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
-        ev_record(c, EV_DENS_K0, s);
-        if (c->prm.tile_cap == 512)
-            k_density<512><<<grid, BS, 0, s>>>(A);
-        else if (c->prm.tile_cap == 256)
-            k_density<256><<<grid, BS, 0, s>>>(A);
-        else
-            k_density<128><<<grid, BS, 0, s>>>(A);
-        SPH_HIP(hipGetLastError());
-        ev_record(c, EV_DENS_KM, s);
-        k_density_scan<<<scan_grid, BS, 0, s>>>(A);
-        SPH_HIP(hipGetLastError());
-        ev_record(c, EV_DENS_K1, s);
+        density_buffers(c);
+        // the first pass starts every particle afresh; after a rebuild the
+        // particles solved earlier keep their results
+        density_enqueue(c, mass, h, rho, f, nw, c->rebuilds == 0, true, s);
         const int64_t* hc = read_counters(c, s);
         c->tm.density_kernel_ms += ev_ms(c, EV_DENS_K0, EV_DENS_K1);
         c->tm.density_rescan_ms += ev_ms(c, EV_DENS_KM, EV_DENS_K1);
@@ -629,8 +650,9 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
                 st->n_pairs = c->n_pairs;
             }
             if (c->rebuilds > 0) {
-                k_dens_regather<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p), h, rho,
-                                                                    f, hs, rhos, fs);
+                k_dens_regather<<<blocks_for(n, 256), 256, 0, s>>>(
+                    n, static_cast<uint32_t*>(c->perm.p), h, rho, f, static_cast<float*>(c->hs.p),
+                    static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p));
                 SPH_HIP(hipGetLastError());
             }
             ev_record(c, EV_DENS_C1, s);

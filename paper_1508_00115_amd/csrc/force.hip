@@ -17,7 +17,7 @@
 
 namespace {
 
-constexpr int BS = 128;
+constexpr int BS = 64;     // one wavefront per block (finest LDS allocation)
 constexpr int WAVES = BS / 64;
 constexpr int FCAP = 128;  // candidates per LDS chunk (3 float4 each)
 constexpr int FSLOTS = FCAP / 2;  // a lane (2+ lanes per particle) tests at most every second candidate
@@ -37,7 +37,7 @@ __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, c
     const float uu = u[o];
     const float vx = vel[3 * (int64_t)o], vy = vel[3 * (int64_t)o + 1], vz = vel[3 * (int64_t)o + 2];
     if (!(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz))
-        atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+        atomicAdd((unsigned long long*)&ctr_slot(ctr)[CT_BAD_INPUT], 1ull);
     const float P = (gamma - 1.0f) * rho * uu;
     const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
     const float phi = fs[p] * P / (rho * rho);
@@ -62,16 +62,53 @@ struct ForceArgs {
     int64_t* ctr;
     WorkSched W;
     float alpha;
+    float list_work;  // pair-term work per particle, in candidate tests (choose_lpi)
 };
+
+// Phase A of one chunk for the lanes of one particle: the lane with index sub
+// in its group tests candidates sub, sub + LPI, ... (slot 0 of the tile: x,
+// y, z, 1/h) and appends the chunk index of every candidate inside
+// max(h_i, h_j), except the particle itself, to its byte list. The chunk is
+// padded with far positions to a multiple of the stride (pad_tile), four tile
+// reads are in flight and the appends are branch-free.
+template <int LPI>
+__device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, float xx, float xy, float xz,
+                                          float hinv2_i, uint8_t* lst)
+{
+    const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
+    int nl = 0;
+    for (int k0 = sub; k0 < len_pad; k0 += 4 * LPI) {
+        float4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = sj[k0 + u * LPI];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float hinv2_j = pj[u].w * pj[u].w;
+            const bool in = ((r2 * hinv2_i < 1.0f) | (r2 * hinv2_j < 1.0f)) & (r2 > 0.0f);
+            lst[nl * 64] = (uint8_t)(k0 + u * LPI);
+            nl += in ? 1 : 0;
+        }
+    }
+    return nl;
+}
+
+// Slot 0 of the unused tile entries [len, CAP): a far position with a tiny
+// 1/h, so no pair test passes there.
+__device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
+{
+    for (int t = len + (int)(threadIdx.x & 63); t < cap; t += 64) sj[t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 1.0e-12f);
+    wave_sync_lds();
+}
 
 __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
 {
-    __shared__ float4 tile[WAVES][3 * FCAP];
-    __shared__ uint8_t lists[WAVES][FSLOTS * 64];
+    __shared__ float4 tile[3 * FCAP];
+    __shared__ uint8_t lists[FSLOTS * 64];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    float4* sj = tile[wv];
-    uint8_t* lst = lists[wv];
+    float4* sj = tile;
+    uint8_t* lst = lists + lane;
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0;
     const float K8PI = 8.0f / SPH_PI_F;
@@ -82,22 +119,17 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         const int4 ci = A.cells[slot];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         const bool fastnb = np_all <= 64;
-        NbrLanes nb;
-        int nj;
-        if (fastnb) {
-            nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
-            nj = nb.nj;
-        } else {
-            nj = count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
-        }
-        const Groups G = make_groups(ni);
-        const int lpi = G.lpi;
-        const int sub = G.sub;
+        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, min(np_all, 64));
+        const int nj = fastnb ? nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
         const bool single_tile = nj <= FCAP;
+        const int lpi = choose_lpi(ni, nj, 2, A.list_work, single_tile, FCAP);
+        const int per_pass = 64 / lpi;
+        const int g = lane / lpi;
+        const int sub = lane & (lpi - 1);
         bool loaded = false;
-        for (int ib = 0; ib < ni; ib += G.per_pass) {
-            const int gi = ib + G.g;
-            const bool valid = G.g < G.per_pass && gi < ni;
+        for (int ib = 0; ib < ni; ib += per_pass) {
+            const int gi = ib + g;
+            const bool valid = gi < ni;
             const int i = i0 + (valid ? gi : 0);
             const float4 i0v = A.jf[3 * (int64_t)i + 0];
             const float4 i1v = A.jf[3 * (int64_t)i + 1];
@@ -123,32 +155,25 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                         stage_tile<3>(sj, A.jf, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len,
                                       FCAP);
                     }
+                    pad_tile(sj, len, FCAP);
                     loaded = true;
                 }
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
-                // (four tile reads in flight, branch-free appends: the store always
-                // happens and the slot only advances on a hit)
-                int nl = 0;
-                for (int k0 = sub; k0 < len; k0 += 4 * lpi) {
-                    float4 pj[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) pj[u] = sj[min(k0 + u * lpi, len - 1)];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int k = k0 + u * lpi;
-                        const float dx = i0v.x - pj[u].x, dy = i0v.y - pj[u].y, dz = i0v.z - pj[u].z;
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const float hinv2_j = pj[u].w * pj[u].w;
-                        const bool in = ((r2 * hinv2_i < 1.0f) | (r2 * hinv2_j < 1.0f)) & (r2 > 0.0f) & (k < len);
-                        lst[nl * 64 + lane] = (uint8_t)k;
-                        nl += in ? 1 : 0;
-                    }
-                }
+                int nl;
+                if (lpi == 2)
+                    nl = force_scan<2>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                else if (lpi == 4)
+                    nl = force_scan<4>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                else if (lpi == 8)
+                    nl = force_scan<8>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                else
+                    nl = force_scan<16>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                if (!valid) nl = 0;
                 cnt += nl;
                 // phase B: the pair terms of the compacted neighbours only
 #pragma unroll 2
                 for (int e = 0; e < nl; ++e) {
-                    const int k = lst[e * 64 + lane];
+                    const int k = lst[e * 64];
                     const float4 p0 = sj[k];
                     const float4 p1 = sj[FCAP + k];
                     const float4 p2 = sj[2 * FCAP + k];
@@ -178,11 +203,11 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                     __builtin_amdgcn_wave_barrier();
                 }
             }
-            ax = gsum(ax, G);
-            ay = gsum(ay, G);
-            az = gsum(az, G);
-            du = gsum(du, G);
-            cnt = gsum_i(cnt, G);
+            ax = group_sum(ax, lpi);
+            ay = group_sum(ay, lpi);
+            az = group_sum(az, lpi);
+            du = group_sum(du, lpi);
+            cnt = group_sum_i(cnt, lpi);
             const bool leader = valid && sub == 0;
             int ng = leader ? 1 : 0;
             for (int o = 32; o >= 1; o >>= 1) ng += __shfl_xor(ng, o, 64);
@@ -223,25 +248,23 @@ namespace sph {
 
 int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_cu, WorkSched& W);
 
-void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons,
-               sph_stats* st, hipStream_t s)
+void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons_d,
+                   bool clear_all, bool events, hipStream_t s)
 {
-    SPH_REQUIRE(c->built && c->density_done, SPH_E_STATE, "sph_force needs a successful sph_density first");
-    SPH_REQUIRE(vel && u && acc && dudt, SPH_E_ARG, "null vel/u/acc/dudt");
     const int64_t n = c->n;
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
-    float4* jf = ensure<float4>(c, c->jf, 3 * n);
-    double* cons_d = nullptr;
-    if (cons) {
-        cons_d = ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes);
-        SPH_HIP(hipMemsetAsync(cons_d, 0, (size_t)CONS_SLOTS * 32 * c->n_boxes, s));
-    }
-    ev_record(c, EV_FORCE_C0, s);
-    SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
-    k_force_prologue<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
-                                                       static_cast<float4*>(c->jd.p), static_cast<float*>(c->hs.p),
-                                                       static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p),
-                                                       vel, u, (float)c->prm.gamma, jf, ctr);
+    float4* jf = static_cast<float4*>(c->jf.p);
+    // all counters, or (after a density pass whose counters are still to be
+    // read) only the work-queue heads
+    if (clear_all)
+        fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);
+    else
+        fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);
+    if (cons_d) fill_u32(cons_d, 0u, (int64_t)CONS_SLOTS * 8 * c->n_boxes, s);
+    k_force_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                         static_cast<float4*>(c->jd.p), static_cast<float*>(c->hs.p),
+                                                         static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p),
+                                                         vel, u, (float)c->prm.gamma, jf, ctr);
     SPH_HIP(hipGetLastError());
     ForceArgs A;
     A.jf = jf;
@@ -257,12 +280,29 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     A.cons = cons_d;
     A.n_boxes = c->n_boxes;
     A.ctr = ctr;
-    const int grid = make_sched(c, c->n_leaves, WAVES, 4, A.W);
+    const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
-    ev_record(c, EV_FORCE_K0, s);
+    A.list_work = (float)(4.0 * c->prm.n_ngb);  // ~n_ngb pairs per particle at ~4 tests' cost each
+    if (events) ev_record(c, EV_FORCE_K0, s);
     k_force<<<grid, BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
-    ev_record(c, EV_FORCE_K1, s);
+    if (events) ev_record(c, EV_FORCE_K1, s);
+}
+
+double* force_buffers(sph_ctx* c, bool cons)
+{
+    ensure<float4>(c, c->jf, 3 * c->n);
+    return cons ? ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes) : nullptr;
+}
+
+void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons,
+               sph_stats* st, hipStream_t s)
+{
+    SPH_REQUIRE(c->built && c->density_done, SPH_E_STATE, "sph_force needs a successful sph_density first");
+    SPH_REQUIRE(vel && u && acc && dudt, SPH_E_ARG, "null vel/u/acc/dudt");
+    double* cons_d = force_buffers(c, cons != nullptr);
+    ev_record(c, EV_FORCE_C0, s);
+    force_enqueue(c, vel, u, acc, dudt, cons_d, true, true, s);
     if (cons || st) {
         if (cons) read_cons(cons_d, cons, c->n_boxes, s);
         const int64_t* hc = read_counters(c, s);

@@ -164,9 +164,22 @@ __global__ void __launch_bounds__(RS_BS) k_rs_scatter(const uint64_t* __restrict
     }
 }
 
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
 
 namespace sph {
+
+void fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_fill_u32<<<blocks_for(n, 256), 256, 0, s>>>(static_cast<uint32_t*>(p), v, n);
+    SPH_HIP(hipGetLastError());
+}
 
 void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                     hipStream_t s)

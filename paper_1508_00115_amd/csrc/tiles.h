@@ -63,6 +63,30 @@ __device__ __forceinline__ bool next_items(const WorkSched& W, int64_t* ctr, int
     return a >= 0;
 }
 
+// Lanes per particle for a cell of ni particles and nj candidates: the power
+// of two (at least lpi_min) that minimises passes x (candidate tests + list
+// work per particle + fixed work of a pass, per lane), plus the re-staging of
+// every pass when the candidates cannot stay resident in LDS (chunks of
+// `chunk`). Weights are VALU costs in units of one candidate test: list work
+// is given per particle (`list_work`), a pass costs ~25, staging a chunk ~20.
+__device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float list_work, bool resident, int chunk)
+{
+    const int nchunks = (nj + chunk - 1) / chunk;
+    int best = 16;
+    float best_cost = 3.0e38f;
+    for (int l = lpi_min; l <= 16; l <<= 1) {
+        const int per = 64 / l;
+        const float passes = (float)((ni + per - 1) / per);
+        float cost = passes * (((float)nj + list_work) / (float)l + 25.0f);
+        if (!resident) cost += passes * (float)nchunks * 20.0f;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = l;
+        }
+    }
+    return best;
+}
+
 // Lanes of a wavefront split among the particles of a cell: lpi lanes per
 // particle (2 to 16, any size), consecutive lanes forming a group. Lanes past
 // the last full group stay idle.
@@ -295,6 +319,31 @@ __device__ __forceinline__ void commit_chunk(float4* sj, const ChunkRegs<NF, CAP
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// commit_chunk for a one-float4 tile whose unused slots [len, CAP) are filled
+// with a position far outside any search radius: a loop over the chunk may
+// then run to a multiple of its stride without a bounds test.
+template <int CAP>
+__device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<1, CAP>& R)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        float4 a = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+        if (t < R.len) {
+            a = R.v[r][0];
+            a.x += R.s[r][0];
+            a.y += R.s[r][1];
+            a.z += R.s[r][2];
+        }
+        sj[t] = a;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 // Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
 // the neighbour cell of each of its candidates by a binary search over the

@@ -9,9 +9,12 @@ legal cell layout):
                  the cells must be rebuilt
     cell_ratio   smallest cell width below the top grid, in search radii
     leaf_target  cells holding more particles than this are split
+    schedule     hardware dispatch or persistent per-XCD queues
+    tile_cap     candidates the density kernel keeps resident in LDS
 
-Each setting is timed on the caller's particles with the library's own HIP
-events (density + force, after a warm-up); the fastest wins. Results are
+Each setting is timed on the caller's particles as whole density + force
+passes (sph_pass, after a warm-up, HIP events around the calls); the fastest
+wins. Results are
 kept in a JSON file keyed by a signature of the particle set; ``tuned.json``
 beside this module holds the results shipped with the library.
 
@@ -29,11 +32,12 @@ import os
 import numpy as np
 
 DEFAULT_GRID = [
-    {"h_margin": m, "cell_ratio": cr, "leaf_target": lt, "schedule": s}
+    {"h_margin": m, "cell_ratio": cr, "leaf_target": lt, "schedule": s, "tile_cap": tc}
     for m in (1.05, 1.1, 1.18, 1.26)
     for cr in (1.0, 0.5)
     for lt in (64, 32)
     for s in (0, 1)
+    for tc in (128, 512)
 ]
 
 
@@ -92,18 +96,21 @@ def autotune(d: dict, device: int = 0, grid=None, reps: int = 5, cache: str | No
     rho, f = torch.empty_like(h), torch.empty_like(h)
     acc, dudt = torch.empty((n, 3), dtype=torch.float32, device=dev), torch.empty_like(h)
     table = []
+    stream = torch.cuda.current_stream(dev)
     for params in grid:
-        ctx = Context(device, timing=1, **params)
+        ctx = Context(device, **params)
         try:
             ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
             times = []
             for r in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 h.copy_(h0)
-                st = ctx.density(mass, h, rho, f)["stats"]
-                ctx.force(vel, u, acc, dudt, cons=False)
-                t = ctx.timings()
-                if r > 0:  # first pass warms up
-                    times.append(t["density_call_ms"] + t["force_call_ms"])
+                e0.record(stream)
+                st = ctx.pass_(mass, h, vel, u, rho=rho, f=f, acc=acc, dudt=dudt)["stats"]
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r > 0:  # the first pass warms up (and captures the launch sequence)
+                    times.append(e0.elapsed_time(e1))
             table.append({"params": params, "ms": float(np.median(times)), "rebuilds": st["rebuilds"],
                           "cells": st["n_cells"]})
         except RuntimeError as e:  # e.g. a margin too large for a small box
