@@ -96,6 +96,10 @@ typedef struct {
     int32_t tile_cap;     /* candidates of a cell the density kernel keeps in LDS
                              for all its passes: 128, 256 or 512 (128); a larger
                              tile means fewer reloads but fewer wavefronts per CU */
+    int32_t cell_order;   /* order cells reach wavefronts: 0 = by decreasing cost,
+                             dealt out to the 8 XCDs (balance; default);
+                             1 = Morton order, a contiguous range per XCD
+                             (neighbouring cells share an XCD's L2) */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP

@@ -37,7 +37,7 @@ class sph_params(ctypes.Structure):
                 ("cell_ratio", ctypes.c_double), ("leaf_target", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("queue_batch", ctypes.c_int32),
-                ("tile_cap", ctypes.c_int32)]
+                ("tile_cap", ctypes.c_int32), ("cell_order", ctypes.c_int32)]
 
 
 class sph_stats(ctypes.Structure):

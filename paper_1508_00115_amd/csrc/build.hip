@@ -399,7 +399,9 @@ __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const 
     vals[a] = (uint32_t)a;
 }
 
-// Schedule slots: the leaf of cost rank r goes to slot xcd_start(nl, r % 8) + r / 8.
+// Schedule slots. by_cost != null: the leaf of cost rank r goes to slot
+// xcd_start(nl, r % 8) + r / 8. by_cost == null: slot r holds leaf r (Morton
+// order, so each XCD takes a contiguous range of neighbouring cells).
 __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, const int* __restrict__ lf_start,
                              const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
                              const int* __restrict__ lf_node, const int* __restrict__ nd_box, int4* __restrict__ cells,
@@ -407,8 +409,8 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, c
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nl) return;
-    const int a = (int)by_cost[r];
-    const int64_t slot = sph::xcd_start(nl, (int)(r & 7)) + (r >> 3);
+    const int a = by_cost ? (int)by_cost[r] : (int)r;
+    const int64_t slot = by_cost ? sph::xcd_start(nl, (int)(r & 7)) + (r >> 3) : r;
     cells[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)(p_start[a + 1] - p_start[a]));
     cell_aux[slot] = make_int2(a, nd_box[lf_node[a]]);
 }
@@ -654,19 +656,22 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
                                                  p_cnt, p_start, p_leaf, p_shift, p_code, ctr);
     SPH_HIP(hipGetLastError());
 
-    // ---- work schedule: leaves by decreasing cost, dealt out to the XCDs -----------------------------
+    // ---- work schedule: leaves by decreasing cost dealt out to the XCDs, or Morton ranges ---------
     {
         uint64_t* sk = ensure<uint64_t>(c, c->sched_key, nl);
         uint64_t* ska = ensure<uint64_t>(c, c->sched_key_alt, nl);
         uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
         uint32_t* sva = ensure<uint32_t>(c, c->sched_val_alt, nl);
-        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv);
-        SPH_HIP(hipGetLastError());
-        radix_sort(c, sk, sv, ska, sva, nl, 32, s);
+        const bool by_cost = c->prm.cell_order == 0;
+        if (by_cost) {
+            k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv);
+            SPH_HIP(hipGetLastError());
+            radix_sort(c, sk, sv, ska, sva, nl, 32, s);
+        }
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
-        k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, sv, lf_start, lf_count, p_start, lf_node, nd_box, cells,
-                                                       cell_aux);
+        k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, lf_start, lf_count, p_start,
+                                                       lf_node, nd_box, cells, cell_aux);
         SPH_HIP(hipGetLastError());
     }
 

@@ -4,10 +4,11 @@
 
 #include "common.h"
 
-// Work sources of the hot kernels. Items are schedule slots: cells ranked by
-// decreasing cost (particles x candidates) and dealt out to the 8 XCDs
-// (xcd_start), so the longest cells start first and every XCD gets an equal
-// share of each cost class.
+// Work sources of the hot kernels. Items are schedule slots: either cells
+// ranked by decreasing cost (particles x candidates) and dealt out to the 8
+// XCDs (xcd_start), so the longest cells start first and every XCD gets an
+// equal share of each cost class, or cells in Morton order, so each XCD runs a
+// contiguous range of neighbouring cells whose particles its L2 keeps.
 //   hardware dispatch: one item per wavefront; consecutive workgroups are
 //     placed round-robin on the 8 XCDs and workgroup b is remapped to the next
 //     slot of its XCD's run, which is rank b;

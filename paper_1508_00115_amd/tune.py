@@ -11,6 +11,7 @@ legal cell layout):
     leaf_target  cells holding more particles than this are split
     schedule     hardware dispatch or persistent per-XCD queues
     tile_cap     candidates the density kernel keeps resident in LDS
+    cell_order   cells by decreasing cost (balance) or in Morton order (L2 reuse)
 
 Each setting is timed on the caller's particles as whole density + force
 passes (sph_pass, after a warm-up, HIP events around the calls); the fastest
@@ -32,12 +33,13 @@ import os
 import numpy as np
 
 DEFAULT_GRID = [
-    {"h_margin": m, "cell_ratio": cr, "leaf_target": lt, "schedule": s, "tile_cap": tc}
+    {"h_margin": m, "cell_ratio": cr, "leaf_target": lt, "schedule": s, "tile_cap": tc, "cell_order": co}
     for m in (1.05, 1.1, 1.18, 1.26)
     for cr in (1.0, 0.5)
     for lt in (64, 32)
     for s in (0, 1)
     for tc in (128, 512)
+    for co in (0, 1)
 ]
 
 
