@@ -379,12 +379,14 @@ __device__ __forceinline__ void spline_w_dw(float q, float& w, float& dw)
     dw = inner ? dw_in : dw_out;
 }
 
-__device__ __forceinline__ float spline_dw(float q)
+// w'(q) at q = r hinv, zero from q = 1 on: 24 u^2 - 6 t^2 with t = max(1 - q, 0)
+// and u = max(1/2 - q, 0), the cubic spline's derivative as truncated powers
+// (no branch, no select; both clamps fold into the FMAs' clamp bit).
+__device__ __forceinline__ float spline_dw_r(float r, float hinv)
 {
-    const float t = 1.0f - q;
-    const float dw_in = q * fmaf(18.0f, q, -12.0f);
-    const float dw_out = -6.0f * t * t;
-    return q < 0.5f ? dw_in : dw_out;
+    const float t = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+    const float u = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
+    return fmaf(24.0f * u, u, -6.0f * (t * t));
 }
 
 __device__ __forceinline__ void spline_w_dw64(double q, double& w, double& dw)

@@ -388,20 +388,29 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             for (int e = 0, len_l = s.done ? 0 : nl; e < len_l; ++e) lst[e * 64] = __builtin_amdgcn_sqrtf(lst[e * 64]);
             while (__any(!s.done)) {
                 const float hinv = 1.0f / s.h;
-                S0 = S1 = 0.f;
                 cnt = 0;
                 const int len_l = s.done ? 0 : nl;
+                // w(q) = 2 t^3 - 8 u^3 and q w'(q) = q (24 u^2 - 6 t^2) with
+                // t = max(1 - q, 0), u = max(1/2 - q, 0): the cubic spline as
+                // truncated powers, no branch and no select (both clamps are
+                // the FMA's clamp to [0, 1]); the four sums are combined after
+                // the loop
+                float At = 0.f, Au = 0.f, Bt = 0.f, Bu = 0.f;
 #pragma unroll 2
                 for (int e = 0; e < len_l; ++e) {
                     const float r = lst[e * 64];
-                    const bool in = r < s.h;
-                    const float q = in ? r * hinv : 1.0f;
-                    float w, dw;
-                    spline_w_dw(q, w, dw);
-                    S0 += w;
-                    S1 = fmaf(q, dw, S1);
-                    cnt += in ? 1 : 0;
+                    const float q = r * hinv;
+                    const float t = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+                    const float u = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
+                    const float t2 = t * t, u2 = u * u;
+                    At = fmaf(t2, t, At);
+                    Au = fmaf(u2, u, Au);
+                    Bt = fmaf(q, t2, Bt);
+                    Bu = fmaf(q, u2, Bu);
+                    cnt += t > 0.0f ? 1 : 0;  // r < h
                 }
+                S0 = fmaf(2.0f, At, -8.0f * Au);
+                S1 = fmaf(24.0f, Bu, -6.0f * Bt);
                 cand_acc += wave_sum_i(len_l);
                 S0 = group_sum(S0, lpi);
                 S1 = group_sum(S1, lpi);

@@ -183,10 +183,8 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                     const float hinv2_j = hinv_j * hinv_j;
                     const float rinv = rsqrtf(r2);
                     const float r = r2 * rinv;
-                    const float qi = fminf(r * hinv_i, 1.0f);
-                    const float qj = fminf(r * hinv_j, 1.0f);
-                    const float Di = Ki * spline_dw(qi);
-                    const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw(qj);
+                    const float Di = Ki * spline_dw_r(r, hinv_i);
+                    const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw_r(r, hinv_j);
                     const float vr = ((i1v.x - p1.x) * dx + (i1v.y - p1.y) * dy + (i1v.z - p1.z) * dz) * rinv;
                     const float wv_ = fminf(vr, 0.0f);
                     const float visc = -A.alpha * (c_i + p2.z - 3.0f * wv_) * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
