@@ -81,8 +81,11 @@ typedef struct {
     int32_t max_iter;     /* Newton iterations per particle (64) */
     double  h_margin;     /* cells are built for search radii h_margin * h_guess
                              (1.26); h may grow by this factor before a rebuild */
-    double  cell_ratio;   /* cells below the top grid are at least
-                             cell_ratio * (largest search radius inside) wide (1.0) */
+    double  cell_ratio;   /* a cell below the top grid is split only while at
+                             most one particle in eight of it has cell_ratio *
+                             search radius above half its width (1.0); the
+                             few wider ones keep a longer reach, never a
+                             wrong result */
     int32_t leaf_target;  /* a cell with more particles than this is split when
                              the width rule allows it (64) */
     int64_t workspace_limit; /* device bytes the context may allocate; 0 = no limit */
@@ -237,6 +240,21 @@ sph_status sph_force_f64(sph_ctx* ctx, const double* vel, const double* u, doubl
 /* Copy the durations of the last calls into *out (host). Errors: SPH_E_ARG. */
 sph_status sph_get_timings(const sph_ctx* ctx, sph_timings* out);
 
+/* Shape of the last sph_build_cells (section 3.1's cells and pair tasks). A
+ * density sweep tests candidate_pairs (particle, candidate) pairs. */
+typedef struct {
+    int64_t n_cells;             /* leaf cells */
+    int64_t n_pairs;             /* (cell, neighbour cell) entries, self included */
+    int64_t max_cell_particles;  /* particles of the largest leaf */
+    int64_t max_neighbour_cells; /* longest neighbour-cell list */
+    int64_t max_candidates;      /* most particles in one leaf's neighbour cells */
+    int64_t candidate_pairs;     /* sum over leaves of particles x candidates */
+} sph_build_info;
+
+/* Copy the shape of the last build into *out (host). Errors: SPH_E_ARG,
+ * SPH_E_STATE (no build yet). */
+sph_status sph_get_build_info(const sph_ctx* ctx, sph_build_info* out);
+
 /* Static description of a status code. */
 const char* sph_status_string(sph_status s);
 
@@ -248,8 +266,8 @@ const char* sph_last_error(const sph_ctx* ctx);
 const char* sph_version(void);
 
 /* sizeof of the structs above as this library was compiled, for bindings that
- * lay them out by hand: which = 0 sph_params, 1 sph_stats, 2 sph_timings;
- * -1 for any other value. */
+ * lay them out by hand: which = 0 sph_params, 1 sph_stats, 2 sph_timings,
+ * 3 sph_build_info; -1 for any other value. */
 int32_t sph_struct_size(int32_t which);
 
 #ifdef __cplusplus

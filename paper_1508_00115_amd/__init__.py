@@ -27,7 +27,7 @@ SPH_E_STATE = 6
 
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
-           "sph_last_error", "sph_version", "sph_struct_size", "sph_pass")
+           "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info")
 
 
 class sph_params(ctypes.Structure):
@@ -47,6 +47,15 @@ class sph_stats(ctypes.Structure):
                 ("candidates_force", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("sweep_interactions_density", ctypes.c_int64),
                 ("rescanned_density", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class sph_build_info(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("max_cell_particles", ctypes.c_int64),
+                ("max_neighbour_cells", ctypes.c_int64), ("max_candidates", ctypes.c_int64),
+                ("candidate_pairs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -100,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_force_f64.restype = S
     lib.sph_get_timings.argtypes = [P, ctypes.POINTER(sph_timings)]
     lib.sph_get_timings.restype = S
+    lib.sph_get_build_info.argtypes = [P, ctypes.POINTER(sph_build_info)]
+    lib.sph_get_build_info.restype = S
     lib.sph_status_string.argtypes = [S]
     lib.sph_status_string.restype = ctypes.c_char_p
     lib.sph_last_error.argtypes = [P]
@@ -174,6 +185,10 @@ def sph_get_timings(ctx, out) -> int:
     return load_library().sph_get_timings(ctx, out)
 
 
+def sph_get_build_info(ctx, out) -> int:
+    return load_library().sph_get_build_info(ctx, out)
+
+
 # ---- torch convenience ---------------------------------------------------------------
 
 
@@ -224,6 +239,11 @@ class Context:
         t = sph_timings()
         _check(sph_get_timings(self.ctx, ctypes.byref(t)), self.ctx)
         return t.as_dict()
+
+    def build_info(self) -> dict:
+        b = sph_build_info()
+        _check(sph_get_build_info(self.ctx, ctypes.byref(b)), self.ctx)
+        return b.as_dict()
 
     def build_cells(self, pos, h_guess, box_first=None, box_len=None, stream=None):
         import torch

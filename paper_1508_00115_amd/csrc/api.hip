@@ -114,7 +114,7 @@ void sph_destroy(sph_ctx* c)
     sph::Buf* all[] = {&c->box_first, &c->box_len, &c->box_G, &c->box_top_base, &c->box_hmax, &c->pos_w,
                        &c->hguess, &c->keys, &c->keys_alt, &c->perm, &c->perm_alt, &c->pos_s, &c->xrel,
                        &c->Hs, &c->leaf_of, &c->unassigned, &c->head, &c->scan1, &c->nid, &c->nd_start,
-                       &c->nd_count, &c->nd_hmax, &c->nd_child0, &c->nd_child1, &c->nd_leaf, &c->nd_box,
+                       &c->nd_count, &c->nd_hmax, &c->nd_wide, &c->nd_child0, &c->nd_child1, &c->nd_leaf, &c->nd_box,
                        &c->nd_level, &c->nd_coord, &c->nflag, &c->nscan, &c->top, &c->lf_start, &c->lf_count,
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->status,
@@ -225,6 +225,14 @@ sph_status sph_get_timings(const sph_ctx* c, sph_timings* out)
     return SPH_OK;
 }
 
+sph_status sph_get_build_info(const sph_ctx* c, sph_build_info* out)
+{
+    if (!c || !out) return SPH_E_ARG;
+    if (!c->built) return SPH_E_STATE;
+    *out = c->binfo;
+    return SPH_OK;
+}
+
 const char* sph_status_string(sph_status s)
 {
     switch (s) {
@@ -253,6 +261,7 @@ int32_t sph_struct_size(int32_t which)
         case 0: return (int32_t)sizeof(sph_params);
         case 1: return (int32_t)sizeof(sph_stats);
         case 2: return (int32_t)sizeof(sph_timings);
+        case 3: return (int32_t)sizeof(sph_build_info);
         default: return -1;
     }
 }

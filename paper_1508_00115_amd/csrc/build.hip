@@ -155,21 +155,57 @@ __global__ void k_lvl_head(int64_t n, const uint64_t* __restrict__ keys, const i
     head[p] = h;
 }
 
-// Node of every unassigned particle at level l; node start, count and
-// largest search radius.
+// Node of every unassigned particle at level l; node start, count, largest
+// search radius, and the number of particles whose search radius is too wide
+// for half the node (cell_ratio * H > w / 2). Particles are sorted, so a
+// wavefront's particles usually share one node: it then adds once.
 __global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const int* __restrict__ leaf_tmp,
                             const uint32_t* __restrict__ head, const uint32_t* __restrict__ excl,
                             const float* __restrict__ Hs, int level, KeyLayout kl, int64_t node_base,
                             int* __restrict__ nid, int* __restrict__ nd_start, int* __restrict__ nd_count,
-                            unsigned* __restrict__ nd_hmax, int* __restrict__ nd_box,
+                            unsigned* __restrict__ nd_hmax, int* __restrict__ nd_wide, int* __restrict__ nd_box,
                             int* __restrict__ nd_level, int* __restrict__ nd_coord,
-                            const int* __restrict__ box_G)
+                            const int* __restrict__ box_G, const double* __restrict__ box_len, float cell_ratio)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n || leaf_tmp[p] >= 0) return;
-    const int64_t id = node_base + (int64_t)excl[p] + head[p] - 1;
-    nid[p] = (int)id;
-    if (head[p]) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < n && leaf_tmp[p] < 0;
+    int id = -1;
+    unsigned hb = 0u;
+    int wide = 0;
+    if (valid) {
+        id = (int)(node_base + (int64_t)excl[p] + head[p] - 1);
+        nid[p] = id;
+        const uint64_t k = keys[p];
+        const int b = (int)(k >> (kl.bits_top + 3 * kl.levels));
+        const double w = box_len[b] / box_G[b] / (double)(1u << level);
+        const float H = Hs[p];
+        hb = __float_as_uint(H);
+        wide = (double)(cell_ratio * H) > 0.5 * w ? 1 : 0;
+    }
+    int id_lo = valid ? id : 0x7fffffff, id_hi = id;
+    for (int o = 32; o >= 1; o >>= 1) {
+        id_lo = min(id_lo, __shfl_xor(id_lo, o, 64));
+        id_hi = max(id_hi, __shfl_xor(id_hi, o, 64));
+    }
+    if (id_hi >= 0 && id_lo == id_hi) {
+        int cnt = valid ? 1 : 0, wsum = wide;
+        unsigned hmx = hb;
+        for (int o = 32; o >= 1; o >>= 1) {
+            cnt += __shfl_xor(cnt, o, 64);
+            wsum += __shfl_xor(wsum, o, 64);
+            hmx = max(hmx, (unsigned)__shfl_xor((int)hmx, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&nd_count[id_hi], cnt);
+            atomicMax(&nd_hmax[id_hi], hmx);
+            if (wsum) atomicAdd(&nd_wide[id_hi], wsum);
+        }
+    } else if (valid) {
+        atomicAdd(&nd_count[id], 1);
+        atomicMax(&nd_hmax[id], hb);
+        if (wide) atomicAdd(&nd_wide[id], 1);
+    }
+    if (valid && head[p]) {
         const uint64_t k = keys[p];
         const int b = (int)(k >> (kl.bits_top + 3 * kl.levels));
         const uint64_t top = (k >> (3 * kl.levels)) & ((1ull << kl.bits_top) - 1);
@@ -184,24 +220,23 @@ __global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const 
         nd_coord[3 * id + 1] = (int)((ty << level) | my);
         nd_coord[3 * id + 2] = (int)((tz << level) | mz);
     }
-    atomicAdd(&nd_count[id], 1);
-    atomicMax(&nd_hmax[id], __float_as_uint(Hs[p]));
 }
 
+// A node is split when it holds more than leaf_target particles and at most
+// one in eight of them has a search radius too wide for half its width. The
+// wide few then sit in small cells with a long reach (pairs are found by box
+// distance with each cell's own largest radius), instead of a few outliers
+// keeping every particle of a dense region in one huge cell.
 __global__ void k_lvl_decide(int64_t M, int64_t node_base, int level, int max_level, int leaf_target,
-                             float cell_ratio, const int* __restrict__ nd_count,
-                             const unsigned* __restrict__ nd_hmax, const int* __restrict__ nd_box,
-                             const double* __restrict__ box_len, const int* __restrict__ box_G,
+                             const int* __restrict__ nd_count, const int* __restrict__ nd_wide,
                              uint32_t* __restrict__ nflag, int* __restrict__ nd_child0,
                              int* __restrict__ nd_child1)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
     const int64_t id = node_base + k;
-    const int b = nd_box[id];
-    const double w = box_len[b] / box_G[b] / (double)(1u << level);
-    const float hm = __uint_as_float(nd_hmax[id]);
-    const bool split = level < max_level && nd_count[id] > leaf_target && (double)(cell_ratio * hm) <= 0.5 * w;
+    const int cnt = nd_count[id];
+    const bool split = level < max_level && cnt > leaf_target && 8 * nd_wide[id] <= cnt;
     nflag[k] = split ? 0u : 1u;
     nd_child0[id] = -1;
     nd_child1[id] = -1;
@@ -387,16 +422,25 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
 // Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
 // Cost of each leaf's cell tasks (particles x candidates) as a sort key that
 // orders by decreasing cost (positive floats order like their bit patterns).
+// Also the build's shape counters (CT_B_*).
 __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
-                            const int* __restrict__ p_leaf, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
+                            const int* __restrict__ p_leaf, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            int64_t* __restrict__ ctr)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= nl) return;
-    int nj = 0;
-    for (uint32_t p = p_start[a]; p < p_start[a + 1]; ++p) nj += lf_count[p_leaf[p]];
-    const float cost = (float)lf_count[a] * (float)nj;
-    keys[a] = 0xffffffffull - __float_as_uint(cost);
-    vals[a] = (uint32_t)a;
+    int ni = 0, np = 0, nj = 0;
+    if (a < nl) {
+        ni = lf_count[a];
+        np = (int)(p_start[a + 1] - p_start[a]);
+        for (uint32_t p = p_start[a]; p < p_start[a + 1]; ++p) nj += lf_count[p_leaf[p]];
+        const float cost = (float)ni * (float)nj;
+        keys[a] = 0xffffffffull - __float_as_uint(cost);
+        vals[a] = (uint32_t)a;
+    }
+    ctr_wave_add(ctr, CT_B_CAND_PAIRS, (int64_t)ni * nj);
+    ctr_wave_max(ctr, CT_B_MAX_NI, ni);
+    ctr_wave_max(ctr, CT_B_MAX_NP, np);
+    ctr_wave_max(ctr, CT_B_MAX_NJ, nj);
 }
 
 // Schedule slots. by_cost != null: the leaf of cost rank r goes to slot
@@ -552,6 +596,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
             grow_keep<int>(c, c->nd_start, cap, node_base, s);
             grow_keep<int>(c, c->nd_count, cap, node_base, s);
             grow_keep<unsigned>(c, c->nd_hmax, cap, node_base, s);
+            grow_keep<int>(c, c->nd_wide, cap, node_base, s);
             grow_keep<int>(c, c->nd_child0, cap, node_base, s);
             grow_keep<int>(c, c->nd_child1, cap, node_base, s);
             grow_keep<int>(c, c->nd_leaf, cap, node_base, s);
@@ -563,6 +608,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         int* nd_start = static_cast<int*>(c->nd_start.p);
         int* nd_count = static_cast<int*>(c->nd_count.p);
         unsigned* nd_hmax = static_cast<unsigned*>(c->nd_hmax.p);
+        int* nd_wide = static_cast<int*>(c->nd_wide.p);
         int* nd_child0 = static_cast<int*>(c->nd_child0.p);
         int* nd_child1 = static_cast<int*>(c->nd_child1.p);
         int* nd_leaf = static_cast<int*>(c->nd_leaf.p);
@@ -571,9 +617,10 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         int* nd_coord = static_cast<int*>(c->nd_coord.p);
         SPH_HIP(hipMemsetAsync(nd_count + node_base, 0, (size_t)M * 4, s));
         SPH_HIP(hipMemsetAsync(nd_hmax + node_base, 0, (size_t)M * 4, s));
+        SPH_HIP(hipMemsetAsync(nd_wide + node_base, 0, (size_t)M * 4, s));
         k_lvl_nodes<<<blocks_for(n, BS), BS, 0, s>>>(n, keys, leaf_tmp, head, excl, Hs, level, kl, node_base,
-                                                     nid, nd_start, nd_count, nd_hmax, nd_box, nd_level,
-                                                     nd_coord, box_G);
+                                                     nid, nd_start, nd_count, nd_hmax, nd_wide, nd_box, nd_level,
+                                                     nd_coord, box_G, box_len, (float)c->prm.cell_ratio);
         SPH_HIP(hipGetLastError());
         if (level == 0) {
             k_top_table<<<blocks_for(M, BS), BS, 0, s>>>(M, nd_box, nd_coord, box_G, box_top_base, top);
@@ -586,8 +633,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         uint32_t* nflag = ensure<uint32_t>(c, c->nflag, M + 1);
         uint32_t* nscan = ensure<uint32_t>(c, c->nscan, M + 1);
         k_lvl_decide<<<blocks_for(M, BS), BS, 0, s>>>(M, node_base, level, c->levels, c->prm.leaf_target,
-                                                      (float)c->prm.cell_ratio, nd_count, nd_hmax, nd_box,
-                                                      box_len, box_G, nflag, nd_child0, nd_child1);
+                                                      nd_count, nd_wide, nflag, nd_child0, nd_child1);
         SPH_HIP(hipGetLastError());
         scan_exclusive(c, nflag, nscan, M, d_tot, s);
         const int64_t K = read_u32(d_tot, s);
@@ -663,11 +709,9 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
         uint32_t* sva = ensure<uint32_t>(c, c->sched_val_alt, nl);
         const bool by_cost = c->prm.cell_order == 0;
-        if (by_cost) {
-            k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv);
-            SPH_HIP(hipGetLastError());
-            radix_sort(c, sk, sv, ska, sva, nl, 32, s);
-        }
+        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv, ctr);
+        SPH_HIP(hipGetLastError());
+        if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, 32, s);
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
         k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, lf_start, lf_count, p_start,
@@ -681,6 +725,15 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_sorted_fill<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<double*>(c->pos_w.p), leaf_of, lf_node,
                                                    nd_coord, nd_level, nd_box, box_G, box_len, pos_s, xrel);
     SPH_HIP(hipGetLastError());
+    {
+        const int64_t* hc = read_counters(c, s);
+        c->binfo.n_cells = nl;
+        c->binfo.n_pairs = c->n_pairs;
+        c->binfo.candidate_pairs = hc[CT_B_CAND_PAIRS];
+        c->binfo.max_cell_particles = hc[CT_B_MAX_NI];
+        c->binfo.max_neighbour_cells = hc[CT_B_MAX_NP];
+        c->binfo.max_candidates = hc[CT_B_MAX_NJ];
+    }
     c->built = true;
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;

@@ -64,6 +64,10 @@ enum {
     CT_BAD_INPUT = 7,    // non-finite or non-positive inputs seen by a kernel
     CT_DENS_SWEEP_INTER = 8,  // pairs inside the trial h, summed over every evaluation
     CT_NEED_SCAN = 9,    // particles left to the re-scanning density kernel
+    CT_B_CAND_PAIRS = 10,  // build: sum over leaves of particles x candidates
+    CT_B_MAX_NI = 11,      // build: largest leaf (max)
+    CT_B_MAX_NP = 12,      // build: longest neighbour-cell list (max)
+    CT_B_MAX_NJ = 13,      // build: most candidates of a leaf (max)
     CT_SUMS = 16,        // entries [0, CT_SUMS) have spread slots
     // single entries
     CT_TOTAL = 16,       // scratch for device-computed totals read by the host
@@ -105,12 +109,15 @@ __device__ inline double* cons_slot(double* cons, int n_boxes)
     return cons + (int64_t)(blockIdx.x % CONS_SLOTS) * 4 * n_boxes;
 }
 
-// Raise CT_SWEEPS to the largest v of the wavefront (all lanes active).
-__device__ inline void ctr_wave_max_sweeps(int64_t* ctr, int64_t v)
+// Raise maximum k (CT_SWEEPS or a CT_B_MAX_* entry) to the largest v of the
+// wavefront (all lanes active).
+__device__ inline void ctr_wave_max(int64_t* ctr, int k, int64_t v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = max(v, (int64_t)__shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctr_slot(ctr)[CT_SWEEPS], (unsigned long long)v);
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long*)&ctr_slot(ctr)[k], (unsigned long long)v);
 }
+
+__device__ inline void ctr_wave_max_sweeps(int64_t* ctr, int64_t v) { ctr_wave_max(ctr, CT_SWEEPS, v); }
 
 struct sph_ctx {
     sph_params prm{};
@@ -146,7 +153,7 @@ struct sph_ctx {
     sph::Buf head, scan1;    // uint32 per particle
     sph::Buf nid;            // int per particle: node at the current level
     // nodes (all levels, level-major)
-    sph::Buf nd_start, nd_count, nd_hmax, nd_child0, nd_child1, nd_leaf, nd_box, nd_level, nd_coord;
+    sph::Buf nd_start, nd_count, nd_hmax, nd_wide, nd_child0, nd_child1, nd_leaf, nd_box, nd_level, nd_coord;
     int64_t node_cap = 0;
     sph::Buf nflag, nscan;   // per-node temporaries of one level
     sph::Buf top;            // int: node of each (box, top cell), -1 if empty
@@ -187,6 +194,7 @@ struct sph_ctx {
     int n_cu = 256;
     hipEvent_t ev[9] = {};
     sph_timings tm{};
+    sph_build_info binfo{};
 
     // ---- the captured density + force pass (sph_pass) -----------------------------
     int64_t layout_serial = 0;           // bumped by every reallocation and every build
@@ -317,7 +325,10 @@ inline const int64_t* read_counters(sph_ctx* c, hipStream_t s)
     int64_t* h = c->h_counters;
     for (int sl = 0; sl < CT_SPREAD_SLOTS; ++sl) {
         const int64_t* p = h + CT_SPREAD + sl * CT_SUMS;
-        for (int k = 0; k < CT_SUMS; ++k) h[k] = k == CT_SWEEPS ? std::max(h[k], p[k]) : h[k] + p[k];
+        for (int k = 0; k < CT_SUMS; ++k) {
+            const bool is_max = k == CT_SWEEPS || k == CT_B_MAX_NI || k == CT_B_MAX_NP || k == CT_B_MAX_NJ;
+            h[k] = is_max ? std::max(h[k], p[k]) : h[k] + p[k];
+        }
     }
     return h;
 }

@@ -306,16 +306,12 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         // candidate has this mass, so has every particle of the cell
         const float m0 = ni > 0 ? A.jd[i0].w : 0.0f;
         int n_flag = 0;  // this lane's particles of the cell left to the re-scan
-        if (np_all > 64) {
-            // very long neighbour-cell lists take the general staging
-            n_flag = flag_for_scan(A, i0, 0, ni);
-            enqueue_scan(A, slot, n_flag);
-            n_scan += n_flag;
-            continue;
-        }
-        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
-        const int nj = nb.nj;
-        const bool resident = nj <= TCAP;
+        NbrCursor cu;
+        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        // resident: one block of neighbour records and at most TCAP candidates,
+        // staged once at fixed tile slots of DCH
+        const bool resident = np_all <= 64 && nj <= TCAP;
         const int lpi = choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH);
         const int per_pass = 64 / lpi;
         const int g = lane / lpi;
@@ -339,15 +335,23 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
                 const bool stream = !(resident && loaded);
                 ChunkRegs<1, DCH> R;
-                if (stream) fetch_chunk(R, A.jd, nb, 0, min(DCH, nj));
-                for (int c0 = 0; c0 < nj; c0 += DCH) {
-                    const int len = min(DCH, nj - c0);
+                if (stream) {
+                    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
+                    fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH));
+                }
+                int len;
+                for (int c0 = 0; c0 < nj; c0 += len) {
+                    len = stream ? R.len : min(DCH, nj - c0);
                     const float4* tc = resident ? sj + c0 : sj;
                     if (stream) {
                         mixed |= chunk_mass_differs(R, m0);
                         // store this chunk (padded to DCH), put the next in flight
                         commit_chunk_padded(sj + (resident ? c0 : 0), R);
-                        if (c0 + DCH < nj) fetch_chunk(R, A.jd, nb, c0 + DCH, min(DCH, nj - c0 - DCH));
+                        const int nx = c0 + len;
+                        if (nx < nj) {
+                            cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
+                            fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH));
+                        }
                     }
                     if (lpi == 2)
                         scan_chunk<2>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
@@ -454,12 +458,12 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         if (k >= n_queued) break;
         const int4 ci = A.cells[A.scan_cells[k]];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
-        // up to 64 neighbour cells: one per lane, chunks staged with independent loads
-        const bool few = np_all <= 64;
-        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, min(np_all, 64));
-        const int nj = few ? nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        // neighbour records 64 at a time, chunks staged with independent loads
+        NbrCursor cu;
+        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
         const Groups G = make_groups(ni);
-        const bool single_tile = nj <= SCAP;
+        const bool single_tile = np_all <= 64 && nj <= SCAP;
         bool loaded = false;
         for (int ib = 0; ib < ni; ib += G.per_pass) {
             const int gi = ib + G.g;
@@ -477,14 +481,14 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                 S0 = S1 = M0 = M1 = 0.f;
                 cnt = 0;
                 const int groups_now = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
-                for (int c0 = 0; c0 < nj; c0 += SCAP) {
-                    const int len = min(SCAP, nj - c0);
-                    if (!(single_tile && loaded)) {
-                        if (few)
-                            stage_fast<1, SCAP>(sj, A.jd, nb, c0, len);
-                        else
-                            stage_tile<1>(sj, A.jd, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0,
-                                          len);
+                int len;
+                for (int c0 = 0; c0 < nj; c0 += len) {
+                    if (single_tile && loaded) {
+                        len = nj;
+                    } else {
+                        cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
+                        len = cursor_chunk(cu, c0, SCAP);
+                        stage_fast<1, SCAP>(sj, A.jd, cu.nb, c0 - cu.off0, len);
                         loaded = true;
                     }
                     for (int k = G.sub; k < len; k += G.lpi) {

@@ -118,10 +118,10 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         const int slot = a_cur++;
         const int4 ci = A.cells[slot];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
-        const bool fastnb = np_all <= 64;
-        const NbrLanes nb = load_nbr(A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, min(np_all, 64));
-        const int nj = fastnb ? nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
-        const bool single_tile = nj <= FCAP;
+        NbrCursor cu;  // neighbour records 64 at a time
+        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        const bool single_tile = np_all <= 64 && nj <= FCAP;
         const int lpi = choose_lpi(ni, nj, 2, A.list_work, single_tile, FCAP);
         const int per_pass = 64 / lpi;
         const int g = lane / lpi;
@@ -142,18 +142,21 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             int cnt = 0;
             ChunkRegs<3, FCAP> R;
             const bool stream_chunks = !(single_tile && loaded);
-            if (fastnb && stream_chunks) fetch_chunk(R, A.jf, nb, 0, min(FCAP, nj));
-            for (int c0 = 0; c0 < nj; c0 += FCAP) {
-                const int len = min(FCAP, nj - c0);
+            if (stream_chunks) {
+                cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
+                fetch_chunk(R, A.jf, cu.nb, 0, cursor_chunk(cu, 0, FCAP));
+            }
+            int len;
+            for (int c0 = 0; c0 < nj; c0 += len) {
+                len = stream_chunks ? R.len : nj;
                 if (stream_chunks) {
-                    if (fastnb) {
-                        // store this chunk, then put the next one in flight while
-                        // this one is computed
-                        commit_chunk(sj, R);
-                        if (c0 + FCAP < nj) fetch_chunk(R, A.jf, nb, c0 + FCAP, min(FCAP, nj - c0 - FCAP));
-                    } else {
-                        stage_tile<3>(sj, A.jf, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all, c0, len,
-                                      FCAP);
+                    // store this chunk, then put the next one in flight while
+                    // this one is computed
+                    commit_chunk(sj, R);
+                    const int nx = c0 + len;
+                    if (nx < nj) {
+                        cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
+                        fetch_chunk(R, A.jf, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, FCAP));
                     }
                     pad_tile(sj, len, FCAP);
                     loaded = true;

@@ -160,57 +160,6 @@ __device__ __forceinline__ int count_candidates(const int* __restrict__ p_leaf, 
     return nj;
 }
 
-// Copy candidates [c0, c0 + len) of the cell's flattened neighbour list into
-// the wave's tile, shifted into the cell's frame. Each particle occupies NF
-// float4 slots (tile layout [slot][candidate]); only slot 0's xyz is shifted.
-// Partner records are read 64 at a time, one per lane, and broadcast with lane
-// shuffles.
-template <int NF>
-__device__ __forceinline__ void stage_tile(float4* sj, const float4* __restrict__ jd, const int* __restrict__ p_leaf,
-                                           const float4* __restrict__ p_shift, const int* __restrict__ lf_start,
-                                           const int* __restrict__ lf_count, int pb0, int np_all, int c0, int len,
-                                           int cap = 0)
-{
-    const int lane = threadIdx.x & 63;
-    int off = 0;
-    for (int b0 = 0; b0 < np_all && off < c0 + len; b0 += 64) {
-        const int q = b0 + lane;
-        int bs = 0, bc = 0;
-        float4 sh = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (q < np_all) {
-            const int bl = p_leaf[pb0 + q];
-            bs = lf_start[bl];
-            bc = lf_count[bl];
-            sh = p_shift[pb0 + q];
-        }
-        const int npb = min(64, np_all - b0);
-        for (int k = 0; k < npb; ++k) {
-            const int bck = __shfl(bc, k, 64);
-            const int lo = max(c0, off), hi = min(c0 + len, off + bck);
-            if (lo < hi) {
-                const int bsk = __shfl(bs, k, 64);
-                const float sx = __shfl(sh.x, k, 64);
-                const float sy = __shfl(sh.y, k, 64);
-                const float sz = __shfl(sh.z, k, 64);
-                for (int t = lo + lane; t < hi; t += 64) {
-                    const int64_t src = (int64_t)NF * (bsk + (t - off));
-                    float4 v = jd[src];
-                    v.x += sx;
-                    v.y += sy;
-                    v.z += sz;
-                    sj[t - c0] = v;
-#pragma unroll
-                    for (int f = 1; f < NF; ++f) sj[f * cap + (t - c0)] = jd[src + f];
-                }
-            }
-            off += bck;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Neighbour-cell records of a cell with at most 64 neighbour cells, one per
 // lane: first particle, count, exclusive prefix of the counts (the cell's
 // offset in the flattened candidate list) and the shift into the cell frame.
@@ -248,6 +197,48 @@ __device__ __forceinline__ NbrLanes load_nbr(const int* __restrict__ p_leaf, con
     nb.nj = __shfl(inc, 63, 64);
     nb.np = np;
     return nb;
+}
+
+// The flattened candidate list of a cell, walked in increasing order: the
+// neighbour-cell records are held 64 at a time (one NbrLanes block), and a
+// chunk never spans two blocks, so any number of neighbour cells is staged
+// with the independent loads of fetch_chunk / stage_fast and every record is
+// read once per sweep. Candidates before the current block: off0.
+struct NbrCursor {
+    NbrLanes nb;
+    int b0, off0;  // first record of the block, candidates before it
+    int pb0, np_all;
+};
+
+__device__ __forceinline__ void cursor_init(NbrCursor& cu, const int* __restrict__ p_leaf,
+                                            const float4* __restrict__ p_shift, const int* __restrict__ lf_start,
+                                            const int* __restrict__ lf_count, int pb0, int np_all)
+{
+    cu.pb0 = pb0;
+    cu.np_all = np_all;
+    cu.b0 = 0;
+    cu.off0 = 0;
+    cu.nb = load_nbr(p_leaf, p_shift, lf_start, lf_count, pb0, min(np_all, 64));
+}
+
+// Move the cursor to the block holding candidate c (c at or after the
+// current block's start; back to the first block when c is before it).
+__device__ __forceinline__ void cursor_seek(NbrCursor& cu, const int* __restrict__ p_leaf,
+                                            const float4* __restrict__ p_shift, const int* __restrict__ lf_start,
+                                            const int* __restrict__ lf_count, int c)
+{
+    if (c < cu.off0) cursor_init(cu, p_leaf, p_shift, lf_start, lf_count, cu.pb0, cu.np_all);
+    while (c >= cu.off0 + cu.nb.nj && cu.b0 + 64 < cu.np_all) {
+        cu.off0 += cu.nb.nj;
+        cu.b0 += 64;
+        cu.nb = load_nbr(p_leaf, p_shift, lf_start, lf_count, cu.pb0 + cu.b0, min(cu.np_all - cu.b0, 64));
+    }
+}
+
+// Length of the chunk that starts at candidate c (cursor on c's block).
+__device__ __forceinline__ int cursor_chunk(const NbrCursor& cu, int c, int cap)
+{
+    return min(cap, cu.off0 + cu.nb.nj - c);
 }
 
 // A chunk of candidates in flight: the loads of stage_fast split from the LDS

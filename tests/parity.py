@@ -64,3 +64,27 @@ def oracle_sample(d: dict, targets, radius: float, box: int = 0) -> dict:
                       targets=np.asarray(targets, dtype=np.int64))
     r.update(fo)
     return r
+
+
+def oracle_sample_exact(d: dict, targets, h_near, box: int = 0) -> dict:
+    """Like oracle_sample, but the sample is every particle j that pairs with a
+    target i (r_ij < max(h_i, h_j), with 2% slack), found from the smoothing
+    lengths h_near (any close estimate, e.g. the GPU's; they only choose the
+    sample, the oracle solves its own h). Suits sets whose h spans decades,
+    where one radius would either miss neighbours or take most of the box."""
+    s, e = int(d["box_first"][box]), int(d["box_first"][box + 1])
+    L = float(d["box_len"][box])
+    pos = np.mod(d["pos"][s:e], L)
+    hn = np.asarray(h_near[s:e], dtype=np.float64) * 1.02
+    targets = np.asarray(targets, dtype=np.int64)
+    # j within its own h of some target (scipy takes one radius per query point)
+    hits = cKDTree(pos[targets], boxsize=L).query_ball_point(pos, hn, return_length=True)
+    # j within the target's h
+    near = cKDTree(pos, boxsize=L).query_ball_point(pos[targets], hn[targets])
+    need = np.unique(np.concatenate([targets, np.nonzero(hits)[0]] + [np.asarray(x, dtype=np.int64) for x in near]))
+    r = oracle.density(pos, d["mass"][s:e], L, targets=need, h_start=d["h0"][s:e])
+    fo = oracle.force(pos, d["vel"][s:e], d["mass"][s:e], d["u"][s:e], r["h"], r["rho"], r["f"], L,
+                      targets=targets)
+    r.update(fo)
+    r["n_sample"] = len(need)
+    return r

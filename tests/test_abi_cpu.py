@@ -45,9 +45,9 @@ def test_status_strings_and_version(lib):
 
 def test_struct_layouts_match_header(lib):
     # the ctypes mirrors must have the sizes the C compiler gave the structs
-    for which, mirror in enumerate((sph.sph_params, sph.sph_stats, sph.sph_timings)):
+    for which, mirror in enumerate((sph.sph_params, sph.sph_stats, sph.sph_timings, sph.sph_build_info)):
         assert lib.sph_struct_size(which) == ctypes.sizeof(mirror), mirror.__name__
-    assert lib.sph_struct_size(3) == -1
+    assert lib.sph_struct_size(4) == -1
     assert ctypes.sizeof(sph.sph_stats) == 80
 
 

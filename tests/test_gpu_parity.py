@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads
-from parity import TOL32, TOL64, assert_within, errors, oracle_sample
+from parity import TOL32, TOL64, assert_within, errors, oracle_sample, oracle_sample_exact
 
 pytestmark = pytest.mark.gpu
 
@@ -222,3 +222,65 @@ def test_empty_box_in_batch(gpu_lib):
     r = oracle.run(d)
     assert_within(errors(g, r), TOL32, "empty box")
     assert np.all(g["cons"][1] == 0.0)
+
+
+def _gpu_pass(sph, d, **params):
+    """Build, then one sph_pass (the launch sequence the benchmark times)."""
+    import torch
+    t = {k: torch.from_numpy(d[k]).cuda() for k in ("pos", "h0", "mass", "vel", "u")}
+    ctx = sph.Context(0, **params)
+    try:
+        ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
+        h = t["h0"].clone()
+        nw = torch.empty_like(h)
+        r = ctx.pass_(t["mass"], h, t["vel"], t["u"], nw=nw)
+        torch.cuda.synchronize()
+        out = {k: r[k].double().cpu().numpy() for k in ("h", "rho", "f", "nw", "acc", "dudt")}
+        out["stats"] = r["stats"]
+        return out
+    finally:
+        ctx.close()
+
+
+def test_batched_full_size_sampled(gpu_lib):
+    """All 256 boxes (about 7M particles) in one pass; a seeded sample of
+    particles in four boxes against the oracle."""
+    import time
+    t0 = time.time()
+    d = workloads.batched()
+    print("batched N", d["pos"].shape[0], "generated in %.1f s" % (time.time() - t0), flush=True)
+    t0 = time.time()
+    g = _gpu_pass(gpu_lib, d)
+    print("batched GPU pass %.1f s" % (time.time() - t0), g["stats"], flush=True)
+    rng = np.random.default_rng([1508, 3, 99])
+    for b in rng.choice(len(d["box_len"]), 4, replace=False):
+        s, e = int(d["box_first"][b]), int(d["box_first"][b + 1])
+        targets = np.sort(rng.choice(e - s, 64, replace=False))
+        r = oracle_sample_exact(d, targets, g["h"], box=int(b))
+        gb = {k: g[k][s:e] for k in ("h", "rho", "f", "nw", "acc", "dudt")}
+        err = errors(gb, r, targets)
+        print("batched box", int(b), e - s, err, flush=True)
+        assert_within(err, TOL32, "batched box %d" % b)
+
+
+def test_large_full_size_sampled(gpu_lib):
+    """The 2^24-particle log-normal set (h over ~1.5 decades) in one pass; a
+    seeded sample against the oracle, with every pair partner of the sample
+    solved by the oracle too."""
+    import time
+    t0 = time.time()
+    d = workloads.lognormal()
+    n = d["pos"].shape[0]
+    print("large N", n, "generated in %.1f s" % (time.time() - t0), flush=True)
+    t0 = time.time()
+    g = _gpu_pass(gpu_lib, d)
+    print("large GPU pass %.1f s" % (time.time() - t0), g["stats"], flush=True)
+    assert g["stats"]["unconverged"] == 0
+    rng = np.random.default_rng([1508, 4, 99])
+    targets = np.sort(rng.choice(n, 48, replace=False))
+    t0 = time.time()
+    r = oracle_sample_exact(d, targets, g["h"])
+    print("large oracle sample of %d in %.1f s" % (r["n_sample"], time.time() - t0), flush=True)
+    err = errors(g, r, targets)
+    print("large sample", r["n_sample"], err, g["stats"], flush=True)
+    assert_within(err, TOL32, "large")

@@ -288,3 +288,20 @@ def test_targets_subset_matches_full():
     assert np.array_equal(sub["h"][idx], full["h"][idx])
     fo = oracle.force(d["pos"], d["vel"], d["mass"], d["u"], full["h"], full["rho"], full["f"], targets=idx)
     assert np.array_equal(fo["acc"][idx], full["acc"][idx])
+
+
+def test_sampled_oracle_reproduces_full_run():
+    """The sampled oracle used by the full-size GPU tests: solving h only for
+    the targets and their pair partners gives the full run's values there."""
+    from parity import oracle_sample_exact
+    d = workloads.lognormal(n_mesh=32, sigma_ln=1.2)
+    full = oracle.run(d)
+    targets = np.sort(np.random.default_rng(5).choice(d["pos"].shape[0], 40, replace=False))
+    r = oracle_sample_exact(d, targets, full["h"])
+    assert r["n_sample"] < d["pos"].shape[0]
+    for k in ("h", "rho", "f"):
+        np.testing.assert_allclose(r[k][targets], full[k][targets], rtol=1e-12)
+    np.testing.assert_allclose(r["acc"][targets], full["acc"][targets], rtol=1e-9,
+                               atol=1e-12 * np.abs(full["acc"]).max())
+    np.testing.assert_allclose(r["dudt"][targets], full["dudt"][targets], rtol=1e-9,
+                               atol=1e-12 * np.abs(full["dudt"]).max())
