@@ -312,8 +312,10 @@ def main() -> int:
         "speedup_vs_fp64_plain": value / value64,
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
-        "autotune": None if tuned is None else [
-            {**t["params"], "ms": t["ms"], "rebuilds": t.get("rebuilds")} for t in tuned["table"]],
+        "autotune_top5": None if tuned is None else [
+            {**t["params"], "ms": t["ms"], "rebuilds": t.get("rebuilds")}
+            for t in sorted((t for t in tuned["table"] if t["ms"] is not None), key=lambda t: t["ms"])[:5]],
+        "autotune_settings": None if tuned is None else len(tuned["table"]),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)

@@ -102,7 +102,10 @@ typedef struct {
     int32_t cell_order;   /* order cells reach wavefronts: 0 = by decreasing cost,
                              dealt out to the 8 XCDs (balance; default);
                              1 = Morton order, a contiguous range per XCD
-                             (neighbouring cells share an XCD's L2) */
+                             (neighbouring cells share an XCD's L2);
+                             2 = the Morton ranges of 1, each ordered by
+                             decreasing cost (L2 locality and a short tail);
+                             other values mean 0 */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP

@@ -28,7 +28,7 @@ sph_params with_defaults(const sph_params* in)
     if (p.schedule != 1) p.schedule = 0;
     if (p.queue_batch <= 0) p.queue_batch = 4;
     if (p.tile_cap != 256 && p.tile_cap != 512) p.tile_cap = 128;
-    if (p.cell_order != 1) p.cell_order = 0;
+    if (p.cell_order != 1 && p.cell_order != 2) p.cell_order = 0;
     return p;
 }
 

@@ -422,10 +422,12 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
 // Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
 // Cost of each leaf's cell tasks (particles x candidates) as a sort key that
 // orders by decreasing cost (positive floats order like their bit patterns).
-// Also the build's shape counters (CT_B_*).
+// xcd_local: the key is prefixed with the XCD whose Morton range holds the
+// leaf (leaves are in Morton order), so the sort keeps each XCD's range
+// together and orders it by cost. Also the build's shape counters (CT_B_*).
 __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
-                            const int* __restrict__ p_leaf, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                            int64_t* __restrict__ ctr)
+                            const int* __restrict__ p_leaf, int xcd_local, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals, int64_t* __restrict__ ctr)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int ni = 0, np = 0, nj = 0;
@@ -434,7 +436,10 @@ __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const 
         np = (int)(p_start[a + 1] - p_start[a]);
         for (uint32_t p = p_start[a]; p < p_start[a + 1]; ++p) nj += lf_count[p_leaf[p]];
         const float cost = (float)ni * (float)nj;
-        keys[a] = 0xffffffffull - __float_as_uint(cost);
+        uint64_t x = 0;
+        if (xcd_local)
+            while (x < 7 && a >= sph::xcd_start(nl, (int)x + 1)) ++x;
+        keys[a] = (x << 32) | (0xffffffffull - __float_as_uint(cost));
         vals[a] = (uint32_t)a;
     }
     ctr_wave_add(ctr, CT_B_CAND_PAIRS, (int64_t)ni * nj);
@@ -443,10 +448,12 @@ __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const 
     ctr_wave_max(ctr, CT_B_MAX_NJ, nj);
 }
 
-// Schedule slots. by_cost != null: the leaf of cost rank r goes to slot
-// xcd_start(nl, r % 8) + r / 8. by_cost == null: slot r holds leaf r (Morton
-// order, so each XCD takes a contiguous range of neighbouring cells).
-__global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, const int* __restrict__ lf_start,
+// Schedule slots. by_cost != null and deal: the leaf of cost rank r goes to
+// slot xcd_start(nl, r % 8) + r / 8. by_cost != null, no deal: slot r holds
+// the leaf of rank r (the ranks already group each XCD's range). by_cost ==
+// null: slot r holds leaf r (Morton order, so each XCD takes a contiguous
+// range of neighbouring cells).
+__global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, int deal, const int* __restrict__ lf_start,
                              const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
                              const int* __restrict__ lf_node, const int* __restrict__ nd_box, int4* __restrict__ cells,
                              int2* __restrict__ cell_aux)
@@ -454,7 +461,7 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, c
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nl) return;
     const int a = by_cost ? (int)by_cost[r] : (int)r;
-    const int64_t slot = by_cost ? sph::xcd_start(nl, (int)(r & 7)) + (r >> 3) : r;
+    const int64_t slot = by_cost && deal ? sph::xcd_start(nl, (int)(r & 7)) + (r >> 3) : r;
     cells[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)(p_start[a + 1] - p_start[a]));
     cell_aux[slot] = make_int2(a, nd_box[lf_node[a]]);
 }
@@ -702,19 +709,23 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
                                                  p_cnt, p_start, p_leaf, p_shift, p_code, ctr);
     SPH_HIP(hipGetLastError());
 
-    // ---- work schedule: leaves by decreasing cost dealt out to the XCDs, or Morton ranges ---------
+    // ---- work schedule: leaves by decreasing cost dealt out to the XCDs, Morton ranges, or Morton
+    //      ranges each ordered by decreasing cost --------------------------------------------------
     {
         uint64_t* sk = ensure<uint64_t>(c, c->sched_key, nl);
         uint64_t* ska = ensure<uint64_t>(c, c->sched_key_alt, nl);
         uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
         uint32_t* sva = ensure<uint32_t>(c, c->sched_val_alt, nl);
-        const bool by_cost = c->prm.cell_order == 0;
-        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, sk, sv, ctr);
+        const int order = c->prm.cell_order;
+        const bool by_cost = order != 1;
+        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, order == 2 ? 1 : 0, sk, sv,
+                                                      ctr);
         SPH_HIP(hipGetLastError());
-        if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, 32, s);
+        if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, order == 2 ? 35 : 32, s);
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
-        k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, lf_start, lf_count, p_start,
+        k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, order == 0 ? 1 : 0, lf_start,
+                                                       lf_count, p_start,
                                                        lf_node, nd_box, cells, cell_aux);
         SPH_HIP(hipGetLastError());
     }

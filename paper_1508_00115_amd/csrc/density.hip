@@ -68,6 +68,7 @@ struct DensArgs {
     int* scan_cells;         // schedule slots queued for k_density_scan (ctr[CT_SCAN_CELLS] of them)
     WorkSched W;             // which wavefront takes which cell
     float target;            // S0 = sum w(q) at the root: 3 n_ngb / 32
+    float inv_target;        // 1 / target
     float tol;               // on |S0 / target - 1|
     int max_iter;
     int lpi_min;             // fewest lanes per particle (a power of two): spreads a list over enough slots
@@ -144,10 +145,12 @@ __device__ __forceinline__ HSolve hsolve_init(float h, float Hi, bool done, uint
 // against ln h (exact where S0 ~ h^slope), bisection when the step leaves the
 // bracket. Stops on |S0/target - 1| <= tol, on a step below FP32 resolution of
 // h, on a root beyond the search radius (overflow) or after max_iter.
-__device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float target, float tol, int max_iter)
+// Quotients use the hardware reciprocal (1 ulp): they only steer the steps,
+// and the tests above are far coarser.
+__device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float inv_target, float tol, int max_iter)
 {
     ++s.nev;
-    const float ratio = S0 / target;
+    const float ratio = S0 * inv_target;
     if (fabsf(ratio - 1.0f) <= tol) {
         s.done = true;
         s.state = ST_DONE;
@@ -164,8 +167,8 @@ __device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float
         s.state = ST_OVERFLOW;
         return;
     }
-    const float slope = -S1 / S0;  // d ln S0 / d ln h
-    float hn = slope > 0.05f ? s.h * __expf(-__logf(ratio) / slope) : 2.0f * s.h;
+    const float slope = -S1 * __builtin_amdgcn_rcpf(S0);  // d ln S0 / d ln h
+    float hn = slope > 0.05f ? s.h * __expf(-__logf(ratio) * __builtin_amdgcn_rcpf(slope)) : 2.0f * s.h;
     if (hn >= s.hi) hn = s.hi_known ? 0.5f * (s.h + s.hi) : s.Hi;
     if (hn <= s.lo) hn = 0.5f * (s.lo + s.h);
     if (fabsf(hn - s.h) <= 2.5e-7f * s.h) {
@@ -197,9 +200,9 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSo
     // counters in a scratch array behind a pointer select)
     n_over += s.state == ST_OVERFLOW ? 1 : 0;
     n_unconv += s.state == ST_UNCONVERGED ? 1 : 0;
-    const float hinv = 1.0f / s.h;
+    const float hinv = __builtin_amdgcn_rcpf(s.h);
     const float rho = (8.0f / SPH_PI_F) * M0 * hinv * hinv * hinv;
-    const float f = M1 < 0.0f ? -3.0f * M0 / M1 : 1.0f;
+    const float f = M1 < 0.0f ? -3.0f * M0 * __builtin_amdgcn_rcpf(M1) : 1.0f;
     A.hs[i] = s.h;
     A.rhos[i] = rho;
     A.fs[i] = f;
@@ -213,11 +216,12 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSo
     max_ev = max(max_ev, s.nev);
 }
 
-__device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_acc, int64_t inter_acc,
-                                               int64_t sweep_acc, int64_t n_over, int64_t n_unconv, int max_ev,
-                                               int64_t n_scan)
+__device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_acc, int64_t list_acc,
+                                               int64_t inter_acc, int64_t sweep_acc, int64_t n_over,
+                                               int64_t n_unconv, int max_ev, int64_t n_scan)
 {
     ctr_add_uniform(A.ctr, CT_DENS_CAND, cand_acc);  // already a wavefront total
+    ctr_wave_add(A.ctr, CT_DENS_CAND, list_acc);
     ctr_wave_add(A.ctr, CT_DENS_INTER, inter_acc);
     ctr_wave_add(A.ctr, CT_DENS_SWEEP_INTER, sweep_acc);
     ctr_wave_add(A.ctr, CT_OVERFLOW, n_over);
@@ -244,7 +248,7 @@ __device__ __forceinline__ int flag_for_scan(const DensArgs& A, int i0, int firs
 // a particle of its cell.
 __device__ __forceinline__ void enqueue_scan(const DensArgs& A, int slot, int n_flag)
 {
-    if (wave_sum_i(n_flag) > 0 && (threadIdx.x & 63) == 0) {
+    if (__any(n_flag > 0) && (threadIdx.x & 63) == 0) {
         const int64_t k = (int64_t)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_CELLS], 1ull);
         A.scan_cells[k] = slot;
     }
@@ -258,12 +262,15 @@ __device__ __forceinline__ void enqueue_scan(const DensArgs& A, int slot, int n_
 // its list. The chunk is padded with far positions up to a multiple of the
 // group's stride (commit_chunk_padded), so there is no bounds test; four tile
 // reads (x, y, z only) are in flight at once and the appends are branch-free
-// (the store always happens, the slot only advances on a hit).
+// (the store always happens, the slot only advances on a hit). The slot is
+// kept as a byte offset into the lists (o, advancing by one row of 64
+// floats per hit) and clamped to the lane's spare slot (o_cap).
 template <int LPI>
 __device__ __forceinline__ void scan_chunk(const float4* tc, int len, float xx, float xy, float xz, float H2,
-                                           float* lst, int& nl)
+                                           float* lists, unsigned& o, unsigned o_cap)
 {
     const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
+    char* base = reinterpret_cast<char*>(lists);
     for (int k0 = 0; k0 < len_pad; k0 += 4 * LPI, tc += 4 * LPI) {
         float3 pj[4];
 #pragma unroll
@@ -272,8 +279,8 @@ __device__ __forceinline__ void scan_chunk(const float4* tc, int len, float xx, 
         for (int u = 0; u < 4; ++u) {
             const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            lst[min(nl, DSLOTS) * 64] = r2;
-            nl += r2 < H2 ? 1 : 0;
+            *reinterpret_cast<float*>(base + min(o, o_cap)) = r2;
+            o += r2 < H2 ? 256u : 0u;
         }
     }
 }
@@ -291,10 +298,11 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
     const int lane = threadIdx.x & 63;
     float4* sj = tile;
     float* lst = lists + lane;
+    const unsigned o_lane = 4u * (unsigned)lane, o_cap = o_lane + 256u * DSLOTS;
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0;  // wave-uniform
     // per-lane counts (far below 2^31 for any particle count that fits a GPU)
-    int inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0;
+    int inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0, list_acc = 0;
     int max_ev = 0;
 
     for (;;) {
@@ -313,8 +321,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         // staged once at fixed tile slots of DCH
         const bool resident = np_all <= 64 && nj <= TCAP;
         const int lpi = choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH);
-        const int per_pass = 64 / lpi;
-        const int g = lane / lpi;
+        const int lg = __builtin_ctz(lpi);
+        const int per_pass = 64 >> lg;
+        const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
         bool loaded = false;  // (resident) every candidate is in the tile
         bool mixed = false;   // a candidate with another mass was staged
@@ -326,11 +335,11 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float4 xi = A.jd[i];
             const uint8_t st0 = A.st_s[i];
             HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_ACTIVE, st0);
-            const int active_groups = wave_sum_i((!s.done && sub == 0) ? 1 : 0);
+            const int active_groups = wave_count(!s.done && sub == 0);
             if (active_groups == 0) continue;
 
             // ---- phase A: squared distances inside the search radius -----------
-            int nl = 0;
+            unsigned o = o_lane;  // byte offset of this lane's next list slot
             {
                 const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
                 const bool stream = !(resident && loaded);
@@ -354,18 +363,19 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                         }
                     }
                     if (lpi == 2)
-                        scan_chunk<2>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                        scan_chunk<2>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else if (lpi == 4)
-                        scan_chunk<4>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                        scan_chunk<4>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else if (lpi == 8)
-                        scan_chunk<8>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                        scan_chunk<8>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else
-                        scan_chunk<16>(tc + sub, len, xi.x, xi.y, xi.z, H2, lst, nl);
+                        scan_chunk<16>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     if (!resident) wave_sync_lds();
                 }
                 loaded = true;
                 cand_acc += (int64_t)active_groups * nj;
             }
+            const int nl = (int)((o - o_lane) >> 8);
             if (mixed) {
                 // lists hold no masses: the cell's remaining particles re-scan
                 // (every candidate is staged in the first pass that streams,
@@ -391,7 +401,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             // r^2 -> r once, so that no evaluation takes a square root
             for (int e = 0, len_l = s.done ? 0 : nl; e < len_l; ++e) lst[e * 64] = __builtin_amdgcn_sqrtf(lst[e * 64]);
             while (__any(!s.done)) {
-                const float hinv = 1.0f / s.h;
+                const float hinv = __builtin_amdgcn_rcpf(s.h);
                 cnt = 0;
                 const int len_l = s.done ? 0 : nl;
                 // w(q) = 2 t^3 - 8 u^3 and q w'(q) = q (24 u^2 - 6 t^2) with
@@ -415,7 +425,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 }
                 S0 = fmaf(2.0f, At, -8.0f * Au);
                 S1 = fmaf(24.0f, Bu, -6.0f * Bt);
-                cand_acc += wave_sum_i(len_l);
+                list_acc += len_l;
                 S0 = group_sum(S0, lpi);
                 S1 = group_sum(S1, lpi);
                 cnt = group_sum_i(cnt, lpi);
@@ -424,7 +434,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 fS0 = S0;
                 fS1 = S1;
                 fcnt = cnt;
-                hsolve_step(s, S0, S1, A.target, A.tol, A.max_iter);
+                hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
             }
             if (valid && sub == 0 && st0 == ST_ACTIVE && fits)
                 write_result(A, i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
@@ -432,7 +442,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         enqueue_scan(A, slot, n_flag);
         n_scan += n_flag;
     }
-    flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
+    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
 }
 
 // ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
@@ -477,7 +487,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
             int cnt = 0;
             while (__any(!s.done)) {
                 const float h2 = s.h * s.h;
-                const float hinv = 1.0f / s.h;
+                const float hinv = __builtin_amdgcn_rcpf(s.h);
                 S0 = S1 = M0 = M1 = 0.f;
                 cnt = 0;
                 const int groups_now = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
@@ -516,13 +526,13 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                 cnt = gsum_i(cnt, G);
                 if (s.done) continue;
                 if (G.sub == 0) sweep_acc += cnt;
-                hsolve_step(s, S0, S1, A.target, A.tol, A.max_iter);
+                hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
             }
             if (valid && G.sub == 0 && st0 == ST_SCAN)
                 write_result(A, i, s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
         }
     }
-    flush_counters(A, cand_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
+    flush_counters(A, cand_acc, 0, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
 }
 
 }  // namespace
@@ -580,6 +590,7 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.status = status;
     A.ctr = ctr;
     A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
+    A.inv_target = (float)(32.0 / (3.0 * c->prm.n_ngb));
     A.tol = (float)c->prm.n_tol;
     A.max_iter = c->prm.max_iter;
     // a particle with a good guess finds about n_ngb * h_margin^3 candidates

@@ -4,7 +4,8 @@
 //
 // The ghost step (after the density, section 3.1's dependency) turns rho, f
 // and u into the per-particle pressure term Phi = f P / rho^2 and sound speed,
-// packed with position, velocity, mass and 1/h into three float4 per particle.
+// packed with position, h^2, velocity, mass and 1/h into three float4 per
+// particle: (x, y, z, h^2), (v, m), (rho, Phi, c, 1/h).
 // The loop then runs one wavefront per leaf cell exactly like the density
 // loop: the cell's neighbour particles are staged into LDS in chunks and each
 // particle of the cell (several lanes per particle for small cells) gathers
@@ -41,9 +42,9 @@ __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, c
     const float P = (gamma - 1.0f) * rho * uu;
     const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
     const float phi = fs[p] * P / (rho * rho);
-    jf[3 * p + 0] = make_float4(x.x, x.y, x.z, 1.0f / h);
+    jf[3 * p + 0] = make_float4(x.x, x.y, x.z, h * h);
     jf[3 * p + 1] = make_float4(vx, vy, vz, x.w);
-    jf[3 * p + 2] = make_float4(rho, phi, c, 0.0f);
+    jf[3 * p + 2] = make_float4(rho, phi, c, 1.0f / h);
 }
 
 struct ForceArgs {
@@ -67,16 +68,20 @@ struct ForceArgs {
 
 // Phase A of one chunk for the lanes of one particle: the lane with index sub
 // in its group tests candidates sub, sub + LPI, ... (slot 0 of the tile: x,
-// y, z, 1/h) and appends the chunk index of every candidate inside
-// max(h_i, h_j), except the particle itself, to its byte list. The chunk is
-// padded with far positions to a multiple of the stride (pad_tile), four tile
-// reads are in flight and the appends are branch-free.
+// y, z, h^2) and appends the chunk index of every candidate inside
+// max(h_i, h_j), except the particle itself, to its byte list (row e of the
+// lists holds entry e of every lane; o is the byte offset of this lane's next
+// entry). The chunk is padded with far positions to a multiple of the stride
+// (pad_tile), four tile reads are in flight and the appends are branch-free.
+// A lane tests at most FCAP / 2 candidates of a chunk, so its list cannot
+// overflow.
 template <int LPI>
 __device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, float xx, float xy, float xz,
-                                          float hinv2_i, uint8_t* lst)
+                                          float h2_i, uint8_t* lists)
 {
     const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
-    int nl = 0;
+    const unsigned o0 = threadIdx.x & 63;
+    unsigned o = o0;
     for (int k0 = sub; k0 < len_pad; k0 += 4 * LPI) {
         float4 pj[4];
 #pragma unroll
@@ -85,17 +90,16 @@ __device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, fl
         for (int u = 0; u < 4; ++u) {
             const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float hinv2_j = pj[u].w * pj[u].w;
-            const bool in = ((r2 * hinv2_i < 1.0f) | (r2 * hinv2_j < 1.0f)) & (r2 > 0.0f);
-            lst[nl * 64] = (uint8_t)(k0 + u * LPI);
-            nl += in ? 1 : 0;
+            const bool in = (r2 < fmaxf(h2_i, pj[u].w)) & (r2 > 0.0f);
+            lists[o] = (uint8_t)(k0 + u * LPI);
+            o += in ? 64u : 0u;
         }
     }
-    return nl;
+    return (int)((o - o0) >> 6);
 }
 
 // Slot 0 of the unused tile entries [len, CAP): a far position with a tiny
-// 1/h, so no pair test passes there.
+// h^2, so no pair test passes there.
 __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
 {
     for (int t = len + (int)(threadIdx.x & 63); t < cap; t += 64) sj[t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 1.0e-12f);
@@ -123,8 +127,9 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= FCAP;
         const int lpi = choose_lpi(ni, nj, 2, A.list_work, single_tile, FCAP);
-        const int per_pass = 64 / lpi;
-        const int g = lane / lpi;
+        const int lg = __builtin_ctz(lpi);
+        const int per_pass = 64 >> lg;
+        const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
         bool loaded = false;
         for (int ib = 0; ib < ni; ib += per_pass) {
@@ -134,7 +139,8 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             const float4 i0v = A.jf[3 * (int64_t)i + 0];
             const float4 i1v = A.jf[3 * (int64_t)i + 1];
             const float4 i2v = A.jf[3 * (int64_t)i + 2];
-            const float hinv_i = i0v.w;
+            const float h2_i = i0v.w;
+            const float hinv_i = i2v.w;
             const float hinv2_i = hinv_i * hinv_i;
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
@@ -164,13 +170,13 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
                 int nl;
                 if (lpi == 2)
-                    nl = force_scan<2>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                    nl = force_scan<2>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 4)
-                    nl = force_scan<4>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                    nl = force_scan<4>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 8)
-                    nl = force_scan<8>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                    nl = force_scan<8>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else
-                    nl = force_scan<16>(sj, len, sub, i0v.x, i0v.y, i0v.z, hinv2_i, lst);
+                    nl = force_scan<16>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 if (!valid) nl = 0;
                 cnt += nl;
                 // phase B: the pair terms of the compacted neighbours only
@@ -182,9 +188,9 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                     const float4 p2 = sj[2 * FCAP + k];
                     const float dx = i0v.x - p0.x, dy = i0v.y - p0.y, dz = i0v.z - p0.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float hinv_j = p0.w;
+                    const float hinv_j = p2.w;
                     const float hinv2_j = hinv_j * hinv_j;
-                    const float rinv = rsqrtf(r2);
+                    const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 > 0 (phase A), far from denormal
                     const float r = r2 * rinv;
                     const float Di = Ki * spline_dw_r(r, hinv_i);
                     const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw_r(r, hinv_j);
@@ -210,9 +216,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             du = group_sum(du, lpi);
             cnt = group_sum_i(cnt, lpi);
             const bool leader = valid && sub == 0;
-            int ng = leader ? 1 : 0;
-            for (int o = 32; o >= 1; o >>= 1) ng += __shfl_xor(ng, o, 64);
-            cand_acc += (int64_t)ng * nj;
+            cand_acc += (int64_t)wave_count(leader) * nj;
             double cm[4] = {0.0, 0.0, 0.0, 0.0};
             if (leader) {
                 const uint32_t o = A.perm[i];
@@ -228,9 +232,11 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                 cm[3] = m * ((double)i1v.x * ax + (double)i1v.y * ay + (double)i1v.z * az + (double)du);
             }
             if (A.cons) {
+                // only the group leaders (lanes g * lpi) hold terms: the
+                // exchanges at distances below lpi would add zeros
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    for (int o = 32; o >= 1; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
+                    for (int o = 32; o >= lpi; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
                 if (lane == 0) {
                     const int b = A.cell_aux[slot].y;
 #pragma unroll

@@ -75,10 +75,13 @@ __device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float lis
     const int nchunks = (nj + chunk - 1) / chunk;
     int best = 16;
     float best_cost = 3.0e38f;
-    for (int l = lpi_min; l <= 16; l <<= 1) {
-        const int per = 64 / l;
-        const float passes = (float)((ni + per - 1) / per);
-        float cost = passes * (((float)nj + list_work) / (float)l + 25.0f);
+#pragma unroll
+    for (int lg = 1; lg <= 4; ++lg) {  // l = 2, 4, 8, 16: every division below is a shift or a constant
+        const int l = 1 << lg;
+        if (l < lpi_min) continue;
+        const int per = 64 >> lg;
+        const float passes = (float)((ni + per - 1) >> (6 - lg));
+        float cost = passes * (((float)nj + list_work) * (1.0f / (float)l) + 25.0f);
         if (!resident) cost += passes * (float)nchunks * 20.0f;
         if (cost < best_cost) {
             best_cost = cost;
@@ -134,15 +137,49 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A 32-bit value of another lane of the same row of 16, by a DPP pattern:
+// 0xB1 = quad_perm [1,0,3,2], 0x4E = quad_perm [2,3,0,1], 0x141 =
+// row_half_mirror (lane i of 8 reads 7 - i), 0x140 = row_mirror (lane i of
+// 16 reads 15 - i). Every lane of the row must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+// Sum over aligned groups of lpi lanes (1, 2, 4, 8 or 16), returned to every
+// lane of the group; the whole wavefront must be active. The two quad
+// patterns add the partners at distance 1 and 2; once each quad holds its
+// sum, the half-row mirror brings in the other quad of the 8 and the row
+// mirror the other half of the 16. The partners of a group add the same two
+// values at every step, so every lane ends with the same bits (the same sums
+// as exchanges at distance 1, 2, 4 and 8). One VALU operation per step.
 __device__ __forceinline__ float group_sum(float v, int lpi)
 {
-    for (int o = 1; o < lpi; o <<= 1) v += __shfl_xor(v, o, 64);
+    if (lpi >= 2) v += dpp_f<0xB1>(v);
+    if (lpi >= 4) v += dpp_f<0x4E>(v);
+    if (lpi >= 8) v += dpp_f<0x141>(v);
+    if (lpi >= 16) v += dpp_f<0x140>(v);
     return v;
 }
 __device__ __forceinline__ int group_sum_i(int v, int lpi)
 {
-    for (int o = 1; o < lpi; o <<= 1) v += __shfl_xor(v, o, 64);
+    if (lpi >= 2) v += dpp_i<0xB1>(v);
+    if (lpi >= 4) v += dpp_i<0x4E>(v);
+    if (lpi >= 8) v += dpp_i<0x141>(v);
+    if (lpi >= 16) v += dpp_i<0x140>(v);
     return v;
+}
+
+// Number of lanes for which c holds (a scalar bit count of the ballot).
+__device__ __forceinline__ int wave_count(bool c)
+{
+    return __popcll(__ballot(c));
 }
 
 // Number of candidates of a cell: the particles of every cell in its list.

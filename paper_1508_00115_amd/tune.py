@@ -11,7 +11,8 @@ legal cell layout):
     leaf_target  cells holding more particles than this are split
     schedule     hardware dispatch or persistent per-XCD queues
     tile_cap     candidates the density kernel keeps resident in LDS
-    cell_order   cells by decreasing cost (balance) or in Morton order (L2 reuse)
+    cell_order   cells by decreasing cost (balance), in Morton order (L2 reuse), or
+                 Morton ranges per XCD each ordered by cost
 
 Each setting is timed on the caller's particles as whole density + force
 passes (sph_pass, after a warm-up, HIP events around the calls); the fastest
@@ -39,7 +40,7 @@ DEFAULT_GRID = [
     for lt in (64, 32)
     for s in (0, 1)
     for tc in (128, 512)
-    for co in (0, 1)
+    for co in (0, 1, 2)
 ]
 
 

@@ -127,7 +127,8 @@ def test_clustered_full_size_sampled(gpu_lib):
                                     dict(h_margin=1.6), dict(h_margin=1.02), dict(schedule=1),
                                     dict(schedule=1, queue_batch=1), dict(schedule=1, queue_batch=64),
                                     dict(cell_order=1), dict(cell_order=1, schedule=1), dict(tile_cap=256),
-                                    dict(tile_cap=512, h_margin=1.26)])
+                                    dict(tile_cap=512, h_margin=1.26), dict(cell_order=2),
+                                    dict(cell_order=2, schedule=1), dict(cell_order=2, leaf_target=8)])
 def test_results_do_not_depend_on_cells(gpu_lib, params):
     d = workloads.lattice_box(18, [1508, 902], jitter=0.3, u=1.0, vel_sigma=0.2)
     g0 = _gpu(gpu_lib, d)
