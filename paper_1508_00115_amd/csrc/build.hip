@@ -316,6 +316,17 @@ __global__ void k_leaf_fill(int64_t n, const uint32_t* __restrict__ head, const 
     }
 }
 
+// First leaf of each box: leaves follow the sorted particles, whose boxes are
+// contiguous blocks, so box b owns leaves [box_leaf[b], box_leaf[b + 1]).
+__global__ void k_box_leaf(int n_boxes, int64_t n, int64_t nl, const int64_t* __restrict__ box_first,
+                           const int* __restrict__ leaf_of, int* __restrict__ box_leaf)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > n_boxes) return;
+    const int64_t p = box_first[b];
+    box_leaf[b] = p < n ? leaf_of[p] : (int)nl;
+}
+
 __global__ void k_leaf_fix(int64_t nl, const int* __restrict__ lf_node, const int* __restrict__ nd_count,
                            const unsigned* __restrict__ nd_hmax, int* __restrict__ nd_leaf,
                            int* __restrict__ lf_count, float* __restrict__ lf_hmax)
@@ -678,6 +689,13 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
                                                  static_cast<unsigned*>(c->nd_hmax.p),
                                                  static_cast<int*>(c->nd_leaf.p), lf_count, lf_hmax);
     SPH_HIP(hipGetLastError());
+    {
+        int* box_leaf = ensure<int>(c, c->box_leaf, c->n_boxes + 1);
+        k_box_leaf<<<blocks_for(c->n_boxes + 1, BS), BS, 0, s>>>(c->n_boxes, n, nl,
+                                                                  static_cast<int64_t*>(c->box_first.p), leaf_of,
+                                                                  box_leaf);
+        SPH_HIP(hipGetLastError());
+    }
 
     // ---- neighbour lists ------------------------------------------------------------------------
     uint32_t* p_cnt = ensure<uint32_t>(c, c->p_cnt, nl + 1);

@@ -100,8 +100,10 @@ __device__ inline void ctr_wave_add(int64_t* ctr, int k, int64_t v)
     ctr_add_uniform(ctr, k, v);
 }
 
-// Per-box conservation sums (4 doubles per box) are kept in CONS_SLOTS copies,
-// picked by workgroup, for the same reason as the counters' spread slots.
+// Per-box conservation sums of the plain FP64 form (4 doubles per box) are
+// kept in CONS_SLOTS copies, picked by workgroup, for the same reason as the
+// counters' spread slots. (The FP32 force loop writes one partial per cell
+// and sums them per box in a second kernel instead.)
 constexpr int CONS_SLOTS = 16;
 
 __device__ inline double* cons_slot(double* cons, int n_boxes)
@@ -181,7 +183,10 @@ struct sph_ctx {
     sph::Buf scan_cells;     // int: leaves holding particles left to the re-scan
     sph::Buf jf;             // 3 float4 per particle for the force loop
     sph::Buf counters;       // int64[CT_COUNT]
-    sph::Buf cons_d;         // double, 4 per box
+    sph::Buf cons_d;         // double, 4 per box (FP32 force loop)
+    sph::Buf cons_part;      // double, 4 per leaf: each cell's share of cons_d
+    sph::Buf box_leaf;       // int, n_boxes + 1: first leaf of each box (leaves follow the boxes)
+    sph::Buf cons64_d;       // double, CONS_SLOTS x 4 per box (plain FP64 form)
     int64_t* h_counters = nullptr;  // pinned host mirror of counters
 
     // ---- FP64 plain form --------------------------------------------------------
@@ -302,16 +307,16 @@ __host__ __device__ inline int64_t xcd_start(int64_t n, int x)
     return (int64_t)x * (n / 8) + (x < n % 8 ? x : n % 8);
 }
 
-// Sum the copies of the conservation sums (device, CONS_SLOTS x 4 x n_boxes)
-// into out (host, 4 x n_boxes) once the stream reaches this point.
-inline void read_cons(const double* cons_d, double* out, int n_boxes, hipStream_t s)
+// Sum the copies of the conservation sums (device, slots x 4 x n_boxes) into
+// out (host, 4 x n_boxes) once the stream reaches this point.
+inline void read_cons(const double* cons_d, double* out, int n_boxes, int slots, hipStream_t s)
 {
-    std::vector<double> h((size_t)CONS_SLOTS * 4 * n_boxes);
+    std::vector<double> h((size_t)slots * 4 * n_boxes);
     SPH_HIP(hipMemcpyAsync(h.data(), cons_d, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < 4 * n_boxes; ++k) {
         double v = 0.0;
-        for (int sl = 0; sl < CONS_SLOTS; ++sl) v += h[(size_t)sl * 4 * n_boxes + k];
+        for (int sl = 0; sl < slots; ++sl) v += h[(size_t)sl * 4 * n_boxes + k];
         out[k] = v;
     }
 }

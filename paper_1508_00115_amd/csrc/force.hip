@@ -12,7 +12,9 @@
 // the terms of every pair inside max(h_i, h_j). The gather form evaluates each
 // pair from both sides, so no two waves write the same particle and the result
 // does not depend on scheduling. Per-box momentum and energy rates are summed
-// in FP64 from each wave's particles.
+// in FP64: each wave stores its cell's share (plain stores, no atomics) and a
+// second kernel adds the shares of each box's cells in a fixed order, so the
+// sums are also reproducible.
 #include "common.h"
 #include "tiles.h"
 
@@ -58,8 +60,7 @@ struct ForceArgs {
     const uint32_t* perm;
     float* acc;
     float* dudt;
-    double* cons;  // CONS_SLOTS copies of 4 per box, may be null
-    int n_boxes;
+    double* cons_part;  // 4 per leaf, may be null
     int64_t* ctr;
     WorkSched W;
     float alpha;
@@ -132,6 +133,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
         bool loaded = false;
+        double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};  // this cell's share of the box sums (lane 0)
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
             const bool valid = gi < ni;
@@ -231,22 +233,52 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                 cm[2] = m * az;
                 cm[3] = m * ((double)i1v.x * ax + (double)i1v.y * ay + (double)i1v.z * az + (double)du);
             }
-            if (A.cons) {
+            if (A.cons_part) {
                 // only the group leaders (lanes g * lpi) hold terms: the
                 // exchanges at distances below lpi would add zeros
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < 4; ++k) {
                     for (int o = 32; o >= lpi; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
-                if (lane == 0) {
-                    const int b = A.cell_aux[slot].y;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) atomicAdd(&cons_slot(A.cons, A.n_boxes)[4 * b + k], cm[k]);
+                    cm_cell[k] += cm[k];
                 }
             }
+        }
+        if (A.cons_part && lane == 0) {
+            const int leaf = A.cell_aux[slot].x;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) A.cons_part[4 * (int64_t)leaf + k] = cm_cell[k];
         }
     }
     ctr_wave_add(A.ctr, CT_FORCE_INTER, inter_acc);
     ctr_add_uniform(A.ctr, CT_FORCE_CAND, cand_acc);  // already a wavefront total
+}
+
+// Per-box sums of the cells' shares: block b adds the shares of its leaves
+// [box_leaf[b], box_leaf[b + 1]) in a fixed order (strided partial sums, then
+// a tree in LDS), so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_cons_reduce(const int* __restrict__ box_leaf,
+                                                     const double* __restrict__ cons_part, double* __restrict__ cons)
+{
+    __shared__ double red[4][256];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    const int l0 = box_leaf[b], l1 = box_leaf[b + 1];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = l0 + t; l < l1; l += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += cons_part[4 * (int64_t)l + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 4) cons[4 * (int64_t)b + t] = red[t][0];
 }
 
 }  // namespace
@@ -267,7 +299,6 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
         fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);
     else
         fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);
-    if (cons_d) fill_u32(cons_d, 0u, (int64_t)CONS_SLOTS * 8 * c->n_boxes, s);
     k_force_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
                                                          static_cast<float4*>(c->jd.p), static_cast<float*>(c->hs.p),
                                                          static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p),
@@ -284,8 +315,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.perm = static_cast<uint32_t*>(c->perm.p);
     A.acc = acc;
     A.dudt = dudt;
-    A.cons = cons_d;
-    A.n_boxes = c->n_boxes;
+    A.cons_part = cons_d ? static_cast<double*>(c->cons_part.p) : nullptr;
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
@@ -294,12 +324,18 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     k_force<<<grid, BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_FORCE_K1, s);
+    if (cons_d) {
+        k_cons_reduce<<<c->n_boxes, 256, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);
+        SPH_HIP(hipGetLastError());
+    }
 }
 
 double* force_buffers(sph_ctx* c, bool cons)
 {
     ensure<float4>(c, c->jf, 3 * c->n);
-    return cons ? ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes) : nullptr;
+    if (!cons) return nullptr;
+    ensure<double>(c, c->cons_part, (size_t)4 * c->n_leaves);
+    return ensure<double>(c, c->cons_d, (size_t)4 * c->n_boxes);
 }
 
 void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons,
@@ -311,7 +347,7 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     ev_record(c, EV_FORCE_C0, s);
     force_enqueue(c, vel, u, acc, dudt, cons_d, true, true, s);
     if (cons || st) {
-        if (cons) read_cons(cons_d, cons, c->n_boxes, s);
+        if (cons) read_cons(cons_d, cons, c->n_boxes, 1, s);
         const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {

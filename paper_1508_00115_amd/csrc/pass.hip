@@ -88,7 +88,7 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
         }
         return;
     }
-    if (cons) read_cons(cons_d, cons, c->n_boxes, s);
+    if (cons) read_cons(cons_d, cons, c->n_boxes, 1, s);
     if (st) {
         st->sweeps = (int32_t)hc[CT_SWEEPS];
         st->rebuilds = 0;

@@ -427,7 +427,7 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     double* jf = ensure<double>(c, c->jf64, 8 * n);
     double* cons_d = nullptr;
     if (cons) {
-        cons_d = ensure<double>(c, c->cons_d, (size_t)CONS_SLOTS * 4 * c->n_boxes);
+        cons_d = ensure<double>(c, c->cons64_d, (size_t)CONS_SLOTS * 4 * c->n_boxes);
         SPH_HIP(hipMemsetAsync(cons_d, 0, (size_t)CONS_SLOTS * 32 * c->n_boxes, s));
     }
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
@@ -459,7 +459,7 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     k_force64<<<blocks_for(n, BS), BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     if (cons || st) {
-        if (cons) read_cons(cons_d, cons, c->n_boxes, s);
+        if (cons) read_cons(cons_d, cons, c->n_boxes, CONS_SLOTS, s);
         const int64_t* hc = read_counters(c, s);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {

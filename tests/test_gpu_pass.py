@@ -142,3 +142,39 @@ def test_pass_rebuild_fallback_matches_oracle(gpu_lib):
     assert_within(e, TOL32, "pass with rebuild")
     n_f = int(r["npair"].sum())
     assert abs(got["stats"]["interactions_force"] - n_f) <= 1e-5 * n_f + 2
+
+
+def test_conservation_sums_reproducible(gpu_lib):
+    """The per-box sums are each cell's share added per box in a fixed order:
+    bit-identical over repeated calls, over the graph-captured pass, and over
+    work schedules and cell orders that change only which wavefront takes
+    which cell (several boxes, so the per-box leaf ranges are exercised)."""
+    import torch
+    d = workloads.batched(n_boxes=8, n_min=1000, n_max=8000, side_min=10, side_max=20)
+    print("case batched8 cons", flush=True)
+    ref = _separate(gpu_lib, d)
+    for params in (dict(), dict(schedule=1), dict(cell_order=1), dict(cell_order=2, schedule=1)):
+        got = _separate(gpu_lib, d, **params)
+        assert np.array_equal(got["cons"], ref["cons"]), params
+    t = _inputs(d)
+    ctx = gpu_lib.Context(0)
+    try:
+        ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
+        bufs = None
+        for rep in range(2):
+            got, bufs = _pass(ctx, t, d, bufs)
+            assert np.array_equal(got["cons"], ref["cons"]), rep
+    finally:
+        ctx.close()
+    # and the sums are those of the outputs (momentum and energy rates per
+    # box), up to the order of FP64 additions
+    m = d["mass"].astype(np.float64)
+    acc, dudt, vel = ref["acc"].astype(np.float64), ref["dudt"].astype(np.float64), d["vel"].astype(np.float64)
+    for b in range(len(d["box_len"])):
+        sl = slice(int(d["box_first"][b]), int(d["box_first"][b + 1]))
+        mom = (m[sl, None] * acc[sl]).sum(axis=0)
+        en = np.sum(m[sl] * (np.einsum("ij,ij->i", vel[sl], acc[sl]) + dudt[sl]))
+        s_mom = np.sum(m[sl] * np.abs(acc[sl]).sum(axis=1))
+        s_en = np.sum(m[sl] * (np.abs(vel[sl] * acc[sl]).sum(axis=1) + np.abs(dudt[sl])))
+        assert np.all(np.abs(ref["cons"][b, :3] - mom) <= 1e-12 * s_mom), b
+        assert abs(ref["cons"][b, 3] - en) <= 1e-12 * s_en, b
