@@ -366,10 +366,13 @@ void density_buffers(sph_ctx* c);
 double* force_buffers(sph_ctx* c, bool cons);
 // Kernel launches only: no allocation, memset or host synchronisation, so
 // they may run under stream capture. events: record the timing events.
+// ghost (density_enqueue, with vel and u): the density kernels also write
+// the force loop's particle streams, so force_enqueue(..., prologue = false)
+// skips its ghost kernel.
 void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, bool fresh,
-                     bool events, hipStream_t s);
+                     bool events, hipStream_t s, const float* ghost_vel = nullptr, const float* ghost_u = nullptr);
 void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons_d,
-                   bool clear_all, bool events, hipStream_t s);
+                   bool clear_all, bool events, hipStream_t s, bool prologue = true);
 void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, const float* vel,
               const float* u, float* acc, float* dudt, double* cons, sph_stats* st, hipStream_t s);
 void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double* f, double* nw,

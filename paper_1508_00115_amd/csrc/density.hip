@@ -73,6 +73,12 @@ struct DensArgs {
     int max_iter;
     int lpi_min;             // fewest lanes per particle (a power of two): spreads a list over enough slots
     float nl_est;            // expected list length of a particle: n_ngb * h_margin^3
+    // ghost step fused into the outputs (null jf: not fused): the force
+    // loop's streams from the final h, rho, f and the caller's v, u
+    const float* vel;
+    const float* u;
+    float4* jf;
+    float gamma;
 };
 
 // Sorted copies of position (cell frame), mass, h and state. fresh: every
@@ -214,6 +220,23 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSo
     A.status[o] = s.state;
     if (s.state == ST_DONE) inter_acc += cnt - 1;
     max_ev = max(max_ev, s.nev);
+    if (A.jf) {
+        // the ghost step of this particle (the same arithmetic as the force
+        // loop's ghost kernel, so both give the same bits)
+        const float4 x = A.jd[i];
+        const float h = s.h;
+        const float uu = A.u[o];
+        const float vx = A.vel[3 * (int64_t)o], vy = A.vel[3 * (int64_t)o + 1], vz = A.vel[3 * (int64_t)o + 2];
+        if (!(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz))
+            atomicAdd((unsigned long long*)&ctr_slot(A.ctr)[CT_BAD_INPUT], 1ull);
+        const float gamma = A.gamma;
+        const float P = (gamma - 1.0f) * rho * uu;
+        const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
+        const float phi = f * P / (rho * rho);
+        A.jf[3 * (int64_t)i + 0] = make_float4(x.x, x.y, x.z, h * h);
+        A.jf[3 * (int64_t)i + 1] = make_float4(vx, vy, vz, x.w);
+        A.jf[3 * (int64_t)i + 2] = make_float4(rho, phi, c, 1.0f / h);
+    }
 }
 
 __device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_acc, int64_t list_acc,
@@ -555,7 +578,7 @@ int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_
 }
 
 void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, bool fresh,
-                     bool events, hipStream_t s)
+                     bool events, hipStream_t s, const float* ghost_vel, const float* ghost_u)
 {
     const int64_t n = c->n;
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
@@ -601,6 +624,10 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.lpi_min = 2;
     while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
     A.scan_cells = static_cast<int*>(c->scan_cells.p);
+    A.vel = ghost_vel;
+    A.u = ghost_u;
+    A.jf = ghost_vel && ghost_u ? static_cast<float4*>(c->jf.p) : nullptr;
+    A.gamma = (float)c->prm.gamma;
     const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
     // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
     const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);

@@ -288,22 +288,26 @@ namespace sph {
 int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_cu, WorkSched& W);
 
 void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons_d,
-                   bool clear_all, bool events, hipStream_t s)
+                   bool clear_all, bool events, hipStream_t s, bool prologue)
 {
     const int64_t n = c->n;
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     float4* jf = static_cast<float4*>(c->jf.p);
     // all counters, or (after a density pass whose counters are still to be
-    // read) only the work-queue heads
+    // read) only the work-queue heads, which only the persistent schedule uses
     if (clear_all)
         fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);
-    else
+    else if (c->prm.schedule == 1)
         fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);
-    k_force_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
-                                                         static_cast<float4*>(c->jd.p), static_cast<float*>(c->hs.p),
-                                                         static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p),
-                                                         vel, u, (float)c->prm.gamma, jf, ctr);
-    SPH_HIP(hipGetLastError());
+    if (prologue) {  // else the density kernels wrote the streams (ghost step fused)
+        k_force_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                             static_cast<float4*>(c->jd.p),
+                                                             static_cast<float*>(c->hs.p),
+                                                             static_cast<float*>(c->rhos.p),
+                                                             static_cast<float*>(c->fs.p), vel, u,
+                                                             (float)c->prm.gamma, jf, ctr);
+        SPH_HIP(hipGetLastError());
+    }
     ForceArgs A;
     A.jf = jf;
     A.cells = static_cast<int4*>(c->cells.p);

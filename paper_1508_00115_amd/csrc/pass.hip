@@ -6,10 +6,13 @@
 // smoothing length outgrew its cell (then the cells are rebuilt). The pass
 // runs density and force back to back without looking, reads the counters
 // once at the end and, in the rare case of an overflow, solves the density
-// again with the synchronous rebuild loop and repeats the force. The kernel
-// sequence never changes between calls with the same buffers, so it is
-// captured on a private stream once and the graph is launched on the
-// caller's stream; the capture is redone when any pointer or size changes.
+// again with the synchronous rebuild loop and repeats the force. The ghost
+// step is folded into the density kernels: a particle's force-loop streams
+// are written as soon as its h is final, so there is no ghost kernel between
+// the loops. The kernel sequence never changes between calls with the same
+// buffers, so it is captured on a private stream once and the graph is
+// launched on the caller's stream; the capture is redone when any pointer or
+// size changes.
 #include "common.h"
 
 namespace sph {
@@ -37,8 +40,8 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
     if (c->prm.timing) {
         // timing mode: the same sequence launched directly, with events
         ev_record(c, EV_DENS_C0, s);
-        density_enqueue(c, mass, h, rho, f, nw, true, true, s);
-        force_enqueue(c, vel, u, acc, dudt, cons_d, false, true, s);
+        density_enqueue(c, mass, h, rho, f, nw, true, true, s, vel, u);
+        force_enqueue(c, vel, u, acc, dudt, cons_d, false, true, s, false);
         ev_record(c, EV_FORCE_C1, s);
     } else {
         const std::vector<uint64_t> key = {
@@ -52,8 +55,8 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
             hipGraph_t g = nullptr;
             SPH_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             try {
-                density_enqueue(c, mass, h, rho, f, nw, true, false, c->cap_stream);
-                force_enqueue(c, vel, u, acc, dudt, cons_d, false, false, c->cap_stream);
+                density_enqueue(c, mass, h, rho, f, nw, true, false, c->cap_stream, vel, u);
+                force_enqueue(c, vel, u, acc, dudt, cons_d, false, false, c->cap_stream, false);
             } catch (...) {
                 (void)hipStreamEndCapture(c->cap_stream, &g);
                 if (g) (void)hipGraphDestroy(g);
