@@ -8,9 +8,9 @@ the smoothing-length solve to convergence, then the ghost step and the force
 loop, issued as one sph_pass (a captured launch sequence with one host
 synchronisation). The cells are built once before timing (the build is
 reported separately), the starting h is restored before every step, and all
-inputs are resident in HBM. Kernel times for the roofline come from a second
-context that makes the same calls separately with HIP events. The
-interaction count of a pass is
+inputs are resident in HBM. The roofline's kernel durations are averages
+over as many passes with the same kernels, launched uncaptured by a timing
+context with HIP events on their stream. The interaction count of a pass is
 
     #{(i, j), j != i: r_ij < h_i}  +  #{(i, j), j != i: r_ij < max(h_i, h_j)}
 
@@ -186,56 +186,52 @@ def main() -> int:
             if args.tune_out:
                 tune.save(d, tuned, args.tune_out)
         params = tuned["best"]
-    # the timed pass: density + force in one captured launch sequence, no
-    # timing events (the production configuration)
+    # the timed region: density + force as one captured launch sequence (the
+    # production configuration)
     ctx = sph.Context(0, **params)
     ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
 
-    def step():
+    def step(c):
         h.copy_(h0)
-        return ctx.pass_(mass, h, vel, u, rho=rho, f=f, acc=acc, dudt=dudt)["stats"]
+        return c.pass_(mass, h, vel, u, rho=rho, f=f, acc=acc, dudt=dudt)["stats"]
 
     for _ in range(args.warmup):
-        step()
+        step(ctx)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        sp = step()
+        sp = step(ctx)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / args.steps
     inter = sp["interactions_density"] + sp["interactions_force"]
     value = inter / (ms_step * 1e-3)
 
-    # ---- kernel timings: the same cells, separate calls with HIP events ---------------
+    # kernel durations: the same passes (the same kernels, the ghost step in
+    # the density kernels) launched uncaptured by a timing context, with HIP
+    # events on the stream they run on; averages over as many steps
     ctx_t = sph.Context(0, timing=1, **params)
     ctx_t.build_cells(pos, h0, d["box_first"], d["box_len"])
     build_ms = ctx_t.timings()["build_ms"]
-
-    def step_timed():
-        h.copy_(h0)
-        dr = ctx_t.density(mass, h, rho, f)
-        fr = ctx_t.force(vel, u, acc, dudt, cons=False)
-        return dr["stats"], fr["stats"], ctx_t.timings()
-
     for _ in range(max(args.warmup, 1)):
-        step_timed()
-    dk, dl, fk, dc, fc = [], [], [], [], []
+        step(ctx_t)
+    dk, dr, fk, pc = [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        sd, sf, t = step_timed()
-        dk.append(t["density_kernel_ms"])
-        dl.append(t["density_kernel_ms"] - t["density_rescan_ms"])
+        st_t = step(ctx_t)
+        t = ctx_t.timings()
+        dk.append(t["density_kernel_ms"] - t["density_rescan_ms"])
+        dr.append(t["density_rescan_ms"])
         fk.append(t["force_kernel_ms"])
-        dc.append(t["density_call_ms"])
-        fc.append(t["force_call_ms"])
+        pc.append(t["pass_call_ms"])
     torch.cuda.synchronize()
-    ms_step_separate = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_step_uncaptured = (time.perf_counter() - t0) * 1e3 / args.steps
     ctx_t.close()
-    assert sd["interactions_density"] == sp["interactions_density"]
-    assert sf["interactions_force"] == sp["interactions_force"]
+    assert st_t["interactions_density"] == sp["interactions_density"]
+    assert st_t["interactions_force"] == sp["interactions_force"]
+    sd = sf = sp
 
     # ---- plain FP64 form on the same cells -------------------------------------------
     mass64, vel64, u64 = mass.double(), vel.double(), u.double()
@@ -261,7 +257,7 @@ def main() -> int:
     value64 = inter / (ms_step64 * 1e-3)
 
     # ---- roofline of the dominant kernel ------------------------------------------------
-    dens_ms = float(np.mean(dl))  # the list kernel alone (the re-scan kernel is timed apart)
+    dens_ms = float(np.mean(dk))  # the list kernel alone (the re-scan kernel is timed apart)
     force_ms = float(np.mean(fk))
     dens_alg = FLOP_DENSITY * sd["sweep_interactions_density"] + \
         FLOP_REJECT * (sd["candidates_density"] - sd["sweep_interactions_density"])
@@ -298,10 +294,9 @@ def main() -> int:
                      "traffic_unit": "bytes per launch (HBM, from hardware counters)",
                      "traffic_gbs": None if traffic is None else traffic["bytes"] / (kms * 1e-3) / 1e9,
                      "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg},
-        "separate_calls_ms_per_step": ms_step_separate,
-        "kernels_ms": {"density_kernel": dens_ms, "density_rescan_kernel": float(np.mean(dk)) - dens_ms,
-                       "density_call": float(np.mean(dc)),
-                       "force_kernel": force_ms, "force_call": float(np.mean(fc)), "build": build_ms},
+        "ms_per_step_uncaptured_with_events": ms_step_uncaptured,
+        "kernels_ms": {"density_kernel": dens_ms, "density_rescan_kernel": float(np.mean(dr)),
+                       "force_kernel": force_ms, "pass_gpu": float(np.mean(pc)), "build": build_ms},
         "useful_tflops": useful,
         "density": {"sweeps": sd["sweeps"], "rebuilds": sd["rebuilds"],
                     "candidates": sd["candidates_density"],

@@ -215,10 +215,11 @@ sph_status sph_force(sph_ctx* ctx, const float* vel, const float* u, float* acc,
  * sph_density followed by sph_force with the same arguments, with one host
  * synchronisation instead of one per step. The sequence is captured into a
  * HIP graph on first use and replayed while the buffers (this call's pointers
- * and the context's own) stay the same; with sph_params.timing it runs
- * uncaptured and records kernel timings. When a smoothing length outgrows its
- * cell, the pass falls back to sph_density's rebuild loop and repeats the
- * force.
+ * and the context's own) stay the same; with sph_params.timing the same
+ * kernels run uncaptured with HIP events around them (sph_get_timings). The
+ * ghost step is done by the density kernels as each smoothing length becomes
+ * final. When a smoothing length outgrows its cell, the pass falls back to
+ * sph_density's rebuild loop and repeats the force.
  *   mass, h, rho, f_gradh, n_weighted: as for sph_density
  *   vel, u, acc, dudt, cons: as for sph_force
  *   stats  host, may be NULL: density and force counts of this pass
