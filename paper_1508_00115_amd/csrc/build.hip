@@ -4,10 +4,12 @@
 // least as wide as the largest search radius in the box (so every neighbour of
 // a particle lies in the same or one of the 26 adjacent top cells, Fig. 1),
 // then each top cell is refined as an octree: a cell is split when it holds
-// more than leaf_target particles and its children would still be at least
-// cell_ratio times the largest search radius inside (the mesh "needs to be
-// adaptive", section 3.1). Leaves hold contiguous ranges of the Morton-sorted
-// particles. For every leaf the tree is walked from the 27 surrounding top
+// more than leaf_target particles and at most one in eight of them has
+// cell_ratio times its search radius wider than half the cell (the mesh
+// "needs to be adaptive", section 3.1; pairs of cells are then found by box
+// distance with each cell's own largest radius, so the few wide particles
+// only give their small cells a longer reach). Leaves hold contiguous ranges
+// of the Morton-sorted particles. For every leaf the tree is walked from the 27 surrounding top
 // cells to collect each leaf within reach -- the cell-pair tasks, found with a
 // tree as the end of section 3.1 describes -- with the periodic image of each.
 //
