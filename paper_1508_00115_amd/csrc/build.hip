@@ -352,7 +352,11 @@ __device__ __forceinline__ void node_geom(int id, const int* nd_coord, const int
 
 // Walk the tree from the 27 top cells around leaf a and list every leaf whose
 // cell box lies within max(Hmax_a, Hmax_leaf) of a's cell box. fill == false
-// counts, fill == true writes the list at p_start[a].
+// counts, fill == true writes the list at p_start[a]. The top cells are
+// visited in three classes of (dx + dy + dz) mod 3, nine cells each, every
+// class spread over the whole 3x3x3 block: the hot kernels stage the list in
+// consecutive chunks, and a chunk that samples the whole neighbourhood gives
+// every particle a similar share of its neighbours (even lane lists).
 __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ lf_node,
                            const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
                            const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
@@ -380,9 +384,11 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
     uint32_t cnt = 0;
     const uint32_t base = fill ? p_start[a] : 0u;
     int stack[MAX_STACK];
+    for (int cls = 0; cls < 3; ++cls)
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dz = -1; dz <= 1; ++dz) {
+                if ((dx + dy + dz + 3) % 3 != cls) continue;
                 int t[3] = {tA[0] + dx, tA[1] + dy, tA[2] + dz};
                 int s[3];
 #pragma unroll
