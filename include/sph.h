@@ -130,7 +130,8 @@ typedef struct {
     int64_t interactions_density; /* #{(i, j), j != i : r_ij < h_i} at the final h */
     int64_t interactions_force;   /* #{(i, j), j != i : r_ij < max(h_i, h_j)} */
     int64_t candidates_density; /* (i, j) candidate pairs tested, summed over sweeps */
-    int64_t candidates_force;   /* (i, j) candidate pairs tested by the force loop */
+    int64_t candidates_force;   /* (i, j) candidate pairs tested by the force loop
+                                   (candidates staged within reach of i's cell) */
     int64_t n_cells;            /* leaf cells of the current build */
     int64_t n_pairs;            /* (cell, neighbour cell) entries, self included */
     int64_t sweep_interactions_density; /* pairs inside the trial h, summed over

@@ -472,17 +472,25 @@ __global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const 
 // the leaf of rank r (the ranks already group each XCD's range). by_cost ==
 // null: slot r holds leaf r (Morton order, so each XCD takes a contiguous
 // range of neighbouring cells).
+// cell_geom: half the leaf's width and its largest search radius, for the
+// hot kernels' cell-box test on staged candidates.
 __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, int deal, const int* __restrict__ lf_start,
                              const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
-                             const int* __restrict__ lf_node, const int* __restrict__ nd_box, int4* __restrict__ cells,
-                             int2* __restrict__ cell_aux)
+                             const int* __restrict__ lf_node, const int* __restrict__ nd_box,
+                             const int* __restrict__ nd_level, const int* __restrict__ box_G,
+                             const double* __restrict__ box_len, const float* __restrict__ lf_hmax,
+                             int4* __restrict__ cells, int2* __restrict__ cell_aux, float2* __restrict__ cell_geom)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nl) return;
     const int a = by_cost ? (int)by_cost[r] : (int)r;
     const int64_t slot = by_cost && deal ? sph::xcd_start(nl, (int)(r & 7)) + (r >> 3) : r;
+    const int node = lf_node[a];
+    const int b = nd_box[node];
     cells[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)(p_start[a + 1] - p_start[a]));
-    cell_aux[slot] = make_int2(a, nd_box[lf_node[a]]);
+    cell_aux[slot] = make_int2(a, b);
+    const double w = box_len[b] / box_G[b] / (double)(1u << nd_level[node]);
+    cell_geom[slot] = make_float2((float)(0.5 * w), lf_hmax[a]);
 }
 
 __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ pos_w,
@@ -750,9 +758,12 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, order == 2 ? 35 : 32, s);
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
+        float2* cell_geom = ensure<float2>(c, c->cell_geom, nl);
         k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, order == 0 ? 1 : 0, lf_start,
-                                                       lf_count, p_start,
-                                                       lf_node, nd_box, cells, cell_aux);
+                                                       lf_count, p_start, lf_node, nd_box, nd_level,
+                                                       static_cast<int*>(c->box_G.p),
+                                                       static_cast<double*>(c->box_len.p), lf_hmax, cells,
+                                                       cell_aux, cell_geom);
         SPH_HIP(hipGetLastError());
     }
 

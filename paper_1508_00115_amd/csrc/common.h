@@ -171,6 +171,7 @@ struct sph_ctx {
     // work schedule of the hot kernels (one slot per leaf, see xcd_start)
     sph::Buf cells;          // int4 per slot: first particle, count, first neighbour entry, neighbour entries
     sph::Buf cell_aux;       // int2 per slot: leaf index, box
+    sph::Buf cell_geom;      // float2 per slot: half width of the leaf, largest search radius in it
     sph::Buf sched_key, sched_key_alt, sched_val, sched_val_alt;  // cost sort
     sph::Buf scan_tmp;       // scan workspace
     sph::Buf sort_hist;      // radix-sort histograms

@@ -53,6 +53,7 @@ struct ForceArgs {
     const float4* jf;
     const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* cell_aux;  // per schedule slot: leaf, box
+    const float2* cell_geom;  // per schedule slot: half width of the leaf, largest search radius in it
     const int* lf_start;
     const int* lf_count;
     const int* p_leaf;
@@ -133,6 +134,9 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
         bool loaded = false;
+        int kept_single = 0;  // (single tile) candidates kept by the cell-box test
+        const float2 geom = A.cell_geom[slot];
+        const float hw = cull_half_width(geom.x), reach2 = cull_reach2(geom.y);
         double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};  // this cell's share of the box sums (lane 0)
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
@@ -154,31 +158,38 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                 cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
                 fetch_chunk(R, A.jf, cu.nb, 0, cursor_chunk(cu, 0, FCAP));
             }
-            int len;
+            int len, kept = 0;  // candidates of this chunk; kept by the cell-box test (all chunks)
             for (int c0 = 0; c0 < nj; c0 += len) {
-                len = stream_chunks ? R.len : nj;
+                int slen;
                 if (stream_chunks) {
-                    // store this chunk, then put the next one in flight while
-                    // this one is computed
-                    commit_chunk(sj, R);
+                    // store this chunk's candidates within reach of the cell,
+                    // then put the next chunk in flight while this one is
+                    // computed
+                    len = R.len;
+                    slen = commit_chunk_culled(sj, R, hw, reach2);
+                    if (single_tile) kept_single = slen;
                     const int nx = c0 + len;
                     if (nx < nj) {
                         cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
                         fetch_chunk(R, A.jf, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, FCAP));
                     }
-                    pad_tile(sj, len, FCAP);
+                    pad_tile(sj, slen, FCAP);
                     loaded = true;
+                } else {
+                    len = nj;
+                    slen = kept_single;
                 }
+                kept += slen;
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
                 int nl;
                 if (lpi == 2)
-                    nl = force_scan<2>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<2>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 4)
-                    nl = force_scan<4>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<4>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 8)
-                    nl = force_scan<8>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<8>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else
-                    nl = force_scan<16>(sj, len, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<16>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 if (!valid) nl = 0;
                 cnt += nl;
                 // phase B: the pair terms of the compacted neighbours only
@@ -218,7 +229,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             du = group_sum(du, lpi);
             cnt = group_sum_i(cnt, lpi);
             const bool leader = valid && sub == 0;
-            cand_acc += (int64_t)wave_count(leader) * nj;
+            cand_acc += (int64_t)wave_count(leader) * kept;
             double cm[4] = {0.0, 0.0, 0.0, 0.0};
             if (leader) {
                 const uint32_t o = A.perm[i];
@@ -311,6 +322,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     ForceArgs A;
     A.jf = jf;
     A.cells = static_cast<int4*>(c->cells.p);
+    A.cell_geom = static_cast<float2*>(c->cell_geom.p);
     A.cell_aux = static_cast<int2*>(c->cell_aux.p);
     A.lf_start = static_cast<int*>(c->lf_start.p);
     A.lf_count = static_cast<int*>(c->lf_count.p);

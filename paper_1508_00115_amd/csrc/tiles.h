@@ -374,6 +374,63 @@ __device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<
 }
 
 
+// The cell-box test of a staged force candidate: its squared distance (cell
+// frame) from the cell's box [-hw, hw]^3. A candidate farther than every
+// search radius of the cell's particles and than its own h pairs with none
+// of them: the 3x3x3 block of cells is a cube, the region within reach of the
+// cell a rounded box about a quarter smaller. (The density loop stages
+// without it: there the compaction cost more than the tests it saved.)
+__device__ __forceinline__ float box_dist2(float x, float y, float z, float hw)
+{
+    const float gx = fmaxf(fabsf(x) - hw, 0.0f), gy = fmaxf(fabsf(y) - hw, 0.0f), gz = fmaxf(fabsf(z) - hw, 0.0f);
+    return fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+}
+
+// Lanes of the wavefront below this one whose bit is set in mask.
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Margins of the cell-box test: FP32 positions in the cell frame carry
+// relative errors near 1e-7, so the box grows by 1e-6 of its half width and
+// the radii by 1e-5 (a candidate near the reach is kept, never dropped).
+__device__ __forceinline__ float cull_half_width(float hw) { return hw * 1.000001f; }
+__device__ __forceinline__ float cull_reach2(float reach) { return (reach * 1.00001f) * (reach * 1.00001f); }
+
+// commit_chunk (NF float4 per candidate, slot 0 = x, y, z, h^2) with the
+// cell-box test: a candidate is kept when the box lies within
+// max(reach, h_j) of it. Returns how many were kept (packed from slot 0).
+template <int NF, int CAP>
+__device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<NF, CAP>& R, float hw,
+                                                   float reach2)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        float4 a = R.v[r][0];
+        a.x += R.s[r][0];
+        a.y += R.s[r][1];
+        a.z += R.s[r][2];
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < fmaxf(reach2, a.w * 1.00002f);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int d = n + lanes_below(m);
+            sj[d] = a;
+#pragma unroll
+            for (int f = 1; f < NF; ++f) sj[f * CAP + d] = R.v[r][f];
+        }
+        n += __popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return n;
+}
+
 // Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
 // the neighbour cell of each of its candidates by a binary search over the
 // lane-held prefix offsets, so all global loads of the chunk are independent
