@@ -318,6 +318,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
 {
     __shared__ float4 tile[TCAP];
     __shared__ float lists[(DSLOTS + 1) * 64];
+    __shared__ uint8_t marks[DCH];  // record starts of the chunk being fetched
     const int lane = threadIdx.x & 63;
     float4* sj = tile;
     float* lst = lists + lane;
@@ -369,7 +370,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 ChunkRegs<1, DCH> R;
                 if (stream) {
                     cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
-                    fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH));
+                    fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH), marks);
                 }
                 int len;
                 for (int c0 = 0; c0 < nj; c0 += len) {
@@ -382,7 +383,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                         const int nx = c0 + len;
                         if (nx < nj) {
                             cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
-                            fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH));
+                            fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH), marks);
                         }
                     }
                     if (lpi == 2)

@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
 {
     __shared__ float4 tile[3 * FCAP];
     __shared__ uint8_t lists[FSLOTS * 64];
+    __shared__ uint8_t marks[FCAP];  // record starts of the chunk being fetched
     const int lane = threadIdx.x & 63;
     float4* sj = tile;
     uint8_t* lst = lists + lane;
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             const bool stream_chunks = !(single_tile && loaded);
             if (stream_chunks) {
                 cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
-                fetch_chunk(R, A.jf, cu.nb, 0, cursor_chunk(cu, 0, FCAP));
+                fetch_chunk(R, A.jf, cu.nb, 0, cursor_chunk(cu, 0, FCAP), marks);
             }
             int len, kept = 0;  // candidates of this chunk; kept by the cell-box test (all chunks)
             for (int c0 = 0; c0 < nj; c0 += len) {
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
                     const int nx = c0 + len;
                     if (nx < nj) {
                         cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
-                        fetch_chunk(R, A.jf, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, FCAP));
+                        fetch_chunk(R, A.jf, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, FCAP), marks);
                     }
                     pad_tile(sj, slen, FCAP);
                     loaded = true;

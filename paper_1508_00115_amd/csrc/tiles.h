@@ -287,28 +287,47 @@ struct ChunkRegs {
     int len;
 };
 
+// Lanes of the wavefront below this one whose bit is set in mask.
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Load candidates [c0, c0 + len) of the cursor's block (len <= CAP) into R.
+// The neighbour record (lane of nb) of each slot is found without a search:
+// the record holding c0 is the last one starting at or before it (a ballot
+// over the record lanes), each record starting inside the chunk marks its
+// first slot in mk (CAP bytes of LDS), and a slot's record is that first one
+// plus the marks up to the slot (a ballot of the marks and a lane count).
+// Every record holds at least one particle, so no two records start at the
+// same slot. The loads of the chunk are independent and issue back to back.
 template <int NF, int CAP>
 __device__ __forceinline__ void fetch_chunk(ChunkRegs<NF, CAP>& R, const float4* __restrict__ jd,
-                                            const NbrLanes& nb, int c0, int len)
+                                            const NbrLanes& nb, int c0, int len, uint8_t* mk)
 {
     const int lane = threadIdx.x & 63;
     constexpr int PER = CAP / 64;
     R.len = len;
+    const int q0 = __popcll(__ballot(lane < nb.np && nb.off <= c0)) - 1;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) mk[lane + 64 * r] = 0;
+    wave_sync_lds();
+    const int s = nb.off - c0;
+    if (lane < nb.np && s > 0 && s < len) mk[s] = 1;
+    wave_sync_lds();
+    int q = q0;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int t = lane + 64 * r;
+        const bool start = mk[t] != 0;
+        const uint64_t m = __ballot(start);
+        const int qt = t < len ? q + lanes_below(m) + (start ? 1 : 0) : q0;
+        q += __popcll(m);
         const int kg = c0 + (t < len ? t : 0);
-        int q = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const int cand = q + step;
-            const int v = __shfl(nb.off, cand < nb.np ? cand : nb.np - 1, 64);
-            if (cand < nb.np && v <= kg) q = cand;
-        }
-        const int src = __shfl(nb.bs, q, 64) + (kg - __shfl(nb.off, q, 64));
-        R.s[r][0] = __shfl(nb.sx, q, 64);
-        R.s[r][1] = __shfl(nb.sy, q, 64);
-        R.s[r][2] = __shfl(nb.sz, q, 64);
+        const int src = __shfl(nb.bs, qt, 64) + (kg - __shfl(nb.off, qt, 64));
+        R.s[r][0] = __shfl(nb.sx, qt, 64);
+        R.s[r][1] = __shfl(nb.sy, qt, 64);
+        R.s[r][2] = __shfl(nb.sz, qt, 64);
 #pragma unroll
         for (int f = 0; f < NF; ++f) R.v[r][f] = jd[(int64_t)NF * src + f];
     }
@@ -384,12 +403,6 @@ __device__ __forceinline__ float box_dist2(float x, float y, float z, float hw)
 {
     const float gx = fmaxf(fabsf(x) - hw, 0.0f), gy = fmaxf(fabsf(y) - hw, 0.0f), gz = fmaxf(fabsf(z) - hw, 0.0f);
     return fmaf(gx, gx, fmaf(gy, gy, gz * gz));
-}
-
-// Lanes of the wavefront below this one whose bit is set in mask.
-__device__ __forceinline__ int lanes_below(uint64_t mask)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 // Margins of the cell-box test: FP32 positions in the cell frame carry
