@@ -23,7 +23,7 @@ namespace {
 constexpr int BS = 64;     // one wavefront per block (finest LDS allocation)
 constexpr int WAVES = BS / 64;
 constexpr int FCAP = 128;  // candidates per LDS chunk (3 float4 each)
-constexpr int FSLOTS = FCAP / 2;  // a lane (2+ lanes per particle) tests at most every second candidate
+constexpr int FSLOTS = FCAP / 4;  // a lane (4+ lanes per particle) tests at most every fourth candidate
 
 __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ jd,
                                  const float* __restrict__ hs, const float* __restrict__ rhos,
@@ -108,7 +108,7 @@ __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
     wave_sync_lds();
 }
 
-__global__ void __launch_bounds__(BS) k_force(ForceArgs A)
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
     __shared__ float4 tile[3 * FCAP];
     __shared__ uint8_t lists[FSLOTS * 64];
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
         cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= FCAP;
-        const int lpi = choose_lpi(ni, nj, 2, A.list_work, single_tile, FCAP);
+        const int lpi = choose_lpi(ni, nj, 4, A.list_work, single_tile, FCAP);
         const int lg = __builtin_ctz(lpi);
         const int per_pass = 64 >> lg;
         const int g = lane >> lg;
@@ -155,25 +155,19 @@ __global__ void __launch_bounds__(BS) k_force(ForceArgs A)
             int cnt = 0;
             ChunkRegs<3, FCAP> R;
             const bool stream_chunks = !(single_tile && loaded);
-            if (stream_chunks) {
-                cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
-                fetch_chunk(R, A.jf, cu.nb, 0, cursor_chunk(cu, 0, FCAP), marks);
-            }
             int len, kept = 0;  // candidates of this chunk; kept by the cell-box test (all chunks)
             for (int c0 = 0; c0 < nj; c0 += len) {
                 int slen;
                 if (stream_chunks) {
-                    // store this chunk's candidates within reach of the cell,
-                    // then put the next chunk in flight while this one is
-                    // computed
+                    // stage this chunk's candidates within reach of the cell
+                    // (loaded and stored here rather than one chunk ahead: the
+                    // registers a fetch in flight would hold cost a wavefront
+                    // per SIMD, and the other wavefronts cover the loads)
+                    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
+                    fetch_chunk(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
                     len = R.len;
                     slen = commit_chunk_culled(sj, R, hw, reach2);
                     if (single_tile) kept_single = slen;
-                    const int nx = c0 + len;
-                    if (nx < nj) {
-                        cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
-                        fetch_chunk(R, A.jf, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, FCAP), marks);
-                    }
                     pad_tile(sj, slen, FCAP);
                     loaded = true;
                 } else {
