@@ -455,10 +455,11 @@ __device__ __forceinline__ double image_shift(int code, int axis, double L)
 __device__ __forceinline__ void wave_atomic_max_u32(unsigned* base, int key, unsigned v, bool valid)
 {
     const int k0 = __shfl(key, 0, 64);
+    const bool any = __any(valid);  // on every lane (not only inside lane 0's branch)
     if (__all(!valid || key == k0)) {
         unsigned m = valid ? v : 0u;
         for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
-        if ((threadIdx.x & 63) == 0 && __any(valid)) atomicMax(&base[k0], m);
+        if ((threadIdx.x & 63) == 0 && any) atomicMax(&base[k0], m);
     } else if (valid) {
         atomicMax(&base[key], v);
     }

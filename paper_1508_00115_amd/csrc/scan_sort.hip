@@ -3,12 +3,13 @@
 // Both work on wave64 primitives: lane-shuffle scans inside a wavefront and
 // ballot-based digit matching for the sort's stable local ranking.
 #include "common.h"
+#include "scan_plan.h"
 
 namespace {
 
-constexpr int SCAN_BS = 256;
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = SCAN_BS * SCAN_ITEMS;
+using sph::SCAN_BS;
+using sph::SCAN_ITEMS;
+using sph::SCAN_TILE;
 
 // Inclusive scan inside one wavefront.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
@@ -46,6 +47,7 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const uint32_t* __restr
                                                          uint32_t* __restrict__ sums)
 {
     __shared__ uint32_t lds4[4];
+    if ((int64_t)blockIdx.x * SCAN_TILE >= n) return;  // whole block: no tile here
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t s = 0;
 #pragma unroll
@@ -65,6 +67,7 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t* in, uint
                                                         uint32_t* __restrict__ total)
 {
     __shared__ uint32_t lds4[4];
+    if ((int64_t)blockIdx.x * SCAN_TILE >= n) return;  // whole block: no tile, no sum to read
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
@@ -188,52 +191,32 @@ void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ui
         if (total) SPH_HIP(hipMemsetAsync(total, 0, sizeof(uint32_t), s));
         return;
     }
-    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 1) {
+    const ScanPlan P = scan_plan(n);
+    if (P.lv.empty()) {
         k_scan_apply<<<1, SCAN_BS, 0, s>>>(in, out, n, nullptr, total);
         SPH_HIP(hipGetLastError());
         return;
     }
-    // one scratch region holds the tile sums of every level, laid out consecutively
-    int64_t need = 0;
-    for (int64_t m = tiles; m > 1; m = (m + SCAN_TILE - 1) / SCAN_TILE) need += m + 64;
-    uint32_t* sums = ensure<uint32_t>(c, c->scan_tmp, (size_t)need + 64);
-    // levels laid out consecutively
-    std::vector<std::pair<uint32_t*, int64_t>> lv;
-    {
-        uint32_t* p = sums;
-        int64_t m = tiles;
-        lv.push_back({p, m});
-        p += m + 64;
-        while (m > 1) {
-            int64_t mm = (m + SCAN_TILE - 1) / SCAN_TILE;
-            if (mm <= 1) break;
-            lv.push_back({p, mm});
-            p += mm + 64;
-            m = mm;
-        }
-    }
-    // reduce down: level 0 sums of `in`, level k sums of level k-1
-    k_scan_reduce<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, lv[0].first);
+    uint32_t* sums = ensure<uint32_t>(c, c->scan_tmp, (size_t)P.scratch_words);
+    auto level = [&](size_t k) { return sums + P.lv[k].offset; };
+    // reduce down: level 0 holds the tile sums of `in`, level k those of level k - 1
+    k_scan_reduce<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, n, level(0));
     SPH_HIP(hipGetLastError());
-    for (size_t k = 1; k < lv.size(); ++k) {
-        k_scan_reduce<<<(unsigned)lv[k].second, SCAN_BS, 0, s>>>(lv[k - 1].first, lv[k - 1].second,
-                                                                  lv[k].first);
+    for (size_t k = 1; k < P.lv.size(); ++k) {
+        k_scan_reduce<<<(unsigned)P.lv[k].count, SCAN_BS, 0, s>>>(level(k - 1), P.lv[k - 1].count, level(k));
         SPH_HIP(hipGetLastError());
     }
-    // scan up: the last level fits one tile
-    {
-        auto& top = lv.back();
-        k_scan_apply<<<1, SCAN_BS, 0, s>>>(top.first, top.first, top.second, nullptr, nullptr);
+    // the last level fits one tile; then apply each level's scanned sums to
+    // the level below, one block per tile of it
+    const size_t top = P.lv.size() - 1;
+    k_scan_apply<<<1, SCAN_BS, 0, s>>>(level(top), level(top), P.lv[top].count, nullptr, nullptr);
+    SPH_HIP(hipGetLastError());
+    for (size_t k = top; k-- > 0;) {
+        k_scan_apply<<<(unsigned)scan_apply_grid(P, k), SCAN_BS, 0, s>>>(level(k), level(k), P.lv[k].count,
+                                                                         level(k + 1), nullptr);
         SPH_HIP(hipGetLastError());
     }
-    for (int k = (int)lv.size() - 2; k >= 0; --k) {
-        k_scan_apply<<<(unsigned)lv[k].second, SCAN_BS, 0, s>>>(lv[k].first, lv[k].first,
-                                                                 lv[k].second, lv[k + 1].first,
-                                                                 nullptr);
-        SPH_HIP(hipGetLastError());
-    }
-    k_scan_apply<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, out, n, lv[0].first, total);
+    k_scan_apply<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, out, n, level(0), total);
     SPH_HIP(hipGetLastError());
 }
 

@@ -264,17 +264,31 @@ def test_batched_full_size_sampled(gpu_lib):
         assert_within(err, TOL32, "batched box %d" % b)
 
 
-def test_large_full_size_sampled(gpu_lib):
+@pytest.fixture(scope="module")
+def large_set():
+    import time
+    t0 = time.time()
+    d = workloads.lognormal()
+    print("large N", d["pos"].shape[0], "generated in %.1f s" % (time.time() - t0), flush=True)
+    return d
+
+
+# library defaults, and the tighter cells tuned for the Sedov set (more tree
+# levels and cells; every scan over the 2^24 particles has two levels of tile sums)
+LARGE_PARAMS = [{}, {"h_margin": 1.05, "cell_ratio": 1.0, "leaf_target": 64, "cell_order": 2}]
+
+
+@pytest.mark.parametrize("params", LARGE_PARAMS)
+def test_large_full_size_sampled(gpu_lib, large_set, params):
     """The 2^24-particle log-normal set (h over ~1.5 decades) in one pass; a
     seeded sample against the oracle, with every pair partner of the sample
     solved by the oracle too."""
     import time
-    t0 = time.time()
-    d = workloads.lognormal()
+    d = large_set
     n = d["pos"].shape[0]
-    print("large N", n, "generated in %.1f s" % (time.time() - t0), flush=True)
+    print("large params", params, flush=True)
     t0 = time.time()
-    g = _gpu_pass(gpu_lib, d)
+    g = _gpu_pass(gpu_lib, d, **params)
     print("large GPU pass %.1f s" % (time.time() - t0), g["stats"], flush=True)
     assert g["stats"]["unconverged"] == 0
     rng = np.random.default_rng([1508, 4, 99])
