@@ -19,10 +19,10 @@
 // Lists hold distances only, so they serve cells whose candidates all share
 // one mass (checked on the staged chunks); they are sized for the common case
 // so many wavefronts fit on a CU. A particle whose list does not fit, or every
-// particle of a cell with mixed masses or more than 64 neighbour cells, is
-// left to k_density_scan: k_density queues such cells, and the re-scanning
-// kernel (launched after it on the same stream, idle when the queue is empty)
-// re-tests their candidates at every evaluation. A particle whose root lies
+// particle of a cell with mixed masses, is left to k_density_scan: k_density
+// queues such cells, and the re-scanning kernel (launched after it on the
+// same stream, idle when the queue is empty) solves them over longer lists of
+// distances and masses, 16 lanes per particle. A particle whose root lies
 // beyond its search radius is flagged; the host rebuilds the cells around a
 // larger guess and solves it again.
 //
@@ -472,18 +472,138 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
 // ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
 // Persistent wavefronts take the queued cells one at a time; a wavefront with
 // no queued cell left exits at once, so the launch costs little when nothing
-// was queued.
+// was queued. The flagged particles of a cell are compacted and taken four at
+// a time, RLPI = 16 lanes each. Phase A walks the cell's candidates once and
+// appends the distance and the mass of every hit inside the search radius to
+// the lane's lists (room for RLPI * RSLOTS hits per particle, four times what
+// the list kernel gives its widest groups); phase B runs Newton's method over
+// the lists with mass-weighted sums, so mixed masses need no other path. A
+// particle with still more hits re-tests every candidate at each evaluation
+// (rewalk_solve).
+constexpr int RLPI = 16;
+constexpr int RSLOTS = 32;
+
+// One evaluation over a lane's list (r and m at stride 64) at 1/h = hinv:
+// S0 = sum w, S1 = sum q w', M0 = sum m w, M1 = sum m q w', and the entries
+// inside h. The cubic spline as truncated powers, as in the list kernel:
+// w = 2 t^3 - 8 u^3 and q w' = q (24 u^2 - 6 t^2).
+struct ListSums {
+    float S0, S1, M0, M1;
+    int cnt;
+};
+
+__device__ __forceinline__ ListSums list_sums(const float* lr, const float* lm, int len, float hinv)
+{
+    float At = 0.f, Au = 0.f, Bt = 0.f, Bu = 0.f, mAt = 0.f, mAu = 0.f, mBt = 0.f, mBu = 0.f;
+    int cnt = 0;
+    for (int e = 0; e < len; ++e) {
+        const float r = lr[e * 64];
+        const float m = lm[e * 64];
+        const float q = r * hinv;
+        const float t = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+        const float u = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
+        const float t2 = t * t, u2 = u * u;
+        const float a = t2 * t, b = u2 * u, c = q * t2, d = q * u2;
+        At += a;
+        Au += b;
+        Bt += c;
+        Bu += d;
+        mAt = fmaf(m, a, mAt);
+        mAu = fmaf(m, b, mAu);
+        mBt = fmaf(m, c, mBt);
+        mBu = fmaf(m, d, mBu);
+        cnt += t > 0.0f ? 1 : 0;
+    }
+    ListSums L;
+    L.S0 = fmaf(2.0f, At, -8.0f * Au);
+    L.S1 = fmaf(24.0f, Bu, -6.0f * Bt);
+    L.M0 = fmaf(2.0f, mAt, -8.0f * mAu);
+    L.M1 = fmaf(24.0f, mBu, -6.0f * mBt);
+    L.cnt = cnt;
+    return L;
+}
+
+// Stage the chunk of candidates starting at c0 into the tile (unless a
+// single-tile cell already holds them all); returns its length.
+__device__ __forceinline__ int rescan_stage(const DensArgs& A, NbrCursor& cu, float4* tile, int c0, int nj,
+                                            bool single_tile, bool& loaded)
+{
+    if (single_tile && loaded) return nj;
+    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
+    const int len = cursor_chunk(cu, c0, SCAP);
+    stage_fast<1, SCAP>(tile, A.jd, cu.nb, c0 - cu.off0, len);
+    loaded = true;
+    return len;
+}
+
+// Newton's method re-testing every candidate at each evaluation, for the
+// lanes whose particle (active) has more hits than its lists hold.
+template <class I>
+__device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, float4* tile, int nj, bool single_tile,
+                                             bool& loaded, bool active, int i, float4 xi, int sub,
+                                             int64_t& cand_acc, I& inter_acc, I& sweep_acc, I& n_over,
+                                             I& n_unconv, int& max_ev)
+{
+    HSolve s = hsolve_init(A.hs[i], A.Hs[i], !active, ST_ACTIVE);
+    float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
+    int cnt = 0;
+    while (__any(!s.done)) {
+        const float h2 = s.h * s.h;
+        const float hinv = __builtin_amdgcn_rcpf(s.h);
+        S0 = S1 = M0 = M1 = 0.f;
+        cnt = 0;
+        const int groups_now = wave_count(!s.done && sub == 0);
+        int len;
+        for (int c0 = 0; c0 < nj; c0 += len) {
+            len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded);
+            for (int k = sub; k < len; k += RLPI) {
+                const float4 pj = tile[k];
+                const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool in = r2 < h2;
+                const float q = in ? __builtin_amdgcn_sqrtf(r2) * hinv : 1.0f;
+                float w, dw;
+                spline_w_dw(q, w, dw);
+                const float qdw = q * dw;
+                S0 += w;
+                S1 += qdw;
+                M0 = fmaf(pj.w, w, M0);
+                M1 = fmaf(pj.w, qdw, M1);
+                cnt += in ? 1 : 0;
+            }
+            if (!single_tile) wave_sync_lds();
+        }
+        cand_acc += (int64_t)groups_now * nj;
+        S0 = group_sum(S0, RLPI);
+        S1 = group_sum(S1, RLPI);
+        M0 = group_sum(M0, RLPI);
+        M1 = group_sum(M1, RLPI);
+        cnt = group_sum_i(cnt, RLPI);
+        if (s.done) continue;
+        if (sub == 0) sweep_acc += cnt;
+        hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
+    }
+    if (active && sub == 0) write_result(A, i, s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
+}
 
 __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
 {
-    __shared__ float4 tile[WAVES][SCAP];
+    __shared__ float4 tile[SCAP];
+    __shared__ float lr_all[(RSLOTS + 1) * 64];
+    __shared__ float lm_all[(RSLOTS + 1) * 64];
+    __shared__ int pidx[64];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    float4* sj = tile[wv];
-    int64_t cand_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
+    const int g = lane / RLPI, sub = lane & (RLPI - 1);
+    float* lr = lr_all + lane;
+    float* lm = lm_all + lane;
+    char* br = reinterpret_cast<char*>(lr_all);
+    char* bm = reinterpret_cast<char*>(lm_all);
+    const unsigned o_lane = 4u * (unsigned)lane, o_cap = o_lane + 256u * RSLOTS;
+    int64_t cand_acc = 0;  // wave-uniform
+    int list_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
     int max_ev = 0;
     const int n_queued = (int)A.ctr[CT_SCAN_CELLS];  // final: written by the list kernel
-    if ((int)blockIdx.x * WAVES + wv >= n_queued) return;
+    if ((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6) >= n_queued) return;
 
     for (;;) {
         int k = 0;
@@ -492,71 +612,83 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         if (k >= n_queued) break;
         const int4 ci = A.cells[A.scan_cells[k]];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
-        // neighbour records 64 at a time, chunks staged with independent loads
-        NbrCursor cu;
+        NbrCursor cu;  // neighbour records 64 at a time
         cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
-        const Groups G = make_groups(ni);
         const bool single_tile = np_all <= 64 && nj <= SCAP;
         bool loaded = false;
-        for (int ib = 0; ib < ni; ib += G.per_pass) {
-            const int gi = ib + G.g;
-            const bool valid = G.g < G.per_pass && gi < ni;
-            const int i = i0 + (valid ? gi : 0);
-            const float4 xi = A.jd[i];
-            const uint8_t st0 = A.st_s[i];
-            HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_SCAN, ST_ACTIVE);
-            if (wave_sum_i((!s.done && G.sub == 0) ? 1 : 0) == 0) continue;
-            float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
-            int cnt = 0;
-            while (__any(!s.done)) {
-                const float h2 = s.h * s.h;
-                const float hinv = __builtin_amdgcn_rcpf(s.h);
-                S0 = S1 = M0 = M1 = 0.f;
-                cnt = 0;
-                const int groups_now = wave_sum_i((!s.done && G.sub == 0) ? 1 : 0);
+        for (int b0 = 0; b0 < ni; b0 += 64) {
+            // the flagged particles of these 64, compacted into pidx
+            const bool flag = b0 + lane < ni && A.st_s[i0 + b0 + lane] == ST_SCAN;
+            const uint64_t fm = __ballot(flag);
+            const int nflag = __popcll(fm);
+            wave_sync_lds();  // the previous block's reads of pidx are done
+            if (flag) pidx[lanes_below(fm)] = b0 + lane;
+            wave_sync_lds();
+            for (int p0 = 0; p0 < nflag; p0 += 64 / RLPI) {
+                const bool valid = p0 + g < nflag;
+                const int i = i0 + pidx[valid ? p0 + g : p0];
+                const float4 xi = A.jd[i];
+                HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid, ST_ACTIVE);
+
+                // ---- phase A: every candidate once, hits inside H listed ----------
+                const float H2 = valid ? s.Hi * s.Hi : -1.0f;
+                unsigned o = o_lane;
                 int len;
                 for (int c0 = 0; c0 < nj; c0 += len) {
-                    if (single_tile && loaded) {
-                        len = nj;
-                    } else {
-                        cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
-                        len = cursor_chunk(cu, c0, SCAP);
-                        stage_fast<1, SCAP>(sj, A.jd, cu.nb, c0 - cu.off0, len);
-                        loaded = true;
-                    }
-                    for (int k = G.sub; k < len; k += G.lpi) {
-                        const float4 pj = sj[k];
+                    len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded);
+                    for (int kk = sub; kk < len; kk += RLPI) {
+                        const float4 pj = tile[kk];
                         const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const bool in = r2 < h2;
-                        const float q = in ? __builtin_amdgcn_sqrtf(r2) * hinv : 1.0f;
-                        float w, dw;
-                        spline_w_dw(q, w, dw);
-                        const float qdw = q * dw;
-                        S0 += w;
-                        S1 += qdw;
-                        M0 = fmaf(pj.w, w, M0);
-                        M1 = fmaf(pj.w, qdw, M1);
-                        cnt += in ? 1 : 0;
+                        const unsigned oo = min(o, o_cap);
+                        *reinterpret_cast<float*>(br + oo) = r2;
+                        *reinterpret_cast<float*>(bm + oo) = pj.w;
+                        o += r2 < H2 ? 256u : 0u;
                     }
                     if (!single_tile) wave_sync_lds();
                 }
-                cand_acc += (int64_t)groups_now * nj;
-                S0 = gsum(S0, G);
-                S1 = gsum(S1, G);
-                M0 = gsum(M0, G);
-                M1 = gsum(M1, G);
-                cnt = gsum_i(cnt, G);
-                if (s.done) continue;
-                if (G.sub == 0) sweep_acc += cnt;
-                hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
+                cand_acc += (int64_t)wave_count(valid && sub == 0) * nj;
+                const int nl = (int)((o - o_lane) >> 8);
+                const bool fits = group_sum_i(nl > RSLOTS ? 1 : 0, RLPI) == 0;
+
+                // ---- phase B: Newton's method over the lists ---------------------
+                const bool listed = valid && fits;
+                if (!listed) s.done = true;
+                const int len_l = listed ? nl : 0;
+                for (int e = 0; e < len_l; ++e) lr[e * 64] = __builtin_amdgcn_sqrtf(lr[e * 64]);
+                float fS0 = 0.f, fM0 = 0.f, fM1 = 0.f;
+                int fcnt = 0;
+                while (__any(!s.done)) {
+                    const float hinv = __builtin_amdgcn_rcpf(s.h);
+                    const int len_e = s.done ? 0 : len_l;
+                    const ListSums L = list_sums(lr, lm, len_e, hinv);
+                    list_acc += len_e;
+                    const float S0 = group_sum(L.S0, RLPI);
+                    const float S1 = group_sum(L.S1, RLPI);
+                    const float M0 = group_sum(L.M0, RLPI);
+                    const float M1 = group_sum(L.M1, RLPI);
+                    const int cnt = group_sum_i(L.cnt, RLPI);
+                    if (s.done) continue;
+                    if (sub == 0) sweep_acc += cnt;
+                    fS0 = S0;
+                    fM0 = M0;
+                    fM1 = M1;
+                    fcnt = cnt;
+                    hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
+                }
+                if (listed && sub == 0)
+                    write_result(A, i, s, fS0, fM0, fM1, fcnt, inter_acc, n_over, n_unconv, max_ev);
+
+                // ---- lists too short: re-test every candidate per evaluation -------
+                const bool rewalk = valid && !fits;
+                if (__any(rewalk))
+                    rewalk_solve(A, cu, tile, nj, single_tile, loaded, rewalk, i, xi, sub, cand_acc, inter_acc,
+                                 sweep_acc, n_over, n_unconv, max_ev);
             }
-            if (valid && G.sub == 0 && st0 == ST_SCAN)
-                write_result(A, i, s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
         }
     }
-    flush_counters(A, cand_acc, 0, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
+    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
 }
 
 }  // namespace

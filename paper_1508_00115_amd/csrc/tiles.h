@@ -91,39 +91,6 @@ __device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float lis
     return best;
 }
 
-// Lanes of a wavefront split among the particles of a cell: lpi lanes per
-// particle (2 to 16, any size), consecutive lanes forming a group. Lanes past
-// the last full group stay idle.
-struct Groups {
-    int lpi, per_pass, g, sub, base;
-};
-
-__device__ __forceinline__ Groups make_groups(int ni, int lpi_min = 2)
-{
-    Groups G;
-    const int lane = threadIdx.x & 63;
-    G.lpi = min(16, max(lpi_min, 64 / max(ni, 1)));
-    G.per_pass = 64 / G.lpi;
-    G.g = lane / G.lpi;
-    G.sub = lane - G.g * G.lpi;
-    G.base = G.g * G.lpi;
-    return G;
-}
-
-// Sum over the lanes of this lane's group, returned to every lane of it.
-__device__ __forceinline__ float gsum(float v, const Groups& G)
-{
-    float s = 0.0f;
-    for (int o = 0; o < G.lpi; ++o) s += __shfl(v, min(G.base + o, 63), 64);
-    return s;
-}
-__device__ __forceinline__ int gsum_i(int v, const Groups& G)
-{
-    int s = 0;
-    for (int o = 0; o < G.lpi; ++o) s += __shfl(v, min(G.base + o, 63), 64);
-    return s;
-}
-
 __device__ __forceinline__ int wave_sum_i(int v)
 {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
