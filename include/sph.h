@@ -83,7 +83,7 @@ typedef struct {
                              (1.26); h may grow by this factor before a rebuild */
     double  cell_ratio;   /* a cell below the top grid is split only while at
                              most one particle in eight of it has cell_ratio *
-                             search radius above half its width (1.0); the
+                             search radius above half its width (0.5); the
                              few wider ones keep a longer reach, never a
                              wrong result */
     int32_t leaf_target;  /* a cell with more particles than this is split when

@@ -22,7 +22,7 @@ sph_params with_defaults(const sph_params* in)
     if (!(p.n_tol > 0)) p.n_tol = 1e-6;
     if (p.max_iter <= 0) p.max_iter = 64;
     if (!(p.h_margin > 1.0)) p.h_margin = 1.26;
-    if (!(p.cell_ratio > 0)) p.cell_ratio = 1.0;
+    if (!(p.cell_ratio > 0)) p.cell_ratio = 0.5;
     if (p.leaf_target <= 0) p.leaf_target = 64;
     if (p.workspace_limit < 0) p.workspace_limit = 0;
     if (p.schedule != 1) p.schedule = 0;

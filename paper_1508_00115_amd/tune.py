@@ -77,9 +77,11 @@ def save(d: dict, result: dict, store: str) -> None:
         json.dump(table, fh, indent=1, sort_keys=True)
 
 
-def autotune(d: dict, device: int = 0, grid=None, reps: int = 5, cache: str | None = None) -> dict:
+def autotune(d: dict, device: int = 0, grid=None, reps: int = 5, cache: str | None = None,
+             progress: bool = False) -> dict:
     """Time every setting of ``grid`` on workload ``d`` (a dict as produced by
-    the ``workloads`` package) and return {"best": params, "table": [...]}."""
+    the ``workloads`` package) and return {"best": params, "table": [...]}.
+    progress: print one line per setting as it is timed."""
     import torch
 
     from . import Context
@@ -121,6 +123,9 @@ def autotune(d: dict, device: int = 0, grid=None, reps: int = 5, cache: str | No
             table.append({"params": params, "ms": None, "error": str(e)})
         finally:
             ctx.close()
+        if progress:
+            print("tune %d/%d %s ms %s" % (len(table), len(grid), json.dumps(params, sort_keys=True),
+                                           table[-1]["ms"]), flush=True)
     ok = [t for t in table if t["ms"] is not None]
     if not ok:
         raise RuntimeError("no cell setting ran: %s" % table)
@@ -151,7 +156,7 @@ def _main() -> int:
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
     d = workloads.make(args.workload)
-    res = autotune(d, 0)
+    res = autotune(d, 0, progress=True)
     save(d, res, args.out)
     print(json.dumps({"workload": args.workload, "best": res["best"], "best_ms": res["best_ms"]}))
     return 0

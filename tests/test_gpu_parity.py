@@ -123,7 +123,7 @@ def test_clustered_full_size_sampled(gpu_lib):
     assert_within(e, TOL32, "clustered")
 
 
-@pytest.mark.parametrize("params", [dict(leaf_target=8), dict(leaf_target=256), dict(cell_ratio=0.5),
+@pytest.mark.parametrize("params", [dict(leaf_target=8), dict(leaf_target=256), dict(cell_ratio=1.0),
                                     dict(h_margin=1.6), dict(h_margin=1.02), dict(schedule=1),
                                     dict(schedule=1, queue_batch=1), dict(schedule=1, queue_batch=64),
                                     dict(cell_order=1), dict(cell_order=1, schedule=1), dict(tile_cap=256),
