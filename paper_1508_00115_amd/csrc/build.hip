@@ -357,19 +357,16 @@ __device__ __forceinline__ void node_geom(int id, const int* nd_coord, const int
 // class spread over the whole 3x3x3 block: the hot kernels stage the list in
 // consecutive chunks, and a chunk that samples the whole neighbourhood gives
 // every particle a similar share of its neighbours (even lane lists).
-__global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ lf_node,
+__device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* __restrict__ lf_node,
                            const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
                            const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
                            const int* __restrict__ nd_leaf, const int* __restrict__ nd_child0,
                            const int* __restrict__ nd_child1, const int* __restrict__ top,
                            const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
-                           const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
-                           const uint32_t* __restrict__ p_start, int* __restrict__ p_leaf,
-                           float4* __restrict__ p_shift, int* __restrict__ p_code,
+                           const double* __restrict__ box_len, const uint32_t* __restrict__ p_start,
+                           int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
                            int64_t* __restrict__ ctr)
 {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n_leaves) return;
     const int A = lf_node[a];
     const int b = nd_box[A];
     const int G = box_G[b];
@@ -435,7 +432,33 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
                     }
                 }
             }
-    if (!fill) p_cnt[a] = cnt;
+    return cnt;
+}
+
+
+__global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ lf_node,
+                           const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
+                           const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
+                           const int* __restrict__ nd_leaf, const int* __restrict__ nd_child0,
+                           const int* __restrict__ nd_child1, const int* __restrict__ top,
+                           const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
+                           const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
+                           const uint32_t* __restrict__ p_start, int* __restrict__ p_leaf,
+                           float4* __restrict__ p_shift, int* __restrict__ p_code,
+                           int64_t* __restrict__ ctr)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cnt = 0;
+    if (a < n_leaves)
+        cnt = partners_of(a, fill, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf, nd_child0, nd_child1,
+                          top, box_top_base, box_G, box_len, p_start, p_leaf, p_shift, p_code, ctr);
+    if (!fill) {
+        if (a < n_leaves) p_cnt[a] = cnt;
+        // the records of all leaves in 64 bits: the list offsets are a 32-bit scan
+        int64_t v = cnt;
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long*)&ctr[CT_B_PAIRS64], (unsigned long long)v);
+    }
 }
 
 // Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
@@ -625,6 +648,9 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         const int64_t M = read_u32(d_tot, s);
         if (M == 0) break;
         const int64_t need = node_base + M;
+        // node ids are int and index 3 ints of nd_coord each
+        SPH_REQUIRE(need <= (int64_t)(INT32_MAX / 3), SPH_E_ARG,
+                    "the cell tree needs more than " + std::to_string(INT32_MAX / 3) + " nodes");
         if (need > c->node_cap) {
             const int64_t cap = std::max<int64_t>(need + need / 2, 1024);
             grow_keep<int>(c, c->nd_start, cap, node_base, s);
@@ -730,10 +756,14 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     scan_exclusive(c, p_cnt, p_start, nl, p_start + nl, s);
     uint32_t np = 0;
     int64_t bad2 = 0;
+    int64_t np64 = 0;
     SPH_HIP(hipMemcpyAsync(&np, p_start + nl, 4, hipMemcpyDeviceToHost, s));
     SPH_HIP(hipMemcpyAsync(&bad2, &ctr[CT_BAD_INPUT], 8, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(&np64, &ctr[CT_B_PAIRS64], 8, hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
     SPH_REQUIRE(bad2 == 0, SPH_E_HIP, "tree walk stack overflow");
+    SPH_REQUIRE(np64 <= (int64_t)UINT32_MAX && (int64_t)np == np64, SPH_E_ARG,
+                std::to_string(np64) + " (cell, neighbour cell) records: more than 2^32 - 1 cannot be indexed");
     c->n_pairs = np;
     int* p_leaf = ensure<int>(c, c->p_leaf, np);
     float4* p_shift = ensure<float4>(c, c->p_shift, np);

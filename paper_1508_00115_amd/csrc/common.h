@@ -73,6 +73,7 @@ enum {
     CT_TOTAL = 16,       // scratch for device-computed totals read by the host
     CT_SCAN_CELLS = 17,  // cells queued for the re-scanning density kernel
     CT_SCAN_POP = 18,    // next queued cell to take
+    CT_B_PAIRS64 = 19,   // build: (cell, neighbour cell) records, counted in 64 bits
     CT_QUEUE = 32,       // 8 work-queue heads (one per XCD), one 64-byte line each: CT_QUEUE + 8 q
     CT_SPREAD = 96,      // CT_SPREAD_SLOTS copies of the sums, CT_SUMS entries each
     CT_SPREAD_SLOTS = 64,
