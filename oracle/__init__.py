@@ -57,7 +57,7 @@ def _load():
         lib.orc_density.argtypes = [I64, P, P, D, D, I64, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.orc_density.restype = ctypes.c_int
         lib.orc_force.argtypes = [I64, P, P, P, P, P, P, P, D, D, D, I64, P,
-                                  P, P, P, P, P, P, P, ctypes.c_int, P]
+                                  P, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.orc_force.restype = ctypes.c_int
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -105,8 +105,10 @@ def density(pos, mass, L: float = 1.0, n_ngb: float = N_NGB, targets=None, h_sta
 def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
           alpha: float = ALPHA, targets=None, threads: int = 0) -> dict:
     """Acceleration, du/dt, their gross scales (sum of |pair term|), their
-    kernel scales (pair terms at full kernel slope) and the ordered pair count
-    #{j != i: r < max(h_i, h_j)} of the targets (all when None)."""
+    kernel scales (pair terms at full kernel slope), the ordered pair count
+    #{j != i: r < max(h_i, h_j)} and the signal velocity
+    max(c_i, max_j (c_i + c_j - 3 min(v_ij . rhat, 0))) of the targets (all
+    when None)."""
     lib = _load()
     pos = _f64(pos, (-1, 3))
     n = pos.shape[0]
@@ -114,14 +116,14 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
     arrs = [_f64(a) for a in (mass, u, h, rho, f)]
     tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
     acc = np.full((n, 3), np.nan)
-    out = {k: np.full(n, np.nan) for k in ("dudt", "gross_a", "gross_u", "scale_a", "scale_u")}
+    out = {k: np.full(n, np.nan) for k in ("dudt", "gross_a", "gross_u", "scale_a", "scale_u", "vsig")}
     npair = np.full(n, -1, dtype=np.int64)
     bad = ctypes.c_int64(-1)
     rc = lib.orc_force(n, _ptr(pos), _ptr(vel), *[_ptr(a) for a in arrs], float(L), float(gamma),
                        float(alpha), 0 if tg is None else tg.size, _ptr(tg), _ptr(acc),
                        _ptr(out["dudt"]), _ptr(out["gross_a"]), _ptr(out["gross_u"]),
-                       _ptr(out["scale_a"]), _ptr(out["scale_u"]), _ptr(npair), int(threads),
-                       ctypes.byref(bad))
+                       _ptr(out["scale_a"]), _ptr(out["scale_u"]), _ptr(npair), _ptr(out["vsig"]),
+                       int(threads), ctypes.byref(bad))
     if rc:
         raise RuntimeError("oracle force: %s (particle %d)" % (_ERR.get(rc, rc), bad.value))
     out["acc"] = acc
@@ -166,7 +168,7 @@ def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPH
     """Oracle over every box of a workload dict (see the ``workloads``
     package); per-particle outputs are concatenated in input order."""
     keys = ("h", "rho", "f", "nw", "nngb", "acc", "dudt", "gross_a", "gross_u", "scale_a", "scale_u",
-            "npair")
+            "npair", "vsig")
     parts = {k: [] for k in keys}
     cons = []
     t_d = t_f = 0.0

@@ -339,12 +339,17 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
  *                 against a scale that rounding in q cannot exceed.
  *   scale_u_out   sum_j m_j (|Phi_i| Dm_i + |Pi| (Dm_i + Dm_j) / 4) |v_ij . rhat|
  *   npair_out     #{j != i : r_ij < max(h_i, h_j)}
+ *   vsig_out      signal velocity max(c_i, max_j (c_i + c_j - 3 w_ij)) over the
+ *                 pairs with 0 < r_ij < max(h_i, h_j): the speed in the Courant
+ *                 condition of the time step (the Gadget-2 choice that the
+ *                 paper's force form follows)
  */
 int orc_force(int64_t n, const double *pos, const double *vel, const double *mass,
               const double *u, const double *h, const double *rho, const double *f,
               double L, double gamma, double alpha, int64_t n_targets, const int64_t *targets,
               double *acc_out, double *dudt_out, double *gross_a_out, double *gross_u_out,
-              double *scale_a_out, double *scale_u_out, int64_t *npair_out, int nthreads, int64_t *bad)
+              double *scale_a_out, double *scale_u_out, int64_t *npair_out, double *vsig_out, int nthreads,
+              int64_t *bad)
 {
     if (n <= 0 || !pos || !vel || !mass || !u || !h || !rho || !f || !acc_out || !dudt_out)
         return ORC_E_ARG;
@@ -391,6 +396,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             const double ci = sqrt(gamma * (gamma - 1.0) * u[i]);
             const double Phii = f[i] * Pi_ / (rho[i] * rho[i]);
             double ax = 0, ay = 0, az = 0, du = 0, ga = 0, gu = 0, sa = 0, su = 0;
+            double vsig = ci;
             int64_t np = 0;
             for (int64_t k = 0; k < c.n; ++k) {
                 int64_t j = c.j[k];
@@ -411,6 +417,8 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                             (vel[3 * i + 2] - vel[3 * j + 2]) * ez;
                 double wv = vr < 0.0 ? vr : 0.0;
                 double Pv = -alpha * (ci + cj - 3.0 * wv) * wv / (rho[i] + rho[j]);
+                double vs = ci + cj - 3.0 * wv;
+                if (vs > vsig) vsig = vs;
                 double Dbar = 0.5 * (Di + Dj);
                 double G = Phii * Di + Phij * Dj + Pv * Dbar;
                 double mj = mass[j];
@@ -435,6 +443,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             if (scale_a_out) scale_a_out[i] = sa;
             if (scale_u_out) scale_u_out[i] = su;
             if (npair_out) npair_out[i] = np;
+            if (vsig_out) vsig_out[i] = vsig;
         }
         cand_free(&c);
     }
