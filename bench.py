@@ -127,6 +127,8 @@ def main() -> int:
     ap.add_argument("--workload", default="sedov")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--leapfrog-steps", type=int, default=10,
+                    help="leapfrog steps timed after the pass (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner")
     ap.add_argument("--tune", action="store_true", help="re-run the autotuner instead of the stored table")
@@ -256,6 +258,35 @@ def main() -> int:
     ms_step64 = e0.elapsed_time(e1) / args.fp64_steps
     value64 = inter / (ms_step64 * 1e-3)
 
+    # ---- one leapfrog step (not part of `value`): half kick, drift, prediction,
+    #      cell build, pass, half kick and the Courant step, on a context that
+    #      records signal velocities --------------------------------------------------------
+    lf = None
+    if args.leapfrog_steps > 0:
+        ctx_l = sph.Context(0, signal_velocity=1, **params)
+        pos_l, vel_l, u_l, h_l = pos.clone(), vel.clone(), u.clone(), h0.clone()
+        ctx_l.build_cells(pos_l, h_l, d["box_first"], d["box_len"])
+        rl = ctx_l.pass_(mass, h_l, vel_l, u_l)
+        acc_l, dudt_l, rho_l = rl["acc"], rl["dudt"], rl["rho"]
+
+        def leap():
+            dt = ctx_l.timestep(0.3)
+            ctx_l.step(dt, pos_l, mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
+            return dt
+
+        leap()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.leapfrog_steps):
+            dt_last = leap()
+        torch.cuda.synchronize()
+        lf = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
+              "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
+              "build_ms": ctx_l.timings()["build_ms"],
+              "note": "wall time per step from the host (kick, drift, kick, cell build, pass, kick, "
+                      "time step), after one untimed step"}
+        ctx_l.close()
+
     # ---- roofline of the dominant kernel ------------------------------------------------
     dens_ms = float(np.mean(dk))  # the list kernel alone (the re-scan kernel is timed apart)
     force_ms = float(np.mean(fk))
@@ -305,6 +336,7 @@ def main() -> int:
         "force": {"candidates": sf["candidates_force"]},
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
         "speedup_vs_fp64_plain": value / value64,
+        "leapfrog": lf,
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
         "autotune_top5": None if tuned is None else [

@@ -106,6 +106,10 @@ typedef struct {
                              2 = the Morton ranges of 1, each ordered by
                              decreasing cost (L2 locality and a short tail);
                              other values mean 0 */
+    int32_t signal_velocity; /* nonzero: the force loop also records each
+                             particle's signal velocity, which sph_timestep
+                             needs (0: not recorded, one operation less per
+                             pair) */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP
@@ -241,6 +245,62 @@ sph_status sph_density_f64(sph_ctx* ctx, const double* mass, double* h, double* 
                            double* f_gradh, double* n_weighted, sph_stats* stats, void* stream);
 sph_status sph_force_f64(sph_ctx* ctx, const double* vel, const double* u, double* acc,
                          double* dudt, double* cons, sph_stats* stats, void* stream);
+
+/*
+ * Time integration. Section 2 marches the particles forward in time from
+ * their initial positions and velocities, the velocities updating the
+ * positions and the accelerations the velocities. These calls give the
+ * kick-drift-kick leapfrog of the Gadget-2 scheme whose force the paper
+ * uses. One step of length dt, with acc and dudt holding the rates at its
+ * start:
+ *
+ *   sph_kick(dt/2, acc, dudt, vel, u -> vel, u)        half kick
+ *   sph_drift(dt, vel, pos)                            positions at t + dt
+ *   sph_kick(dt/2, acc, dudt, vel, u -> vel_p, u_p)    v and u predicted to t + dt
+ *   sph_build_cells(pos, h), sph_pass(mass, h, ..., vel_p, u_p, acc, dudt)
+ *   sph_kick(dt/2, acc, dudt, vel, u -> vel, u)        closing half kick
+ *
+ * and sph_timestep after the pass gives the next dt. The force sees the
+ * predicted v and u: its viscosity and pressure need both at t + dt.
+ */
+
+/*
+ * vel_out = vel_in + acc dt and u_out = u_in + dudt dt for the n particles of
+ * the last sph_build_cells, computed in FP64 and rounded to FP32.
+ *   dt               step (finite, any sign)
+ *   acc, dudt        device, 3n and n floats
+ *   vel_in, u_in     device, 3n and n floats
+ *   vel_out, u_out   device, 3n and n floats out; may be vel_in and u_in
+ * Errors: SPH_E_ARG (null pointer, non-finite dt), SPH_E_STATE (no build yet),
+ * SPH_E_HIP. Does not synchronise.
+ */
+sph_status sph_kick(sph_ctx* ctx, double dt, const float* acc, const float* dudt, const float* vel_in,
+                    const float* u_in, float* vel_out, float* u_out, void* stream);
+
+/*
+ * pos += vel dt in FP64, each particle wrapped into its periodic box (the
+ * boxes of the last sph_build_cells). The cells no longer match the
+ * positions afterwards: sph_density, sph_force, sph_pass and sph_timestep
+ * need a new sph_build_cells first.
+ *   dt    step (finite, any sign)
+ *   vel   device, 3n floats
+ *   pos   device, 3n doubles, in and out
+ * Errors: SPH_E_ARG, SPH_E_STATE (no build yet), SPH_E_HIP. Does not
+ * synchronise.
+ */
+sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, void* stream);
+
+/*
+ * Courant time step from the last force pass: *dt = courant * min_i h_i /
+ * v_sig,i, where v_sig,i = max(c_i, max_j (c_i + c_j - 3 w_ij)) over the
+ * pairs of i in the force loop (the signal velocity of its viscosity term);
+ * +inf when every v_sig is 0. Needs sph_params.signal_velocity.
+ *   courant  > 0 (0.1 to 0.4 is usual)
+ *   dt       host, out
+ * Errors: SPH_E_ARG, SPH_E_STATE (no force pass with signal velocities since
+ * the last build), SPH_E_HIP. Synchronises `stream`.
+ */
+sph_status sph_timestep(sph_ctx* ctx, double courant, double* dt, void* stream);
 
 /* Copy the durations of the last calls into *out (host). Errors: SPH_E_ARG. */
 sph_status sph_get_timings(const sph_ctx* ctx, sph_timings* out);

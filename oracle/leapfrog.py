@@ -47,7 +47,8 @@ def drift(pos, vel, dt: float, L: float):
     """Positions after a drift of length dt, wrapped into [0, L)."""
     x = np.asarray(pos, dtype=np.float64).reshape(-1, 3) + np.asarray(vel, dtype=np.float64).reshape(-1, 3) * dt
     x = x - L * np.floor(x / L)
-    x[x >= L] = 0.0
+    x[x < 0.0] += L  # x / L rounded up to an integer
+    x[x >= L] = 0.0  # rounded up to L
     return x
 
 

@@ -27,7 +27,8 @@ SPH_E_STATE = 6
 
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
-           "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info")
+           "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info",
+           "sph_kick", "sph_drift", "sph_timestep")
 
 
 class sph_params(ctypes.Structure):
@@ -37,7 +38,8 @@ class sph_params(ctypes.Structure):
                 ("cell_ratio", ctypes.c_double), ("leaf_target", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("queue_batch", ctypes.c_int32),
-                ("tile_cap", ctypes.c_int32), ("cell_order", ctypes.c_int32)]
+                ("tile_cap", ctypes.c_int32), ("cell_order", ctypes.c_int32),
+                ("signal_velocity", ctypes.c_int32)]
 
 
 class sph_stats(ctypes.Structure):
@@ -117,6 +119,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_last_error.restype = ctypes.c_char_p
     lib.sph_version.argtypes = []
     lib.sph_version.restype = ctypes.c_char_p
+    lib.sph_kick.argtypes = [P, ctypes.c_double, P, P, P, P, P, P, P]
+    lib.sph_kick.restype = ctypes.c_int
+    lib.sph_drift.argtypes = [P, ctypes.c_double, P, P, P]
+    lib.sph_drift.restype = ctypes.c_int
+    lib.sph_timestep.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
+    lib.sph_timestep.restype = ctypes.c_int
     lib.sph_struct_size.argtypes = [ctypes.c_int32]
     lib.sph_struct_size.restype = ctypes.c_int32
     _lib = lib
@@ -179,6 +187,18 @@ def sph_density_f64(ctx, mass, h, rho, f, nw, stats, stream) -> int:
 
 def sph_force_f64(ctx, vel, u, acc, dudt, cons, stats, stream) -> int:
     return load_library().sph_force_f64(ctx, vel, u, acc, dudt, cons, stats, stream)
+
+
+def sph_kick(ctx, dt, acc, dudt, vel_in, u_in, vel_out, u_out, stream) -> int:
+    return load_library().sph_kick(ctx, dt, acc, dudt, vel_in, u_in, vel_out, u_out, stream)
+
+
+def sph_drift(ctx, dt, vel, pos, stream) -> int:
+    return load_library().sph_drift(ctx, dt, vel, pos, stream)
+
+
+def sph_timestep(ctx, courant, dt_out, stream) -> int:
+    return load_library().sph_timestep(ctx, courant, dt_out, stream)
 
 
 def sph_get_timings(ctx, out) -> int:
@@ -261,6 +281,7 @@ class Context:
         _check(rc, self.ctx)
         self.n = n
         self.n_boxes = len(bl)
+        self.box_first, self.box_len = bf, bl
 
     def density(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
         """h is updated in place; returns the output tensors and the stats."""
@@ -312,6 +333,56 @@ class Context:
         _check(rc, self.ctx)
         return {"h": h, "rho": rho, "f": f, "nw": nw, "acc": acc, "dudt": dudt, "cons": cb,
                 "stats": st.as_dict()}
+
+    # ---- time integration (kick-drift-kick leapfrog) ------------------------------------
+
+    def kick(self, dt, acc, dudt, vel, u, vel_out=None, u_out=None, stream=None):
+        """sph_kick: vel_out = vel + acc dt, u_out = u + dudt dt (in place by default)."""
+        import torch
+        n = self.n
+        vel_out = vel if vel_out is None else vel_out
+        u_out = u if u_out is None else u_out
+        rc = sph_kick(self.ctx, float(dt), _dev(acc, torch.float32, (n, 3), "acc"),
+                      _dev(dudt, torch.float32, (n,), "dudt"), _dev(vel, torch.float32, (n, 3), "vel"),
+                      _dev(u, torch.float32, (n,), "u"), _dev(vel_out, torch.float32, (n, 3), "vel_out"),
+                      _dev(u_out, torch.float32, (n,), "u_out"), _stream(stream))
+        _check(rc, self.ctx)
+        return vel_out, u_out
+
+    def drift(self, dt, vel, pos, stream=None):
+        """sph_drift: pos += vel dt, wrapped into the boxes (the cells must be rebuilt after)."""
+        import torch
+        n = self.n
+        rc = sph_drift(self.ctx, float(dt), _dev(vel, torch.float32, (n, 3), "vel"),
+                       _dev(pos, torch.float64, (n, 3), "pos"), _stream(stream))
+        _check(rc, self.ctx)
+        return pos
+
+    def timestep(self, courant, stream=None) -> float:
+        """sph_timestep: courant * min h / v_sig after the last force pass."""
+        out = ctypes.c_double()
+        rc = sph_timestep(self.ctx, float(courant), ctypes.byref(out), _stream(stream))
+        _check(rc, self.ctx)
+        return out.value
+
+    def step(self, dt, pos, mass, h, vel, u, acc, dudt, box_first=None, box_len=None, rho=None, f=None,
+             stream=None) -> dict:
+        """One kick-drift-kick step of length dt (every array in place): acc
+        and dudt hold the rates at the start and hold those at the end on
+        return. The sequence of sph.h (half kick, drift, prediction, cells,
+        pass, half kick); the predicted v and u live in two scratch tensors.
+        The boxes default to those of the last build_cells."""
+        import torch
+        vel_p = torch.empty_like(vel)
+        u_p = torch.empty_like(u)
+        self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
+        self.drift(dt, vel, pos, stream=stream)
+        self.kick(0.5 * dt, acc, dudt, vel, u, vel_p, u_p, stream=stream)
+        self.build_cells(pos, h, self.box_first if box_first is None else box_first,
+                         self.box_len if box_len is None else box_len, stream=stream)
+        r = self.pass_(mass, h, vel_p, u_p, rho=rho, f=f, acc=acc, dudt=dudt, stream=stream)
+        self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
+        return r
 
     def density_f64(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
         import torch

@@ -813,6 +813,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         c->binfo.max_candidates = hc[CT_B_MAX_NJ];
     }
     c->built = true;
+    c->vsig_valid = false;  // signal velocities belong to the cells of the last force pass
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
     c->density64_done = false;

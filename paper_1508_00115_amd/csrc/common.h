@@ -74,6 +74,7 @@ enum {
     CT_SCAN_CELLS = 17,  // cells queued for the re-scanning density kernel
     CT_SCAN_POP = 18,    // next queued cell to take
     CT_B_PAIRS64 = 19,   // build: (cell, neighbour cell) records, counted in 64 bits
+    CT_DT_MIN = 20,      // sph_timestep: smallest h / v_sig (float bits in the low word)
     CT_QUEUE = 32,       // 8 work-queue heads (one per XCD), one 64-byte line each: CT_QUEUE + 8 q
     CT_SPREAD = 96,      // CT_SPREAD_SLOTS copies of the sums, CT_SUMS entries each
     CT_SPREAD_SLOTS = 64,
@@ -184,6 +185,8 @@ struct sph_ctx {
     sph::Buf st_s;           // uint8, sorted copy of status
     sph::Buf scan_cells;     // int: leaves holding particles left to the re-scan
     sph::Buf jf;             // 3 float4 per particle for the force loop
+    sph::Buf vsig_s;         // float, sorted: signal velocity of the last force pass
+    bool vsig_valid = false; // vsig_s matches the current cells and h
     sph::Buf counters;       // int64[CT_COUNT]
     sph::Buf cons_d;         // double, 4 per box (FP32 force loop)
     sph::Buf cons_part;      // double, 4 per leaf: each cell's share of cons_d
@@ -379,6 +382,11 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
               const float* u, float* acc, float* dudt, double* cons, sph_stats* st, hipStream_t s);
 void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double* f, double* nw,
                  sph_stats* st, hipStream_t s);
+// Leapfrog pieces (integrate.hip).
+void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const float* vel_in, const float* u_in,
+          float* vel_out, float* u_out, hipStream_t s);
+void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s);
+double timestep(sph_ctx* c, double courant, hipStream_t s);
 void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, double* dudt,
                double* cons, sph_stats* st, hipStream_t s);
 

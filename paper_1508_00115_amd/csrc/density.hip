@@ -793,7 +793,7 @@ void density_buffers(sph_ctx* c)
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, sph_stats* st,
                  hipStream_t s)
 {
-    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density before sph_build_cells");
+    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density needs cells for the current positions (sph_build_cells, also after sph_drift)");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
     const int64_t n = c->n;
     int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;

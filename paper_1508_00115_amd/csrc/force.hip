@@ -62,6 +62,7 @@ struct ForceArgs {
     float* acc;
     float* dudt;
     double* cons_part;  // 4 per leaf, may be null
+    float* vsig;        // sorted: signal velocity per particle (k_force<true> only)
     int64_t* ctr;
     WorkSched W;
     float alpha;
@@ -108,6 +109,9 @@ __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
     wave_sync_lds();
 }
 
+// VSIG: also record each particle's signal velocity max(c_i, max_j (c_i +
+// c_j - 3 w_ij)) over its pairs, for the Courant time step.
+template <bool VSIG>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
     __shared__ float4 tile[3 * FCAP];
@@ -152,6 +156,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
             float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
+            float vmax = 0.f;  // (VSIG) largest c_i + c_j - 3 w_ij of this lane's pairs
             int cnt = 0;
             ChunkRegs<3, FCAP> R;
             const bool stream_chunks = !(single_tile && loaded);
@@ -204,7 +209,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float Dj = K8PI * hinv2_j * hinv2_j * spline_dw_r(r, hinv_j);
                     const float vr = ((i1v.x - p1.x) * dx + (i1v.y - p1.y) * dy + (i1v.z - p1.z) * dz) * rinv;
                     const float wv_ = fminf(vr, 0.0f);
-                    const float visc = -A.alpha * (c_i + p2.z - 3.0f * wv_) * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
+                    const float vsig_ij = c_i + p2.z - 3.0f * wv_;
+                    const float visc = -A.alpha * vsig_ij * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
+                    if constexpr (VSIG) vmax = fmaxf(vmax, vsig_ij);
                     const float Dbar = 0.5f * (Di + Dj);
                     const float G = fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
                     const float mGr = p1.w * G * rinv;
@@ -223,6 +230,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             az = group_sum(az, lpi);
             du = group_sum(du, lpi);
             cnt = group_sum_i(cnt, lpi);
+            if constexpr (VSIG) vmax = group_max(vmax, lpi);
             const bool leader = valid && sub == 0;
             cand_acc += (int64_t)wave_count(leader) * kept;
             double cm[4] = {0.0, 0.0, 0.0, 0.0};
@@ -232,6 +240,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 A.acc[3 * (int64_t)o + 1] = ay;
                 A.acc[3 * (int64_t)o + 2] = az;
                 A.dudt[o] = du;
+                if constexpr (VSIG) A.vsig[i] = fmaxf(vmax, c_i);
                 inter_acc += cnt;
                 const double m = i1v.w;
                 cm[0] = m * ax;
@@ -327,13 +336,19 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.acc = acc;
     A.dudt = dudt;
     A.cons_part = cons_d ? static_cast<double*>(c->cons_part.p) : nullptr;
+    const bool vsig = c->prm.signal_velocity != 0;
+    A.vsig = vsig ? static_cast<float*>(c->vsig_s.p) : nullptr;
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
     A.list_work = (float)(4.0 * c->prm.n_ngb);  // ~n_ngb pairs per particle at ~4 tests' cost each
     if (events) ev_record(c, EV_FORCE_K0, s);
-    k_force<<<grid, BS, 0, s>>>(A);
+    if (vsig)
+        k_force<true><<<grid, BS, 0, s>>>(A);
+    else
+        k_force<false><<<grid, BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
+    c->vsig_valid = vsig;
     if (events) ev_record(c, EV_FORCE_K1, s);
     if (cons_d) {
         k_cons_reduce<<<c->n_boxes, 256, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);
@@ -344,6 +359,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
 double* force_buffers(sph_ctx* c, bool cons)
 {
     ensure<float4>(c, c->jf, 3 * c->n);
+    if (c->prm.signal_velocity) ensure<float>(c, c->vsig_s, c->n);
     if (!cons) return nullptr;
     ensure<double>(c, c->cons_part, (size_t)4 * c->n_leaves);
     return ensure<double>(c, c->cons_d, (size_t)4 * c->n_boxes);

@@ -1,0 +1,107 @@
+// Time integration: the pieces of a kick-drift-kick leapfrog (section 2 of the
+// Swift paper: particles are marched forward in time, positions with their
+// velocities and velocities with their accelerations; the leapfrog is the
+// Gadget-2 scheme whose force the paper uses) and the Courant time step from
+// the signal velocities the force loop records.
+//
+// Kick and drift stream caller-order arrays once each (HBM-bound, one pass
+// over the components, fully coalesced); the time step reduces h / v_sig
+// over the sorted particles with one atomic per wavefront.
+#include "common.h"
+
+#include <cmath>
+
+namespace {
+
+// vel_out = vel_in + acc dt over the 3n components, u_out = u_in + dudt dt
+// over the first n threads; FP64 arithmetic rounded once to FP32.
+__global__ void k_kick(int64_t n, double dt, const float* __restrict__ acc, const float* __restrict__ dudt,
+                       const float* vel_in, const float* u_in, float* vel_out, float* u_out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 3 * n) vel_out[t] = (float)((double)vel_in[t] + (double)acc[t] * dt);
+    if (t < n) u_out[t] = (float)((double)u_in[t] + (double)dudt[t] * dt);
+}
+
+// pos += vel dt over the 3n components, wrapped into the particle's box.
+__global__ void k_drift(int64_t n, double dt, const float* __restrict__ vel, double* __restrict__ pos,
+                        const int64_t* __restrict__ box_first, int n_boxes, const double* __restrict__ box_len)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n) return;
+    const double L = box_len[n_boxes > 1 ? box_of(box_first, n_boxes, t / 3) : 0];
+    const double x = pos[t] + (double)vel[t] * dt;
+    double y = x - L * floor(x / L);
+    if (y < 0.0) y += L;  // x / L rounded up to an integer
+    if (y >= L) y = 0.0;  // y rounded up to L
+    pos[t] = y;  // a non-finite position stays non-finite: the next build rejects it
+}
+
+// Smallest h / v_sig over the particles with v_sig > 0, as float bits
+// (non-negative floats order like their bit patterns) into *out, which holds
+// +inf beforehand.
+__global__ void k_dt_min(int64_t n, const float* __restrict__ hs, const float* __restrict__ vsig,
+                         unsigned* __restrict__ out)
+{
+    float m = INFINITY;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const float v = vsig[p];
+        if (v > 0.0f) m = fminf(m, hs[p] / v);
+    }
+    for (int o = 32; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(m));
+}
+
+}  // namespace
+
+namespace sph {
+
+void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const float* vel_in, const float* u_in,
+          float* vel_out, float* u_out, hipStream_t s)
+{
+    SPH_REQUIRE(c->n > 0, SPH_E_STATE, "sph_kick before sph_build_cells");
+    SPH_REQUIRE(acc && dudt && vel_in && u_in && vel_out && u_out, SPH_E_ARG, "null acc/dudt/vel/u");
+    SPH_REQUIRE(std::isfinite(dt), SPH_E_ARG, "dt must be finite");
+    const int64_t n = c->n;
+    k_kick<<<blocks_for(3 * n, 256), 256, 0, s>>>(n, dt, acc, dudt, vel_in, u_in, vel_out, u_out);
+    SPH_HIP(hipGetLastError());
+}
+
+void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s)
+{
+    SPH_REQUIRE(c->n > 0 && c->box_first.p && c->box_len.p, SPH_E_STATE, "sph_drift before sph_build_cells");
+    SPH_REQUIRE(vel && pos, SPH_E_ARG, "null vel/pos");
+    SPH_REQUIRE(std::isfinite(dt), SPH_E_ARG, "dt must be finite");
+    const int64_t n = c->n;
+    k_drift<<<blocks_for(3 * n, 256), 256, 0, s>>>(n, dt, vel, pos, static_cast<int64_t*>(c->box_first.p),
+                                                    c->n_boxes, static_cast<double*>(c->box_len.p));
+    SPH_HIP(hipGetLastError());
+    // the cells, offsets and signal velocities describe the old positions
+    c->built = false;
+    c->density_done = false;
+    c->density64_done = false;
+    c->vsig_valid = false;
+}
+
+double timestep(sph_ctx* c, double courant, hipStream_t s)
+{
+    SPH_REQUIRE(std::isfinite(courant) && courant > 0.0, SPH_E_ARG, "courant must be finite and > 0");
+    SPH_REQUIRE(c->built && c->vsig_valid, SPH_E_STATE,
+                "sph_timestep needs a force pass with sph_params.signal_velocity since the last build");
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    unsigned* slot = reinterpret_cast<unsigned*>(&ctr[CT_DT_MIN]);
+    fill_u32(slot, 0x7f800000u, 1, s);  // +inf
+    const int64_t n = c->n;
+    const int grid = (int)std::min<int64_t>(blocks_for(n, 256), (int64_t)c->n_cu * 4);
+    k_dt_min<<<std::max(grid, 1), 256, 0, s>>>(n, static_cast<float*>(c->hs.p), static_cast<float*>(c->vsig_s.p),
+                                               slot);
+    SPH_HIP(hipGetLastError());
+    unsigned bits = 0;
+    SPH_HIP(hipMemcpyAsync(&bits, slot, 4, hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    float m;
+    std::memcpy(&m, &bits, 4);
+    return courant * (double)m;
+}
+
+}  // namespace sph

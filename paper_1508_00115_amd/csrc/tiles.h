@@ -134,6 +134,15 @@ __device__ __forceinline__ float group_sum(float v, int lpi)
     if (lpi >= 16) v += dpp_f<0x140>(v);
     return v;
 }
+// Largest value over aligned groups of lpi lanes, with the same patterns.
+__device__ __forceinline__ float group_max(float v, int lpi)
+{
+    if (lpi >= 2) v = fmaxf(v, dpp_f<0xB1>(v));
+    if (lpi >= 4) v = fmaxf(v, dpp_f<0x4E>(v));
+    if (lpi >= 8) v = fmaxf(v, dpp_f<0x141>(v));
+    if (lpi >= 16) v = fmaxf(v, dpp_f<0x140>(v));
+    return v;
+}
 __device__ __forceinline__ int group_sum_i(int v, int lpi)
 {
     if (lpi >= 2) v += dpp_i<0xB1>(v);
