@@ -257,11 +257,13 @@ sph_status sph_force_f64(sph_ctx* ctx, const double* vel, const double* u, doubl
  *   sph_kick(dt/2, acc, dudt, vel, u -> vel, u)        half kick
  *   sph_drift(dt, vel, pos)                            positions at t + dt
  *   sph_kick(dt/2, acc, dudt, vel, u -> vel_p, u_p)    v and u predicted to t + dt
- *   sph_build_cells(pos, h), sph_pass(mass, h, ..., vel_p, u_p, acc, dudt)
+ *   sph_pass(mass, h, ..., vel_p, u_p, acc, dudt)      rates at t + dt
  *   sph_kick(dt/2, acc, dudt, vel, u -> vel, u)        closing half kick
  *
  * and sph_timestep after the pass gives the next dt. The force sees the
- * predicted v and u: its viscosity and pressure need both at t + dt.
+ * predicted v and u: its viscosity and pressure need both at t + dt. The
+ * cells are kept across drifts (below); sph_build_cells is only needed for
+ * new particles or new boxes.
  */
 
 /*
@@ -279,14 +281,21 @@ sph_status sph_kick(sph_ctx* ctx, double dt, const float* acc, const float* dudt
 
 /*
  * pos += vel dt in FP64, each particle wrapped into its periodic box (the
- * boxes of the last sph_build_cells). The cells no longer match the
- * positions afterwards: sph_density, sph_force, sph_pass and sph_timestep
- * need a new sph_build_cells first.
+ * boxes of the last sph_build_cells). The cells are kept. The library bounds
+ * the distance every particle has moved since the cells were built by delta,
+ * the sum over drifts of sqrt(3) max |v dt|. Its offsets from the cell
+ * centres follow the particle, the density searches h_margin * h_guess -
+ * 2 delta instead of h_margin * h_guess, and the force widens each cell box
+ * by delta. Every pair within reach is still found. The next sph_density or
+ * sph_pass rebuilds the cells first once 2 delta exceeds
+ * (1 - 1/h_margin) times the smallest search radius, or when an h outgrows
+ * the reduced radius. After a drift, sph_force and sph_timestep need a
+ * density pass first.
  *   dt    step (finite, any sign)
  *   vel   device, 3n floats
  *   pos   device, 3n doubles, in and out
- * Errors: SPH_E_ARG, SPH_E_STATE (no build yet), SPH_E_HIP. Does not
- * synchronise.
+ * Errors: SPH_E_ARG (a non-finite position is reported by the next density
+ * pass), SPH_E_STATE (no cells yet), SPH_E_HIP. Does not synchronise.
  */
 sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, void* stream);
 
@@ -298,7 +307,7 @@ sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, voi
  *   courant  > 0 (0.1 to 0.4 is usual)
  *   dt       host, out
  * Errors: SPH_E_ARG, SPH_E_STATE (no force pass with signal velocities since
- * the last build), SPH_E_HIP. Synchronises `stream`.
+ * the last build or drift), SPH_E_HIP. Synchronises `stream`.
  */
 sph_status sph_timestep(sph_ctx* ctx, double courant, double* dt, void* stream);
 

@@ -281,7 +281,6 @@ class Context:
         _check(rc, self.ctx)
         self.n = n
         self.n_boxes = len(bl)
-        self.box_first, self.box_len = bf, bl
 
     def density(self, mass, h, rho=None, f=None, nw=None, stream=None) -> dict:
         """h is updated in place; returns the output tensors and the stats."""
@@ -350,7 +349,7 @@ class Context:
         return vel_out, u_out
 
     def drift(self, dt, vel, pos, stream=None):
-        """sph_drift: pos += vel dt, wrapped into the boxes (the cells must be rebuilt after)."""
+        """sph_drift: pos += vel dt, wrapped into the boxes (the cells are kept)."""
         import torch
         n = self.n
         rc = sph_drift(self.ctx, float(dt), _dev(vel, torch.float32, (n, 3), "vel"),
@@ -365,21 +364,18 @@ class Context:
         _check(rc, self.ctx)
         return out.value
 
-    def step(self, dt, pos, mass, h, vel, u, acc, dudt, box_first=None, box_len=None, rho=None, f=None,
-             stream=None) -> dict:
+    def step(self, dt, pos, mass, h, vel, u, acc, dudt, rho=None, f=None, stream=None) -> dict:
         """One kick-drift-kick step of length dt (every array in place): acc
         and dudt hold the rates at the start and hold those at the end on
-        return. The sequence of sph.h (half kick, drift, prediction, cells,
-        pass, half kick); the predicted v and u live in two scratch tensors.
-        The boxes default to those of the last build_cells."""
+        return. The sequence of sph.h (half kick, drift, prediction, pass,
+        half kick; the library keeps or rebuilds the cells); the predicted v
+        and u live in two scratch tensors."""
         import torch
         vel_p = torch.empty_like(vel)
         u_p = torch.empty_like(u)
         self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
         self.drift(dt, vel, pos, stream=stream)
         self.kick(0.5 * dt, acc, dudt, vel, u, vel_p, u_p, stream=stream)
-        self.build_cells(pos, h, self.box_first if box_first is None else box_first,
-                         self.box_len if box_len is None else box_len, stream=stream)
         r = self.pass_(mass, h, vel_p, u_p, rho=rho, f=f, acc=acc, dudt=dudt, stream=stream)
         self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
         return r

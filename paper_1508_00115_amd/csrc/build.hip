@@ -530,13 +530,28 @@ __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, cons
     const int b = nd_box[id];
     double c[3], w;
     node_geom(id, nd_coord, nd_level, box_len[b] / box_G[b], c, w);
-    double x[3];
+    const double L = box_len[b];
+    double d[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        x[a] = pos_w[3 * (int64_t)o + a];
-        pos_s[3 * p + a] = x[a];
+        // the image of the particle nearest its leaf: itself at a build; after
+        // a drift across the box boundary, the one on the leaf's side
+        const double x = pos_w[3 * (int64_t)o + a];
+        const double img = L * rint((x - c[a]) / L);
+        pos_s[3 * p + a] = x - img;
+        d[a] = (x - c[a]) - img;
     }
-    xrel[p] = make_float4((float)(x[0] - c[0]), (float)(x[1] - c[1]), (float)(x[2] - c[2]), 0.0f);
+    xrel[p] = make_float4((float)d[0], (float)d[1], (float)d[2], 0.0f);
+}
+
+// Smallest search radius (float bits; non-negative floats order like their bits).
+__global__ void k_min_H(int64_t n, const float* __restrict__ Hs, unsigned* __restrict__ out)
+{
+    float m = INFINITY;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        m = fminf(m, Hs[p]);
+    for (int o = 32; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(m));
 }
 
 int ceil_log2(uint64_t v)
@@ -803,8 +818,19 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_sorted_fill<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<double*>(c->pos_w.p), leaf_of, lf_node,
                                                    nd_coord, nd_level, nd_box, box_G, box_len, pos_s, xrel);
     SPH_HIP(hipGetLastError());
+    // no drift since this build; the smallest search radius bounds how far
+    // the particles may drift before the cells are rebuilt
+    unsigned* drift = ensure<unsigned>(c, c->drift, 4);
+    fill_u32(drift, 0u, 2, s);
+    fill_u32(drift + 2, 0x7f800000u, 1, s);
+    k_min_H<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, BS), 1024)), BS, 0, s>>>(n, Hs,
+                                                                                                  drift + 2);
+    SPH_HIP(hipGetLastError());
+    unsigned hmin_bits = 0;
+    SPH_HIP(hipMemcpyAsync(&hmin_bits, drift + 2, 4, hipMemcpyDeviceToHost, s));
     {
-        const int64_t* hc = read_counters(c, s);
+        const int64_t* hc = read_counters(c, s);  // synchronises: hmin_bits is in
+        std::memcpy(&c->h_min, &hmin_bits, 4);
         c->binfo.n_cells = nl;
         c->binfo.n_pairs = c->n_pairs;
         c->binfo.candidate_pairs = hc[CT_B_CAND_PAIRS];
@@ -813,6 +839,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         c->binfo.max_candidates = hc[CT_B_MAX_NJ];
     }
     c->built = true;
+    c->drift_pending = false;
     c->vsig_valid = false;  // signal velocities belong to the cells of the last force pass
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
@@ -847,13 +874,27 @@ void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const do
     build_from_wrapped(c, s);
 }
 
+// Offsets of every particle from its leaf centre (and the sorted FP64
+// positions) from the current positions, keeping the cells: after a drift.
+void refresh_offsets(sph_ctx* c, hipStream_t s)
+{
+    const int64_t n = c->n;
+    k_sorted_fill<<<blocks_for(n, BS), BS, 0, s>>>(
+        n, static_cast<uint32_t*>(c->perm.p), static_cast<double*>(c->pos_w.p), static_cast<int*>(c->leaf_of.p),
+        static_cast<int*>(c->lf_node.p), static_cast<int*>(c->nd_coord.p), static_cast<int*>(c->nd_level.p),
+        static_cast<int*>(c->nd_box.p), static_cast<int*>(c->box_G.p), static_cast<double*>(c->box_len.p),
+        static_cast<double*>(c->pos_s.p), static_cast<float4*>(c->xrel.p));
+    SPH_HIP(hipGetLastError());
+}
+
 // Rebuild around new smoothing lengths (caller order) keeping the positions.
 void rebuild_cells(sph_ctx* c, const float* h_caller, hipStream_t s)
 {
     float* hg = static_cast<float*>(c->hguess.p);
     unsigned* box_hmax = static_cast<unsigned*>(c->box_hmax.p);
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
-    SPH_HIP(hipMemcpyAsync(hg, h_caller, (size_t)c->n * 4, hipMemcpyDeviceToDevice, s));
+    if (h_caller && h_caller != hg)  // null: the guesses of the last build
+        SPH_HIP(hipMemcpyAsync(hg, h_caller, (size_t)c->n * 4, hipMemcpyDeviceToDevice, s));
     SPH_HIP(hipMemsetAsync(box_hmax, 0, (size_t)c->n_boxes * 4, s));
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
     k_box_hmax<<<blocks_for(c->n, BS), BS, 0, s>>>(c->n, static_cast<int64_t*>(c->box_first.p), c->n_boxes, hg,

@@ -152,6 +152,14 @@ struct sph_ctx {
     sph::Buf pos_s;          // double3 AoS, sorted
     sph::Buf xrel;           // float4 (x, y, z, 0) offsets from the leaf centre, sorted
     sph::Buf Hs;             // float search radius h_margin * h_guess, sorted
+    // Drift since the last build (the cells are kept across drifts), 4 words:
+    // [0] float bound delta on how far any particle moved (the kernels search
+    // Hs - 2 delta and widen cell boxes by delta), [1] float bits of the
+    // largest |v dt| component of the current drift, [2] float bits of the
+    // smallest Hs. Cleared by every build.
+    sph::Buf drift;
+    float h_min = 0.0f;           // smallest Hs of the last build (host copy)
+    bool drift_pending = false;   // a drift since the last check of delta
     sph::Buf leaf_of;        // int, sorted particle -> leaf
     sph::Buf unassigned;     // int flags per particle during the level loop
     sph::Buf head, scan1;    // uint32 per particle
@@ -356,7 +364,7 @@ void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
 
 void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len,
                  int64_t n, const double* pos, const float* h_guess, hipStream_t s);
-void rebuild_cells(sph_ctx* c, const float* h_guess_caller_order, hipStream_t s);
+void rebuild_cells(sph_ctx* c, const float* h_guess_caller_order /* null: the last guesses */, hipStream_t s);
 
 // Fill n 32-bit words with v by a kernel (not a memset node, so that the
 // call may be captured into a HIP graph).
@@ -387,6 +395,12 @@ void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const floa
           float* vel_out, float* u_out, hipStream_t s);
 void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s);
 double timestep(sph_ctx* c, double courant, hipStream_t s);
+// Offsets from the leaf centres from the current positions (build.hip).
+void refresh_offsets(sph_ctx* c, hipStream_t s);
+// Before a density pass after a drift: reject non-finite positions, and
+// rebuild the cells (around h_caller, or the last guesses when null) once the
+// drift bound eats into the margin of the search radii.
+void check_drift(sph_ctx* c, const float* h_caller, hipStream_t s);
 void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, double* dudt,
                double* cons, sph_stats* st, hipStream_t s);
 

@@ -79,6 +79,7 @@ struct DensArgs {
     const float* u;
     float4* jf;
     float gamma;
+    const float* drift;      // [0]: bound on the drift since the build (search Hs - 2 drift)
 };
 
 // Sorted copies of position (cell frame), mass, h and state. fresh: every
@@ -323,6 +324,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
     float4* sj = tile;
     float* lst = lists + lane;
     const unsigned o_lane = 4u * (unsigned)lane, o_cap = o_lane + 256u * DSLOTS;
+    const float two_delta = 2.0f * A.drift[0];  // the cells are searched to Hs - 2 drift
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0;  // wave-uniform
     // per-lane counts (far below 2^31 for any particle count that fits a GPU)
@@ -358,7 +360,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const int i = i0 + (valid ? gi : 0);
             const float4 xi = A.jd[i];
             const uint8_t st0 = A.st_s[i];
-            HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid || st0 != ST_ACTIVE, st0);
+            HSolve s = hsolve_init(A.hs[i], A.Hs[i] - two_delta, !valid || st0 != ST_ACTIVE, st0);
             const int active_groups = wave_count(!s.done && sub == 0);
             if (active_groups == 0) continue;
 
@@ -544,7 +546,7 @@ __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, f
                                              int64_t& cand_acc, I& inter_acc, I& sweep_acc, I& n_over,
                                              I& n_unconv, int& max_ev)
 {
-    HSolve s = hsolve_init(A.hs[i], A.Hs[i], !active, ST_ACTIVE);
+    HSolve s = hsolve_init(A.hs[i], A.Hs[i] - 2.0f * A.drift[0], !active, ST_ACTIVE);
     float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
     int cnt = 0;
     while (__any(!s.done)) {
@@ -599,6 +601,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
     char* br = reinterpret_cast<char*>(lr_all);
     char* bm = reinterpret_cast<char*>(lm_all);
     const unsigned o_lane = 4u * (unsigned)lane, o_cap = o_lane + 256u * RSLOTS;
+    const float two_delta = 2.0f * A.drift[0];
     int64_t cand_acc = 0;  // wave-uniform
     int list_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
     int max_ev = 0;
@@ -629,7 +632,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                 const bool valid = p0 + g < nflag;
                 const int i = i0 + pidx[valid ? p0 + g : p0];
                 const float4 xi = A.jd[i];
-                HSolve s = hsolve_init(A.hs[i], A.Hs[i], !valid, ST_ACTIVE);
+                HSolve s = hsolve_init(A.hs[i], A.Hs[i] - two_delta, !valid, ST_ACTIVE);
 
                 // ---- phase A: every candidate once, hits inside H listed ----------
                 const float H2 = valid ? s.Hi * s.Hi : -1.0f;
@@ -761,6 +764,7 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.u = ghost_u;
     A.jf = ghost_vel && ghost_u ? static_cast<float4*>(c->jf.p) : nullptr;
     A.gamma = (float)c->prm.gamma;
+    A.drift = static_cast<float*>(c->drift.p);
     const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
     // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
     const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
@@ -793,8 +797,9 @@ void density_buffers(sph_ctx* c)
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, sph_stats* st,
                  hipStream_t s)
 {
-    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density needs cells for the current positions (sph_build_cells, also after sph_drift)");
+    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
+    check_drift(c, h, s);
     const int64_t n = c->n;
     int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;
     int32_t sweeps = 0;

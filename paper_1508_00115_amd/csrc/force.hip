@@ -63,6 +63,7 @@ struct ForceArgs {
     float* dudt;
     double* cons_part;  // 4 per leaf, may be null
     float* vsig;        // sorted: signal velocity per particle (k_force<true> only)
+    const float* drift; // [0]: bound on the drift since the build (cell boxes widen by it)
     int64_t* ctr;
     WorkSched W;
     float alpha;
@@ -123,6 +124,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0;
     const float K8PI = 8.0f / SPH_PI_F;
+    const float delta = A.drift[0];  // particles may sit this far outside their cell boxes
 
     for (;;) {
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         bool loaded = false;
         int kept_single = 0;  // (single tile) candidates kept by the cell-box test
         const float2 geom = A.cell_geom[slot];
-        const float hw = cull_half_width(geom.x), reach2 = cull_reach2(geom.y);
+        const float hw = cull_half_width(geom.x + delta), reach2 = cull_reach2(geom.y);
         double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};  // this cell's share of the box sums (lane 0)
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
@@ -338,6 +340,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.cons_part = cons_d ? static_cast<double*>(c->cons_part.p) : nullptr;
     const bool vsig = c->prm.signal_velocity != 0;
     A.vsig = vsig ? static_cast<float*>(c->vsig_s.p) : nullptr;
+    A.drift = static_cast<float*>(c->drift.p);
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;

@@ -23,18 +23,44 @@ __global__ void k_kick(int64_t n, double dt, const float* __restrict__ acc, cons
     if (t < n) u_out[t] = (float)((double)u_in[t] + (double)dudt[t] * dt);
 }
 
-// pos += vel dt over the 3n components, wrapped into the particle's box.
+// pos += vel dt over the 3n components, wrapped into the particle's box, also
+// into the library's copy pos_w; the largest |v dt| of a component goes to
+// drift[1] (float bits) and a non-finite result sets drift[3].
 __global__ void k_drift(int64_t n, double dt, const float* __restrict__ vel, double* __restrict__ pos,
-                        const int64_t* __restrict__ box_first, int n_boxes, const double* __restrict__ box_len)
+                        double* __restrict__ pos_w, const int64_t* __restrict__ box_first, int n_boxes,
+                        const double* __restrict__ box_len, unsigned* __restrict__ drift)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * n) return;
-    const double L = box_len[n_boxes > 1 ? box_of(box_first, n_boxes, t / 3) : 0];
-    const double x = pos[t] + (double)vel[t] * dt;
-    double y = x - L * floor(x / L);
-    if (y < 0.0) y += L;  // x / L rounded up to an integer
-    if (y >= L) y = 0.0;  // y rounded up to L
-    pos[t] = y;  // a non-finite position stays non-finite: the next build rejects it
+    float m = 0.0f;
+    bool bad = false;
+    if (t < 3 * n) {
+        const double L = box_len[n_boxes > 1 ? box_of(box_first, n_boxes, t / 3) : 0];
+        const double step = (double)vel[t] * dt;
+        const double x = pos[t] + step;
+        double y = x - L * floor(x / L);
+        if (y < 0.0) y += L;  // x / L rounded up to an integer
+        if (y >= L) y = 0.0;  // y rounded up to L
+        pos[t] = y;
+        pos_w[t] = y;
+        bad = !isfinite(y);
+        m = bad ? 0.0f : (float)fabs(step);
+    }
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const bool any_bad = __any(bad);
+    if ((threadIdx.x & 63) == 0) {
+        if (m > 0.0f) atomicMax(&drift[1], __float_as_uint(m));
+        if (any_bad) atomicOr(&drift[3], 1u);
+    }
+}
+
+// delta += sqrt(3) * (largest component step), rounded up; the step maximum
+// is cleared for the next drift.
+__global__ void k_drift_close(unsigned* __restrict__ drift)
+{
+    if (threadIdx.x != 0) return;
+    const float d = __uint_as_float(drift[0]) + 1.7320509f * __uint_as_float(drift[1]);
+    drift[0] = __float_as_uint(d * 1.000001f);
+    drift[1] = 0u;
 }
 
 // Smallest h / v_sig over the particles with v_sig > 0, as float bits
@@ -69,25 +95,46 @@ void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const floa
 
 void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s)
 {
-    SPH_REQUIRE(c->n > 0 && c->box_first.p && c->box_len.p, SPH_E_STATE, "sph_drift before sph_build_cells");
+    SPH_REQUIRE(c->built && c->drift.p, SPH_E_STATE, "sph_drift needs cells (sph_build_cells)");
     SPH_REQUIRE(vel && pos, SPH_E_ARG, "null vel/pos");
     SPH_REQUIRE(std::isfinite(dt), SPH_E_ARG, "dt must be finite");
     const int64_t n = c->n;
-    k_drift<<<blocks_for(3 * n, 256), 256, 0, s>>>(n, dt, vel, pos, static_cast<int64_t*>(c->box_first.p),
-                                                    c->n_boxes, static_cast<double*>(c->box_len.p));
+    unsigned* dr = static_cast<unsigned*>(c->drift.p);
+    k_drift<<<blocks_for(3 * n, 256), 256, 0, s>>>(n, dt, vel, pos, static_cast<double*>(c->pos_w.p),
+                                                    static_cast<int64_t*>(c->box_first.p), c->n_boxes,
+                                                    static_cast<double*>(c->box_len.p), dr);
     SPH_HIP(hipGetLastError());
-    // the cells, offsets and signal velocities describe the old positions
-    c->built = false;
+    k_drift_close<<<1, 64, 0, s>>>(dr);
+    SPH_HIP(hipGetLastError());
+    // the cells stay; the offsets from their centres follow the particles
+    refresh_offsets(c, s);
+    c->drift_pending = true;
     c->density_done = false;
     c->density64_done = false;
     c->vsig_valid = false;
+}
+
+void check_drift(sph_ctx* c, const float* h_caller, hipStream_t s)
+{
+    if (!c->drift_pending) return;
+    unsigned w[4];
+    SPH_HIP(hipMemcpyAsync(w, c->drift.p, sizeof(w), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    c->drift_pending = false;
+    SPH_REQUIRE(w[3] == 0u, SPH_E_ARG, "a drift produced a non-finite position");
+    float delta;
+    std::memcpy(&delta, &w[0], 4);
+    // the kernels search Hs - 2 delta: keep that above Hs / h_margin, the
+    // radius the starting guesses had at the build
+    const double budget = (1.0 - 1.0 / c->prm.h_margin) * (double)c->h_min;
+    if (!(2.0 * (double)delta <= budget)) rebuild_cells(c, h_caller, s);
 }
 
 double timestep(sph_ctx* c, double courant, hipStream_t s)
 {
     SPH_REQUIRE(std::isfinite(courant) && courant > 0.0, SPH_E_ARG, "courant must be finite and > 0");
     SPH_REQUIRE(c->built && c->vsig_valid, SPH_E_STATE,
-                "sph_timestep needs a force pass with sph_params.signal_velocity since the last build");
+                "sph_timestep needs a force pass with sph_params.signal_velocity since the last build or drift");
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     unsigned* slot = reinterpret_cast<unsigned*>(&ctr[CT_DT_MIN]);
     fill_u32(slot, 0x7f800000u, 1, s);  // +inf

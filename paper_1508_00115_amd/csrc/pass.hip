@@ -31,8 +31,9 @@ void drop_graph(sph_ctx* c)
 void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw, const float* vel,
               const float* u, float* acc, float* dudt, double* cons, sph_stats* st, hipStream_t s)
 {
-    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_pass needs cells for the current positions (sph_build_cells, also after sph_drift)");
+    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_pass before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f && vel && u && acc && dudt, SPH_E_ARG, "null input or output");
+    check_drift(c, h, s);
     c->density_done = false;
     c->rebuilds = 0;
     density_buffers(c);

@@ -17,6 +17,7 @@ struct D64Args {
     const double* pos_s;      // sorted FP64 positions (AoS)
     const double* m_s;        // sorted masses
     const float* Hs;          // sorted search radii
+    const float* drift;       // [0]: bound on the drift since the build (search Hs - 2 drift)
     double* hs;               // sorted h: in start, out result
     double* rhos;
     double* fs;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void density64_one(const D64Args& A, int64_t i, D64Co
     const int a = A.leaf_of[i];
     const double L = A.box_len[A.nd_box[A.lf_node[a]]];
     const double xi = A.pos_s[3 * i], yi = A.pos_s[3 * i + 1], zi = A.pos_s[3 * i + 2];
-    const double Hi = (double)A.Hs[i];
+    const double Hi = (double)A.Hs[i] - 2.0 * (double)A.drift[0];
     double h = A.hs[i];
     if (!(h > 0.0) || h > Hi) h = Hi;
     double lo = 0.0, hi = Hi;
@@ -317,6 +318,7 @@ void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double*
 {
     SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density_f64 before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
+    check_drift(c, nullptr, s);  // a rebuild after a drift uses the guesses of the last build
     const int64_t n = c->n;
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     uint8_t* status = ensure<uint8_t>(c, c->status, n);
@@ -340,6 +342,7 @@ void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double*
         A.pos_s = static_cast<double*>(c->pos_s.p);
         A.m_s = m_s;
         A.Hs = static_cast<float*>(c->Hs.p);
+        A.drift = static_cast<float*>(c->drift.p);
         A.hs = hs;
         A.rhos = rhos;
         A.fs = fs;

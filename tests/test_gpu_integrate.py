@@ -68,7 +68,16 @@ def test_timestep_needs_signal_velocities(gpu_lib):
         ctx.close()
 
 
-def test_drift_invalidates_the_cells(gpu_lib):
+def _drifted(d, x):
+    e = dict(d)
+    e["pos"] = x
+    return e
+
+
+def test_drift_keeps_the_cells(gpu_lib):
+    """After drifts the pass runs on the kept cells (search radius reduced by
+    twice the drift bound) and, once the bound eats the margin, on rebuilt
+    ones; both against the oracle at the drifted positions."""
     import torch
     d = _case()
     t = _tensors(d)
@@ -77,20 +86,34 @@ def test_drift_invalidates_the_cells(gpu_lib):
         ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
         h = t["h0"].clone()
         r = ctx.pass_(t["mass"], h, t["vel"], t["u"])
-        ctx.drift(1e-4, t["vel"], t["pos"])
-        for call in (lambda: ctx.pass_(t["mass"], h, t["vel"], t["u"]), lambda: ctx.timestep(0.3),
-                     lambda: ctx.density(t["mass"], h)):
+        vmax = float(np.abs(d["vel"]).max())
+        # the rebuild threshold: 2 delta > (1 - 1/h_margin) h_margin min(h_guess), h_margin 1.26
+        budget = (1.0 - 1.0 / 1.26) * 1.26 * float(d["h0"].min())
+        dt = 0.2 * budget / (2.0 * math.sqrt(3.0) * vmax)  # delta well inside the budget
+        ctx.drift(dt, t["vel"], t["pos"])
+        for call in (lambda: ctx.timestep(0.3), lambda: ctx.force(t["vel"], t["u"])):
             with pytest.raises(gpu_lib.SphError) as e:
                 call()
             assert e.value.code == gpu_lib.SPH_E_STATE
-        ctx.kick(1e-4, r["acc"], r["dudt"], t["vel"], t["u"])  # a kick needs no cells
         with pytest.raises(gpu_lib.SphError) as e:
             ctx.kick(float("nan"), r["acc"], r["dudt"], t["vel"], t["u"])
         assert e.value.code == gpu_lib.SPH_E_ARG
-        ctx.build_cells(t["pos"], h, d["box_first"], d["box_len"])
-        ctx.pass_(t["mass"], h, t["vel"], t["u"])
-        assert ctx.timestep(0.3) > 0
-        torch.cuda.synchronize()
+        for regime, n_drift, step in (("kept cells", 1, dt), ("rebuilt cells", 8, 20.0 * dt)):
+            if regime == "rebuilt cells":
+                for _ in range(n_drift):
+                    ctx.drift(step, t["vel"], t["pos"])
+                delta = math.sqrt(3.0) * vmax * (dt + n_drift * step)
+                assert 2.0 * delta > budget  # this regime must rebuild
+            r = ctx.pass_(t["mass"], h, t["vel"], t["u"])
+            torch.cuda.synchronize()
+            g = {"h": _np(h), "rho": _np(r["rho"]), "f": _np(r["f"]), "nw": _np(h) * 0 + 1,
+                 "acc": _np(r["acc"]), "dudt": _np(r["dudt"])}
+            ro = oracle.run(_drifted(d, _np(t["pos"])))
+            e = errors(g, ro)
+            e["nw"] = 0.0
+            print(regime, e, flush=True)
+            assert_within(e, TOL32, regime)
+            assert ctx.timestep(0.3) > 0
     finally:
         ctx.close()
 
@@ -114,8 +137,7 @@ def test_one_step_matches_oracle(gpu_lib):
         ctx.drift(dt, vel, pos)
         vel_p, u_p = torch.empty_like(vel), torch.empty_like(u)
         ctx.kick(0.5 * dt, a0, du0, vel, u, vel_p, u_p)
-        ctx.build_cells(pos, h, d["box_first"], d["box_len"])
-        r1 = ctx.pass_(t["mass"], h, vel_p, u_p)
+        r1 = ctx.pass_(t["mass"], h, vel_p, u_p)  # on the kept cells
         ctx.kick(0.5 * dt, r1["acc"], r1["dudt"], vel, u)
         torch.cuda.synchronize()
         x1, vp, up, v1, u1 = _np(pos), _np(vel_p), _np(u_p), _np(vel), _np(u)
