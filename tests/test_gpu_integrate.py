@@ -74,12 +74,27 @@ def _drifted(d, x):
     return e
 
 
-def test_drift_keeps_the_cells(gpu_lib):
+def _boxes8():
+    # eight boxes of different particle counts, scaled to sides 0.8 .. 1.5
+    d = workloads.batched(n_boxes=8, n_min=1000, n_max=8000, side_min=10, side_max=20)
+    pos, h0 = d["pos"].copy(), d["h0"].astype(np.float64)
+    L = 0.8 + 0.1 * np.arange(8)
+    for b in range(8):
+        s, e = int(d["box_first"][b]), int(d["box_first"][b + 1])
+        pos[s:e] *= L[b]
+        h0[s:e] *= L[b]
+    d["pos"], d["h0"], d["box_len"] = pos, h0.astype(np.float32), L
+    return d
+
+
+@pytest.mark.parametrize("case", ["lattice", "batched8"])
+def test_drift_keeps_the_cells(gpu_lib, case):
     """After drifts the pass runs on the kept cells (search radius reduced by
     twice the drift bound) and, once the bound eats the margin, on rebuilt
-    ones; both against the oracle at the drifted positions."""
+    ones; both against the oracle at the drifted positions (one box, and
+    eight boxes of different sides and counts, each wrapped on its own)."""
     import torch
-    d = _case()
+    d = _case() if case == "lattice" else _boxes8()
     t = _tensors(d)
     ctx = gpu_lib.Context(0, signal_velocity=1)
     try:
