@@ -53,6 +53,48 @@ struct KeyLayout {
     int levels;    // octree levels below the top grid (3 key bits each)
 };
 
+// Raise base[key] to v over a workgroup of WBS threads (valid lanes only).
+// Each wavefront reduces first; when every wavefront of the group holds one
+// key (a single box, or the inside of a box) a single atomic per group
+// remains, otherwise each wavefront adds its own. Same-address atomics
+// serialise at the L2, so one per 64 lanes still cost tens of microseconds
+// for a million particles. Every thread of the group must call it.
+constexpr int WBS = 1024;
+__device__ __forceinline__ void block_atomic_max_u32(unsigned* base, int key, unsigned v, bool valid)
+{
+    __shared__ int wkey[WBS / 64];
+    __shared__ unsigned wmax[WBS / 64];
+    __shared__ int wstate[WBS / 64];  // 0: no valid lane, 1: one key, 2: several keys
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    const bool any = __any(valid);
+    const int kref = __shfl(valid ? key : 0x7fffffff, __ffsll((unsigned long long)__ballot(valid)) - 1, 64);
+    const bool uni = __all(!valid || key == kref);
+    unsigned m = valid ? v : 0u;
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    if (lane == 0) {
+        wkey[w] = kref;
+        wmax[w] = m;
+        wstate[w] = !any ? 0 : (uni ? 1 : 2);
+    }
+    __syncthreads();
+    bool one = true;  // every wavefront with a valid lane holds one and the same key
+    int k0 = -1;
+    unsigned mm = 0u;
+    for (int q = 0; q < nw; ++q) {
+        if (wstate[q] == 0) continue;
+        if (wstate[q] == 2 || (k0 >= 0 && wkey[q] != k0)) one = false;
+        k0 = k0 < 0 ? wkey[q] : k0;
+        mm = max(mm, wmax[q]);
+    }
+    if (one) {
+        if (threadIdx.x == 0 && k0 >= 0) atomicMax(&base[k0], mm);
+    } else if (uni) {
+        if (lane == 0 && any) atomicMax(&base[kref], m);
+    } else if (valid) {
+        atomicMax(&base[key], v);
+    }
+}
+
 __global__ void k_wrap(int64_t n, const double* __restrict__ pos, const int64_t* __restrict__ box_first,
                        int n_boxes, const double* __restrict__ box_len, const float* __restrict__ hg,
                        double* __restrict__ pos_w, float* __restrict__ hg_copy,
@@ -79,7 +121,7 @@ __global__ void k_wrap(int64_t n, const double* __restrict__ pos, const int64_t*
         hg_copy[p] = h;
         if (bad) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
     }
-    wave_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), in_range && !bad);
+    block_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), in_range && !bad);
 }
 
 // Largest search radius per box from the stored (caller-order) h guesses.
@@ -98,7 +140,7 @@ __global__ void k_box_hmax(int64_t n, const int64_t* __restrict__ box_first, int
         ok = (h > 0.0f) && isfinite(h);
         if (!ok) atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
     }
-    wave_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), ok);
+    block_atomic_max_u32(box_hmax, b, __float_as_uint(margin * h), ok);
 }
 
 __global__ void k_keys(int64_t n, const double* __restrict__ pos_w, const int64_t* __restrict__ box_first,
@@ -159,8 +201,7 @@ __global__ void k_lvl_head(int64_t n, const uint64_t* __restrict__ keys, const i
 
 // Node of every unassigned particle at level l; node start, count, largest
 // search radius, and the number of particles whose search radius is too wide
-// for half the node (cell_ratio * H > w / 2). Particles are sorted, so a
-// wavefront's particles usually share one node: it then adds once.
+// for half the node (cell_ratio * H > w / 2).
 __global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const int* __restrict__ leaf_tmp,
                             const uint32_t* __restrict__ head, const uint32_t* __restrict__ excl,
                             const float* __restrict__ Hs, int level, KeyLayout kl, int64_t node_base,
@@ -184,28 +225,29 @@ __global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const 
         hb = __float_as_uint(H);
         wide = (double)(cell_ratio * H) > 0.5 * w ? 1 : 0;
     }
-    int id_lo = valid ? id : 0x7fffffff, id_hi = id;
-    for (int o = 32; o >= 1; o >>= 1) {
-        id_lo = min(id_lo, __shfl_xor(id_lo, o, 64));
-        id_hi = max(id_hi, __shfl_xor(id_hi, o, 64));
+    // The particles of a node are consecutive among the valid lanes (sorted
+    // order; lanes of assigned particles only sit between nodes), so a scan
+    // that combines equal ids gives each run's totals in its last lane, and
+    // one atomic per run and array remains instead of one per particle.
+    const int lane = threadIdx.x & 63;
+    int cnt = valid ? 1 : 0, wsum = wide;
+    unsigned hmx = hb;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int id_o = __shfl_up(id, o, 64);
+        const int c_o = __shfl_up(cnt, o, 64);
+        const int w_o = __shfl_up(wsum, o, 64);
+        const unsigned h_o = (unsigned)__shfl_up((int)hmx, o, 64);
+        if (valid && lane >= o && id_o == id) {
+            cnt += c_o;
+            wsum += w_o;
+            hmx = max(hmx, h_o);
+        }
     }
-    if (id_hi >= 0 && id_lo == id_hi) {
-        int cnt = valid ? 1 : 0, wsum = wide;
-        unsigned hmx = hb;
-        for (int o = 32; o >= 1; o >>= 1) {
-            cnt += __shfl_xor(cnt, o, 64);
-            wsum += __shfl_xor(wsum, o, 64);
-            hmx = max(hmx, (unsigned)__shfl_xor((int)hmx, o, 64));
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&nd_count[id_hi], cnt);
-            atomicMax(&nd_hmax[id_hi], hmx);
-            if (wsum) atomicAdd(&nd_wide[id_hi], wsum);
-        }
-    } else if (valid) {
-        atomicAdd(&nd_count[id], 1);
-        atomicMax(&nd_hmax[id], hb);
-        if (wide) atomicAdd(&nd_wide[id], 1);
+    const int id_next = __shfl_down(id, 1, 64);
+    if (valid && (lane == 63 || id_next != id)) {
+        atomicAdd(&nd_count[id], cnt);
+        atomicMax(&nd_hmax[id], hmx);
+        if (wsum) atomicAdd(&nd_wide[id], wsum);
     }
     if (valid && head[p]) {
         const uint64_t k = keys[p];
@@ -545,13 +587,19 @@ __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, cons
 }
 
 // Smallest search radius (float bits; non-negative floats order like their bits).
-__global__ void k_min_H(int64_t n, const float* __restrict__ Hs, unsigned* __restrict__ out)
+__global__ void __launch_bounds__(BS) k_min_H(int64_t n, const float* __restrict__ Hs, unsigned* __restrict__ out)
 {
+    __shared__ float wm[BS / 64];
     float m = INFINITY;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
         m = fminf(m, Hs[p]);
     for (int o = 32; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // one atomic per workgroup
+        for (int q = 1; q < BS / 64; ++q) m = fminf(m, wm[q]);
+        atomicMin(out, __float_as_uint(m));
+    }
 }
 
 int ceil_log2(uint64_t v)
@@ -823,8 +871,8 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     unsigned* drift = ensure<unsigned>(c, c->drift, 4);
     fill_u32(drift, 0u, 2, s);
     fill_u32(drift + 2, 0x7f800000u, 1, s);
-    k_min_H<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, BS), 1024)), BS, 0, s>>>(n, Hs,
-                                                                                                  drift + 2);
+    k_min_H<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, BS), 256)), BS, 0, s>>>(n, Hs,
+                                                                                                 drift + 2);
     SPH_HIP(hipGetLastError());
     unsigned hmin_bits = 0;
     SPH_HIP(hipMemcpyAsync(&hmin_bits, drift + 2, 4, hipMemcpyDeviceToHost, s));
@@ -867,7 +915,7 @@ void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const do
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     SPH_HIP(hipMemsetAsync(box_hmax, 0, (size_t)n_boxes * 4, s));
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
-    k_wrap<<<blocks_for(n, BS), BS, 0, s>>>(n, pos, bf, n_boxes, bl, h_guess, pw, hg, box_hmax,
+    k_wrap<<<blocks_for(n, WBS), WBS, 0, s>>>(n, pos, bf, n_boxes, bl, h_guess, pw, hg, box_hmax,
                                             (float)c->prm.h_margin, ctr);
     SPH_HIP(hipGetLastError());
     c->rebuilds = 0;
@@ -897,7 +945,7 @@ void rebuild_cells(sph_ctx* c, const float* h_caller, hipStream_t s)
         SPH_HIP(hipMemcpyAsync(hg, h_caller, (size_t)c->n * 4, hipMemcpyDeviceToDevice, s));
     SPH_HIP(hipMemsetAsync(box_hmax, 0, (size_t)c->n_boxes * 4, s));
     SPH_HIP(hipMemsetAsync(ctr, 0, CT_COUNT * 8, s));
-    k_box_hmax<<<blocks_for(c->n, BS), BS, 0, s>>>(c->n, static_cast<int64_t*>(c->box_first.p), c->n_boxes, hg,
+    k_box_hmax<<<blocks_for(c->n, WBS), WBS, 0, s>>>(c->n, static_cast<int64_t*>(c->box_first.p), c->n_boxes, hg,
                                                    box_hmax, (float)c->prm.h_margin, ctr);
     SPH_HIP(hipGetLastError());
     build_from_wrapped(c, s);

@@ -66,16 +66,22 @@ __global__ void k_drift_close(unsigned* __restrict__ drift)
 // Smallest h / v_sig over the particles with v_sig > 0, as float bits
 // (non-negative floats order like their bit patterns) into *out, which holds
 // +inf beforehand.
-__global__ void k_dt_min(int64_t n, const float* __restrict__ hs, const float* __restrict__ vsig,
-                         unsigned* __restrict__ out)
+__global__ void __launch_bounds__(256) k_dt_min(int64_t n, const float* __restrict__ hs,
+                                                const float* __restrict__ vsig, unsigned* __restrict__ out)
 {
+    __shared__ float wm[4];
     float m = INFINITY;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const float v = vsig[p];
         if (v > 0.0f) m = fminf(m, hs[p] / v);
     }
     for (int o = 32; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // one atomic per workgroup: same-address atomics serialise at the L2
+        for (int q = 1; q < 4; ++q) m = fminf(m, wm[q]);
+        atomicMin(out, __float_as_uint(m));
+    }
 }
 
 }  // namespace
@@ -139,7 +145,7 @@ double timestep(sph_ctx* c, double courant, hipStream_t s)
     unsigned* slot = reinterpret_cast<unsigned*>(&ctr[CT_DT_MIN]);
     fill_u32(slot, 0x7f800000u, 1, s);  // +inf
     const int64_t n = c->n;
-    const int grid = (int)std::min<int64_t>(blocks_for(n, 256), (int64_t)c->n_cu * 4);
+    const int grid = (int)std::min<int64_t>(blocks_for(n, 256), (int64_t)c->n_cu);
     k_dt_min<<<std::max(grid, 1), 256, 0, s>>>(n, static_cast<float*>(c->hs.p), static_cast<float*>(c->vsig_s.p),
                                                slot);
     SPH_HIP(hipGetLastError());
