@@ -15,7 +15,10 @@
  *   - after the density (the dependency of section 3.1), the symmetric
  *     pressure-gradient loop in the grad-h form of Gadget-2 that the paper
  *     says Swift implements (section 2, after Eq. 2), with a signal-velocity
- *     artificial viscosity, giving accelerations and du/dt.
+ *     artificial viscosity, giving accelerations and du/dt;
+ *   - marching the particles forward in time (section 2): kick-drift-kick
+ *     leapfrog steps with a Courant time step, the cells kept across steps
+ *     while the particles stay within their margin.
  *
  * Kernel: cubic spline with compact support h, W(r, h) = 8 / (pi h^3) w(r/h),
  *   w(q) = 1 - 6 q^2 + 6 q^3 (q <= 1/2), 2 (1 - q)^3 (1/2 < q <= 1), 0 beyond.
