@@ -407,7 +407,8 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                            const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
                            const double* __restrict__ box_len, const uint32_t* __restrict__ p_start,
                            int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
-                           int64_t* __restrict__ ctr)
+                           int2* __restrict__ p_rec, const int* __restrict__ lf_start,
+                           const int* __restrict__ lf_count, int64_t* __restrict__ ctr)
 {
     const int A = lf_node[a];
     const int b = nd_box[A];
@@ -459,6 +460,7 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                         if (fill) {
                             const uint32_t o = base + cnt;
                             p_leaf[o] = lf;
+                            p_rec[o] = make_int2(lf_start[lf], lf_count[lf]);
                             p_shift[o] = make_float4((float)(cX[0] + S[0] - cA[0]), (float)(cX[1] + S[1] - cA[1]),
                                                      (float)(cX[2] + S[2] - cA[2]), 0.0f);
                             p_code[o] = image_code(s[0], s[1], s[2]);
@@ -486,14 +488,16 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
                            const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
                            const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
                            const uint32_t* __restrict__ p_start, int* __restrict__ p_leaf,
-                           float4* __restrict__ p_shift, int* __restrict__ p_code,
+                           float4* __restrict__ p_shift, int* __restrict__ p_code, int2* __restrict__ p_rec,
+                           const int* __restrict__ lf_start, const int* __restrict__ lf_count,
                            int64_t* __restrict__ ctr)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t cnt = 0;
     if (a < n_leaves)
         cnt = partners_of(a, fill, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf, nd_child0, nd_child1,
-                          top, box_top_base, box_G, box_len, p_start, p_leaf, p_shift, p_code, ctr);
+                          top, box_top_base, box_G, box_len, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
+                          lf_count, ctr);
     if (!fill) {
         if (a < n_leaves) p_cnt[a] = cnt;
         // the records of all leaves in 64 bits: the list offsets are a 32-bit scan
@@ -814,7 +818,8 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     const int* nd_child1 = static_cast<int*>(c->nd_child1.p);
     k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 0, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
                                                  nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, nullptr, nullptr, nullptr, nullptr, ctr);
+                                                 p_cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                 nullptr, ctr);
     SPH_HIP(hipGetLastError());
     scan_exclusive(c, p_cnt, p_start, nl, p_start + nl, s);
     uint32_t np = 0;
@@ -831,9 +836,11 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     int* p_leaf = ensure<int>(c, c->p_leaf, np);
     float4* p_shift = ensure<float4>(c, c->p_shift, np);
     int* p_code = ensure<int>(c, c->p_code, np);
+    int2* p_rec = ensure<int2>(c, c->p_rec, np);
     k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 1, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
                                                  nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, p_start, p_leaf, p_shift, p_code, ctr);
+                                                 p_cnt, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
+                                                 lf_count, ctr);
     SPH_HIP(hipGetLastError());
 
     // ---- work schedule: leaves by decreasing cost dealt out to the XCDs, Morton ranges, or Morton

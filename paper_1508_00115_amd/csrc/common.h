@@ -176,6 +176,7 @@ struct sph_ctx {
     sph::Buf p_start;        // uint32 n_leaves + 1
     sph::Buf p_cnt;          // uint32 n_leaves
     sph::Buf p_leaf;         // int
+    sph::Buf p_rec;          // int2 per record: first particle and count of the neighbour leaf
     sph::Buf p_shift;        // float4 (dx, dy, dz, 0): leaf-centre frame offset
     sph::Buf p_code;         // int: periodic image code (3 x 2 bits)
     // work schedule of the hot kernels (one slot per leaf, see xcd_start)

@@ -54,9 +54,7 @@ struct DensArgs {
     float* fs;
     uint8_t* st_s;           // sorted state
     const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, entries
-    const int* lf_start;
-    const int* lf_count;
-    const int* p_leaf;
+    const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     const uint32_t* perm;
     float* h_out;
@@ -341,8 +339,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         const float m0 = ni > 0 ? A.jd[i0].w : 0.0f;
         int n_flag = 0;  // this lane's particles of the cell left to the re-scan
         NbrCursor cu;
-        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
-        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         // resident: one block of neighbour records and at most TCAP candidates,
         // staged once at fixed tile slots of DCH
         const bool resident = np_all <= 64 && nj <= TCAP;
@@ -371,7 +369,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 const bool stream = !(resident && loaded);
                 ChunkRegs<1, DCH> R;
                 if (stream) {
-                    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, 0);
+                    cursor_seek(cu, A.p_rec, A.p_shift, 0);
                     fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH), marks);
                 }
                 int len;
@@ -384,7 +382,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                         commit_chunk_padded(sj + (resident ? c0 : 0), R);
                         const int nx = c0 + len;
                         if (nx < nj) {
-                            cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, nx);
+                            cursor_seek(cu, A.p_rec, A.p_shift, nx);
                             fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH), marks);
                         }
                     }
@@ -531,7 +529,7 @@ __device__ __forceinline__ int rescan_stage(const DensArgs& A, NbrCursor& cu, fl
                                             bool single_tile, bool& loaded)
 {
     if (single_tile && loaded) return nj;
-    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
+    cursor_seek(cu, A.p_rec, A.p_shift, c0);
     const int len = cursor_chunk(cu, c0, SCAP);
     stage_fast<1, SCAP>(tile, A.jd, cu.nb, c0 - cu.off0, len);
     loaded = true;
@@ -616,8 +614,8 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         const int4 ci = A.cells[A.scan_cells[k]];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         NbrCursor cu;  // neighbour records 64 at a time
-        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
-        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= SCAP;
         bool loaded = false;
         for (int b0 = 0; b0 < ni; b0 += 64) {
@@ -737,9 +735,7 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.fs = fs;
     A.st_s = st_s;
     A.cells = static_cast<int4*>(c->cells.p);
-    A.lf_start = static_cast<int*>(c->lf_start.p);
-    A.lf_count = static_cast<int*>(c->lf_count.p);
-    A.p_leaf = static_cast<int*>(c->p_leaf.p);
+    A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.perm = static_cast<uint32_t*>(c->perm.p);
     A.h_out = h;

@@ -54,9 +54,7 @@ struct ForceArgs {
     const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* cell_aux;  // per schedule slot: leaf, box
     const float2* cell_geom;  // per schedule slot: half width of the leaf, largest search radius in it
-    const int* lf_start;
-    const int* lf_count;
-    const int* p_leaf;
+    const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     const uint32_t* perm;
     float* acc;
@@ -132,8 +130,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         const int4 ci = A.cells[slot];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         NbrCursor cu;  // neighbour records 64 at a time
-        cursor_init(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, pb0, np_all);
-        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_leaf, A.lf_count, pb0, np_all);
+        cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
+        const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= FCAP;
         const int lpi = choose_lpi(ni, nj, 4, A.list_work, single_tile, FCAP);
         const int lg = __builtin_ctz(lpi);
@@ -170,7 +168,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     // (loaded and stored here rather than one chunk ahead: the
                     // registers a fetch in flight would hold cost a wavefront
                     // per SIMD, and the other wavefronts cover the loads)
-                    cursor_seek(cu, A.p_leaf, A.p_shift, A.lf_start, A.lf_count, c0);
+                    cursor_seek(cu, A.p_rec, A.p_shift, c0);
                     fetch_chunk(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
                     len = R.len;
                     slen = commit_chunk_culled(sj, R, hw, reach2);
@@ -330,9 +328,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.cells = static_cast<int4*>(c->cells.p);
     A.cell_geom = static_cast<float2*>(c->cell_geom.p);
     A.cell_aux = static_cast<int2*>(c->cell_aux.p);
-    A.lf_start = static_cast<int*>(c->lf_start.p);
-    A.lf_count = static_cast<int*>(c->lf_count.p);
-    A.p_leaf = static_cast<int*>(c->p_leaf.p);
+    A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.perm = static_cast<uint32_t*>(c->perm.p);
     A.acc = acc;

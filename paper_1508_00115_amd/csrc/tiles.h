@@ -159,14 +159,13 @@ __device__ __forceinline__ int wave_count(bool c)
 }
 
 // Number of candidates of a cell: the particles of every cell in its list.
-__device__ __forceinline__ int count_candidates(const int* __restrict__ p_leaf, const int* __restrict__ lf_count,
-                                                int pb0, int np_all)
+__device__ __forceinline__ int count_candidates(const int2* __restrict__ p_rec, int pb0, int np_all)
 {
     const int lane = threadIdx.x & 63;
     int nj = 0;
     for (int b0 = 0; b0 < np_all; b0 += 64) {
         const int q = b0 + lane;
-        int cnt = q < np_all ? lf_count[p_leaf[pb0 + q]] : 0;
+        int cnt = q < np_all ? p_rec[pb0 + q].y : 0;
         for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
         nj += cnt;
     }
@@ -176,14 +175,15 @@ __device__ __forceinline__ int count_candidates(const int* __restrict__ p_leaf, 
 // Neighbour-cell records of a cell with at most 64 neighbour cells, one per
 // lane: first particle, count, exclusive prefix of the counts (the cell's
 // offset in the flattened candidate list) and the shift into the cell frame.
+// A record holds its cell's first particle and count itself (p_rec, written
+// by the build), so the staging is one load away from the cell's record list.
 struct NbrLanes {
     int bs, bc, off;
     float sx, sy, sz;
     int np, nj;
 };
 
-__device__ __forceinline__ NbrLanes load_nbr(const int* __restrict__ p_leaf, const float4* __restrict__ p_shift,
-                                             const int* __restrict__ lf_start, const int* __restrict__ lf_count,
+__device__ __forceinline__ NbrLanes load_nbr(const int2* __restrict__ p_rec, const float4* __restrict__ p_shift,
                                              int pb0, int np)
 {
     const int lane = threadIdx.x & 63;
@@ -192,10 +192,10 @@ __device__ __forceinline__ NbrLanes load_nbr(const int* __restrict__ p_leaf, con
     nb.bc = 0;
     nb.sx = nb.sy = nb.sz = 0.f;
     if (lane < np) {
-        const int bl = p_leaf[pb0 + lane];
+        const int2 rec = p_rec[pb0 + lane];
         const float4 sh = p_shift[pb0 + lane];
-        nb.bs = lf_start[bl];
-        nb.bc = lf_count[bl];
+        nb.bs = rec.x;
+        nb.bc = rec.y;
         nb.sx = sh.x;
         nb.sy = sh.y;
         nb.sz = sh.z;
@@ -223,28 +223,26 @@ struct NbrCursor {
     int pb0, np_all;
 };
 
-__device__ __forceinline__ void cursor_init(NbrCursor& cu, const int* __restrict__ p_leaf,
-                                            const float4* __restrict__ p_shift, const int* __restrict__ lf_start,
-                                            const int* __restrict__ lf_count, int pb0, int np_all)
+__device__ __forceinline__ void cursor_init(NbrCursor& cu, const int2* __restrict__ p_rec,
+                                            const float4* __restrict__ p_shift, int pb0, int np_all)
 {
     cu.pb0 = pb0;
     cu.np_all = np_all;
     cu.b0 = 0;
     cu.off0 = 0;
-    cu.nb = load_nbr(p_leaf, p_shift, lf_start, lf_count, pb0, min(np_all, 64));
+    cu.nb = load_nbr(p_rec, p_shift, pb0, min(np_all, 64));
 }
 
 // Move the cursor to the block holding candidate c (c at or after the
 // current block's start; back to the first block when c is before it).
-__device__ __forceinline__ void cursor_seek(NbrCursor& cu, const int* __restrict__ p_leaf,
-                                            const float4* __restrict__ p_shift, const int* __restrict__ lf_start,
-                                            const int* __restrict__ lf_count, int c)
+__device__ __forceinline__ void cursor_seek(NbrCursor& cu, const int2* __restrict__ p_rec,
+                                            const float4* __restrict__ p_shift, int c)
 {
-    if (c < cu.off0) cursor_init(cu, p_leaf, p_shift, lf_start, lf_count, cu.pb0, cu.np_all);
+    if (c < cu.off0) cursor_init(cu, p_rec, p_shift, cu.pb0, cu.np_all);
     while (c >= cu.off0 + cu.nb.nj && cu.b0 + 64 < cu.np_all) {
         cu.off0 += cu.nb.nj;
         cu.b0 += 64;
-        cu.nb = load_nbr(p_leaf, p_shift, lf_start, lf_count, cu.pb0 + cu.b0, min(cu.np_all - cu.b0, 64));
+        cu.nb = load_nbr(p_rec, p_shift, cu.pb0 + cu.b0, min(cu.np_all - cu.b0, 64));
     }
 }
 
