@@ -876,8 +876,8 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     // no drift since this build; the smallest search radius bounds how far
     // the particles may drift before the cells are rebuilt
     unsigned* drift = ensure<unsigned>(c, c->drift, 4);
-    fill_u32(drift, 0u, 2, s);
-    fill_u32(drift + 2, 0x7f800000u, 1, s);
+    fill_u32(drift, 0u, 4, s);               // bound, step maximum, (minimum below), non-finite flag
+    fill_u32(drift + 2, 0x7f800000u, 1, s);  // +inf before the minimum
     k_min_H<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, BS), 256)), BS, 0, s>>>(n, Hs,
                                                                                                  drift + 2);
     SPH_HIP(hipGetLastError());

@@ -17,7 +17,7 @@ import pytest
 import oracle
 import workloads
 from oracle import leapfrog
-from parity import TOL32, assert_within, errors
+from parity import TOL32, TOL64, assert_within, errors
 
 pytestmark = pytest.mark.gpu
 
@@ -119,11 +119,23 @@ def test_drift_keeps_the_cells(gpu_lib, case):
                     ctx.drift(step, t["vel"], t["pos"])
                 delta = math.sqrt(3.0) * vmax * (dt + n_drift * step)
                 assert 2.0 * delta > budget  # this regime must rebuild
+            ro = oracle.run(_drifted(d, _np(t["pos"])))
+            # the plain FP64 form first (its own check of the drift, and a
+            # rebuild from the last guesses in the second regime), then FP32
+            h64 = t["h0"].double().clone()
+            r64 = ctx.density_f64(t["mass"].double(), h64)
+            f64 = ctx.force_f64(t["vel"].double(), t["u"].double(), cons=False)
+            torch.cuda.synchronize()
+            g64 = {"h": _np(h64), "rho": _np(r64["rho"]), "f": _np(r64["f"]), "nw": _np(h64) * 0 + 1,
+                   "acc": _np(f64["acc"]), "dudt": _np(f64["dudt"])}
+            e64 = errors(g64, ro)
+            e64["nw"] = 0.0
+            print(regime, "fp64", e64, flush=True)
+            assert_within(e64, TOL64, regime + " fp64")
             r = ctx.pass_(t["mass"], h, t["vel"], t["u"])
             torch.cuda.synchronize()
             g = {"h": _np(h), "rho": _np(r["rho"]), "f": _np(r["f"]), "nw": _np(h) * 0 + 1,
                  "acc": _np(r["acc"]), "dudt": _np(r["dudt"])}
-            ro = oracle.run(_drifted(d, _np(t["pos"])))
             e = errors(g, ro)
             e["nw"] = 0.0
             print(regime, e, flush=True)
