@@ -283,8 +283,8 @@ def main() -> int:
         lf = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
               "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
               "build_ms": ctx_l.timings()["build_ms"],
-              "note": "wall time per step from the host (kick, drift, kick, cell build, pass, kick, "
-                      "time step), after one untimed step"}
+              "note": "wall time per step from the host (kick, drift, kick, pass with a cell rebuild "
+                      "when the drift bound requires one, kick, time step), after one untimed step"}
         ctx_l.close()
 
     # ---- roofline of the dominant kernel ------------------------------------------------

@@ -473,21 +473,5 @@ __device__ __forceinline__ double image_shift(int code, int axis, double L)
     return v == 0 ? 0.0 : (v == 1 ? L : -L);
 }
 
-// atomicMax of v into base[key] with one atomic per wavefront when every valid
-// lane has the same key (consecutive particles mostly share a box), one per
-// lane otherwise. All 64 lanes must call it; invalid lanes pass valid = false.
-__device__ __forceinline__ void wave_atomic_max_u32(unsigned* base, int key, unsigned v, bool valid)
-{
-    const int k0 = __shfl(key, 0, 64);
-    const bool any = __any(valid);  // on every lane (not only inside lane 0's branch)
-    if (__all(!valid || key == k0)) {
-        unsigned m = valid ? v : 0u;
-        for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
-        if ((threadIdx.x & 63) == 0 && any) atomicMax(&base[k0], m);
-    } else if (valid) {
-        atomicMax(&base[key], v);
-    }
-}
-
 #define SPH_PI_F 3.14159265358979323846f
 #define SPH_PI_D 3.14159265358979323846

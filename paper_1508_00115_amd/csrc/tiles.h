@@ -91,12 +91,6 @@ __device__ __forceinline__ int choose_lpi(int ni, int nj, int lpi_min, float lis
     return best;
 }
 
-__device__ __forceinline__ int wave_sum_i(int v)
-{
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -319,31 +313,10 @@ __device__ __forceinline__ bool chunk_mass_differs(const ChunkRegs<NF, CAP>& R, 
     return __any(d);
 }
 
-template <int NF, int CAP>
-__device__ __forceinline__ void commit_chunk(float4* sj, const ChunkRegs<NF, CAP>& R)
-{
-    const int lane = threadIdx.x & 63;
-    constexpr int PER = CAP / 64;
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const int t = lane + 64 * r;
-        if (t < R.len) {
-            float4 a = R.v[r][0];
-            a.x += R.s[r][0];
-            a.y += R.s[r][1];
-            a.z += R.s[r][2];
-            sj[t] = a;
-#pragma unroll
-            for (int f = 1; f < NF; ++f) sj[f * CAP + t] = R.v[r][f];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// commit_chunk for a one-float4 tile whose unused slots [len, CAP) are filled
-// with a position far outside any search radius: a loop over the chunk may
-// then run to a multiple of its stride without a bounds test.
+// Store a fetched one-float4 chunk into the tile (shifted into the cell
+// frame), its unused slots [len, CAP) filled with a position far outside any
+// search radius: a loop over the chunk may then run to a multiple of its
+// stride without a bounds test.
 template <int CAP>
 __device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<1, CAP>& R)
 {
@@ -385,8 +358,8 @@ __device__ __forceinline__ float box_dist2(float x, float y, float z, float hw)
 __device__ __forceinline__ float cull_half_width(float hw) { return hw * 1.000001f; }
 __device__ __forceinline__ float cull_reach2(float reach) { return (reach * 1.00001f) * (reach * 1.00001f); }
 
-// commit_chunk (NF float4 per candidate, slot 0 = x, y, z, h^2) with the
-// cell-box test: a candidate is kept when the box lies within
+// Store a fetched chunk (NF float4 per candidate, slot 0 = x, y, z, h^2) with
+// the cell-box test: a candidate is kept when the box lies within
 // max(reach, h_j) of it. Returns how many were kept (packed from slot 0).
 template <int NF, int CAP>
 __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<NF, CAP>& R, float hw,
