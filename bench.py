@@ -332,8 +332,10 @@ def main() -> int:
         "density": {"sweeps": sd["sweeps"], "rebuilds": sd["rebuilds"],
                     "candidates": sd["candidates_density"],
                     "sweep_interactions": sd["sweep_interactions_density"],
+                    "candidates_per_interaction": sd["candidates_density"] / max(1, sd["interactions_density"]),
                     "cells": sd["n_cells"], "cell_pairs": sd["n_pairs"]},
-        "force": {"candidates": sf["candidates_force"]},
+        "force": {"candidates": sf["candidates_force"],
+                  "candidates_per_interaction": sf["candidates_force"] / max(1, sf["interactions_force"])},
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
         "speedup_vs_fp64_plain": value / value64,
         "leapfrog": lf,
