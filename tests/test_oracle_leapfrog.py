@@ -139,3 +139,16 @@ def test_energy_error_is_second_order_and_small():
         exch.append(0.5 * float((s["mass"][:, None] * np.asarray(s["vel"]) ** 2).sum()) - kin0)
     assert abs(err[0]) < 0.02 * abs(exch[0]), (err, exch)
     assert abs(err[0] / err[1]) > 3.0, err
+
+
+def test_drift_wraps_into_the_box():
+    # crossings of both faces, several box lengths, and values within rounding
+    # of a multiple of L all land in [0, L) at the periodic image of x + v dt
+    L = 0.8
+    x = np.array([[0.79, 0.01, 0.4], [0.0, 0.7999999999999999, 0.4], [0.3, 0.3, 0.3]])
+    v = np.array([[1.0, -1.0, 0.0], [-1e-17, 1e-16, 0.0], [25.0, -33.0, 8.0]])
+    dt = 0.05
+    y = leapfrog.drift(x, v, dt, L)
+    assert np.all(y >= 0.0) and np.all(y < L)
+    d = (y - (x + v * dt)) / L
+    assert np.max(np.abs(d - np.round(d))) < 1e-12
