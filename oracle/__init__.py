@@ -57,8 +57,10 @@ def _load():
         lib.orc_density.argtypes = [I64, P, P, D, D, I64, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.orc_density.restype = ctypes.c_int
         lib.orc_force.argtypes = [I64, P, P, P, P, P, P, P, D, D, D, I64, P,
-                                  P, P, P, P, P, P, P, P, ctypes.c_int, P]
+                                  P, P, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.orc_force.restype = ctypes.c_int
+        lib.orc_divcurl.argtypes = [I64, P, P, P, P, P, D, I64, P, P, P, P, ctypes.c_int, P]
+        lib.orc_divcurl.restype = ctypes.c_int
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -103,12 +105,13 @@ def density(pos, mass, L: float = 1.0, n_ngb: float = N_NGB, targets=None, h_sta
 
 
 def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
-          alpha: float = ALPHA, targets=None, threads: int = 0) -> dict:
+          alpha: float = ALPHA, targets=None, threads: int = 0, balsara=None) -> dict:
     """Acceleration, du/dt, their gross scales (sum of |pair term|), their
     kernel scales (pair terms at full kernel slope), the ordered pair count
     #{j != i: r < max(h_i, h_j)} and the signal velocity
     max(c_i, max_j (c_i + c_j - 3 min(v_ij . rhat, 0))) of the targets (all
-    when None)."""
+    when None). ``balsara``: per-particle Balsara factors that scale the
+    viscosity of each pair by their mean (None: no switch)."""
     lib = _load()
     pos = _f64(pos, (-1, 3))
     n = pos.shape[0]
@@ -123,7 +126,7 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
                        float(alpha), 0 if tg is None else tg.size, _ptr(tg), _ptr(acc),
                        _ptr(out["dudt"]), _ptr(out["gross_a"]), _ptr(out["gross_u"]),
                        _ptr(out["scale_a"]), _ptr(out["scale_u"]), _ptr(npair), _ptr(out["vsig"]),
-                       int(threads), ctypes.byref(bad))
+                       _ptr(None if balsara is None else _f64(balsara)), int(threads), ctypes.byref(bad))
     if rc:
         raise RuntimeError("oracle force: %s (particle %d)" % (_ERR.get(rc, rc), bad.value))
     out["acc"] = acc
@@ -131,14 +134,50 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
     return out
 
 
+def divcurl(pos, vel, mass, h, rho, L: float = 1.0, targets=None, threads: int = 0) -> dict:
+    """Velocity divergence ``div``, curl ``curl`` (n, 3) and the gross scale
+    ``gross`` (sum of |m_j v_ij D_i| / rho_i) of the targets (all when None),
+    as in the Balsara paragraph of the header of ``sph_oracle.c``."""
+    lib = _load()
+    pos = _f64(pos, (-1, 3))
+    n = pos.shape[0]
+    vel = _f64(vel, (-1, 3))
+    mass, h, rho = _f64(mass), _f64(h), _f64(rho)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    out = {"div": np.full(n, np.nan), "curl": np.full((n, 3), np.nan), "gross": np.full(n, np.nan)}
+    bad = ctypes.c_int64(-1)
+    rc = lib.orc_divcurl(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(h), _ptr(rho), float(L),
+                         0 if tg is None else tg.size, _ptr(tg), _ptr(out["div"]), _ptr(out["curl"]),
+                         _ptr(out["gross"]), int(threads), ctypes.byref(bad))
+    if rc:
+        raise RuntimeError("oracle divcurl: %s (particle %d)" % (_ERR.get(rc, rc), bad.value))
+    return out
+
+
+def balsara_factor(div, curl, u, h, gamma: float = GAMMA):
+    """B = |div v| / (|div v| + |curl v| + 1e-4 c / h), c the sound speed of
+    the ideal gas at u (the Gadget-2 form of the Balsara switch)."""
+    a = np.abs(np.asarray(div, dtype=np.float64))
+    w = np.linalg.norm(np.asarray(curl, dtype=np.float64).reshape(-1, 3), axis=1)
+    c = np.sqrt(gamma * (gamma - 1.0) * np.asarray(u, dtype=np.float64))
+    return a / (a + w + 1e-4 * c / np.asarray(h, dtype=np.float64))
+
+
 def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: float = GAMMA,
-            alpha: float = ALPHA, h_start=None, threads: int = 0) -> dict:
+            alpha: float = ALPHA, h_start=None, threads: int = 0, balsara: bool = False) -> dict:
     """Density then force for every particle of one periodic box, with the
-    conservation sums of the box and the wall time of the two phases."""
+    conservation sums of the box and the wall time of the two phases. With
+    ``balsara`` the force applies the Balsara switch; the factors are
+    returned as ``balsara``, div v and curl v as ``div`` and ``curl``."""
     t0 = time.perf_counter()
     d = density(pos, mass, L, n_ngb, h_start=h_start, threads=threads)
     t1 = time.perf_counter()
-    fo = force(pos, vel, mass, u, d["h"], d["rho"], d["f"], L, gamma, alpha, threads=threads)
+    B = None
+    if balsara:
+        dc = divcurl(pos, vel, mass, d["h"], d["rho"], L, threads=threads)
+        B = balsara_factor(dc["div"], dc["curl"], u, d["h"], gamma)
+        d.update(div=dc["div"], curl=dc["curl"], gross_dc=dc["gross"], balsara=B)
+    fo = force(pos, vel, mass, u, d["h"], d["rho"], d["f"], L, gamma, alpha, threads=threads, balsara=B)
     t2 = time.perf_counter()
     d.update(fo)
     d.update(conservation(mass, vel, fo["acc"], fo["dudt"]))
@@ -164,11 +203,11 @@ def conservation(mass, vel, acc, dudt) -> dict:
 
 
 def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPHA,
-        threads: int = 0) -> dict:
+        threads: int = 0, balsara: bool = False) -> dict:
     """Oracle over every box of a workload dict (see the ``workloads``
     package); per-particle outputs are concatenated in input order."""
     keys = ("h", "rho", "f", "nw", "nngb", "acc", "dudt", "gross_a", "gross_u", "scale_a", "scale_u",
-            "npair", "vsig")
+            "npair", "vsig") + (("div", "curl", "gross_dc", "balsara") if balsara else ())
     parts = {k: [] for k in keys}
     cons = []
     t_d = t_f = 0.0
@@ -177,13 +216,13 @@ def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPH
         s, e = int(d["box_first"][b]), int(d["box_first"][b + 1])
         if e == s:
             for k in keys:
-                parts[k].append(np.zeros((0, 3) if k == "acc" else (0,),
+                parts[k].append(np.zeros((0, 3) if k in ("acc", "curl") else (0,),
                                          dtype=np.int64 if k in ("nngb", "npair") else np.float64))
             cons.append((np.zeros(3), 0.0, 0.0, 0.0))
             continue
         r = run_box(d["pos"][s:e], d["vel"][s:e], d["mass"][s:e], d["u"][s:e],
                     float(d["box_len"][b]), n_ngb, gamma, alpha, h_start=d["h0"][s:e],
-                    threads=threads)
+                    threads=threads, balsara=balsara)
         for k in keys:
             parts[k].append(r[k])
         cons.append((r["mom"], r["energy"], r["mom_scale"], r["energy_scale"]))

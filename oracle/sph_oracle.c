@@ -29,6 +29,12 @@
  *              G = Phi_i D_i + Phi_j D_j + Pi_ij (D_i + D_j) / 2
  *              a_i    -= m_j G rhat
  *              du_i/dt += m_j (Phi_i D_i + Pi_ij (D_i + D_j) / 4) (v_ij . rhat)
+ *   Balsara    (optional) Pi_ij is scaled by (B_i + B_j) / 2 with the
+ *              Balsara factor B_k = |div v|_k / (|div v|_k + |curl v|_k +
+ *              1e-4 c_k / h_k) (the Gadget-2 form; not in the paper), from
+ *              rho_i (div v)_i  = sum_j m_j (v_j - v_i) . rhat D_i
+ *              rho_i (curl v)_i = sum_j m_j (v_i - v_j) x rhat D_i
+ *              over 0 < r_ij < h_i (orc_divcurl)
  *
  * Distances use the minimum image of a periodic cubic box of side L, which
  * needs every smoothing length below L / 2 (checked).
@@ -343,13 +349,15 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
  *                 pairs with 0 < r_ij < max(h_i, h_j): the speed in the Courant
  *                 condition of the time step (the Gadget-2 choice that the
  *                 paper's force form follows)
+ *   balsara       per-particle Balsara factors B (see the header) scaling the
+ *                 viscosity by (B_i + B_j) / 2; NULL: no switch
  */
 int orc_force(int64_t n, const double *pos, const double *vel, const double *mass,
               const double *u, const double *h, const double *rho, const double *f,
               double L, double gamma, double alpha, int64_t n_targets, const int64_t *targets,
               double *acc_out, double *dudt_out, double *gross_a_out, double *gross_u_out,
-              double *scale_a_out, double *scale_u_out, int64_t *npair_out, double *vsig_out, int nthreads,
-              int64_t *bad)
+              double *scale_a_out, double *scale_u_out, int64_t *npair_out, double *vsig_out,
+              const double *balsara, int nthreads, int64_t *bad)
 {
     if (n <= 0 || !pos || !vel || !mass || !u || !h || !rho || !f || !acc_out || !dudt_out)
         return ORC_E_ARG;
@@ -417,6 +425,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                             (vel[3 * i + 2] - vel[3 * j + 2]) * ez;
                 double wv = vr < 0.0 ? vr : 0.0;
                 double Pv = -alpha * (ci + cj - 3.0 * wv) * wv / (rho[i] + rho[j]);
+                if (balsara) Pv *= 0.5 * (balsara[i] + balsara[j]);
                 double vs = ci + cj - 3.0 * wv;
                 if (vs > vsig) vsig = vs;
                 double Dbar = 0.5 * (Di + Dj);
@@ -444,6 +453,82 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             if (scale_u_out) scale_u_out[i] = su;
             if (npair_out) npair_out[i] = np;
             if (vsig_out) vsig_out[i] = vsig;
+        }
+        cand_free(&c);
+    }
+    grid_free(&gr);
+    return status;
+}
+
+/*
+ * Velocity divergence and curl of the listed targets (all when targets ==
+ * NULL), the SPH estimates of the header's Balsara paragraph: the gather sums
+ * over the neighbours j != i with 0 < r_ij < h_i, divided by rho_i.
+ *   div_out       (div v)_i
+ *   curl_out      (curl v)_i, 3 per particle
+ *   gross_out     sum_j m_j |v_ij| |D_i| / rho_i, which bounds both sums'
+ *                 terms (the scale their rounding errors are judged by)
+ * h and rho must be valid for every particle within h of a target.
+ */
+int orc_divcurl(int64_t n, const double *pos, const double *vel, const double *mass,
+                const double *h, const double *rho, double L, int64_t n_targets, const int64_t *targets,
+                double *div_out, double *curl_out, double *gross_out, int nthreads, int64_t *bad)
+{
+    if (n <= 0 || !pos || !vel || !mass || !h || !rho || !div_out || !curl_out) return ORC_E_ARG;
+    if (nthreads > 0) {
+#ifdef _OPENMP
+        omp_set_num_threads(nthreads);
+#endif
+    }
+    double hmax = 0.0;
+    for (int64_t p = 0; p < n; ++p)
+        if (h[p] > hmax) hmax = h[p];
+    if (!(hmax < 0.5 * L)) return ORC_E_RADIUS;
+    grid_t gr;
+    int rc = grid_build(&gr, n, pos, L);
+    if (rc) { grid_free(&gr); return rc; }
+    const int64_t nt = targets ? n_targets : n;
+    int status = ORC_OK;
+    *bad = -1;
+
+#pragma omp parallel
+    {
+        cand_t c = {0, 0, NULL, NULL, NULL};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t t = 0; t < nt; ++t) {
+            int st;
+#pragma omp atomic read
+            st = status;
+            if (st != ORC_OK) continue;
+            int64_t i = targets ? targets[t] : t;
+            if (!(h[i] > 0) || !(rho[i] > 0) || gather(&gr, pos, i, h[i], &c)) {
+#pragma omp critical
+                { if (status == ORC_OK) { status = h[i] > 0 && rho[i] > 0 ? ORC_E_NOMEM : ORC_E_ARG; *bad = i; } }
+                continue;
+            }
+            const double hi_ = h[i];
+            double dv = 0, cx = 0, cy = 0, cz = 0, g = 0;
+            for (int64_t k = 0; k < c.n; ++k) {
+                int64_t j = c.j[k];
+                double r = c.r[k];
+                if (j == i || !(r > 0.0) || !(r < hi_)) continue;
+                double ex = c.dx[3 * k + 0] / r, ey = c.dx[3 * k + 1] / r, ez = c.dx[3 * k + 2] / r;
+                double Di = 8.0 / (ORC_PI * hi_ * hi_ * hi_ * hi_) * dw_shape(r / hi_);
+                double wx = vel[3 * i + 0] - vel[3 * j + 0];  /* v_i - v_j */
+                double wy = vel[3 * i + 1] - vel[3 * j + 1];
+                double wz = vel[3 * i + 2] - vel[3 * j + 2];
+                double mD = mass[j] * Di;
+                dv -= mD * (wx * ex + wy * ey + wz * ez);
+                cx += mD * (wy * ez - wz * ey);
+                cy += mD * (wz * ex - wx * ez);
+                cz += mD * (wx * ey - wy * ex);
+                g += fabs(mD) * sqrt(wx * wx + wy * wy + wz * wz);
+            }
+            div_out[i] = dv / rho[i];
+            curl_out[3 * i + 0] = cx / rho[i];
+            curl_out[3 * i + 1] = cy / rho[i];
+            curl_out[3 * i + 2] = cz / rho[i];
+            if (gross_out) gross_out[i] = g / rho[i];
         }
         cand_free(&c);
     }
