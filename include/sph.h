@@ -113,6 +113,17 @@ typedef struct {
                              particle's signal velocity, which sph_timestep
                              needs (0: not recorded, one operation less per
                              pair) */
+    int32_t balsara;      /* nonzero: Balsara switch on the viscosity. The FP32
+                             force pass first sums each particle's velocity
+                             divergence and curl over its neighbours inside h
+                             (rho div v = sum m_j (v_j - v_i) . grad_i W(h_i),
+                             rho curl v = sum m_j (v_i - v_j) x grad_i W(h_i)),
+                             forms B = |div v| / (|div v| + |curl v| +
+                             1e-4 c / h) (0 where the denominator is 0), and
+                             scales each pair's viscosity by (B_i + B_j) / 2.
+                             The Gadget-2 form of the switch; the paper has
+                             no switch. Not in sph_force_f64 (SPH_E_ARG). One
+                             more pass over the pairs (0: off) */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP
@@ -313,6 +324,15 @@ sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, voi
  * the last build or drift), SPH_E_HIP. Synchronises `stream`.
  */
 sph_status sph_timestep(sph_ctx* ctx, double courant, double* dt, void* stream);
+
+/*
+ * Balsara factors B of the last force pass (see sph_params.balsara), in the
+ * caller's particle order.
+ *   balsara  device, n floats, out (caller-owned)
+ * Errors: SPH_E_ARG (null), SPH_E_STATE (no force pass with the switch since
+ * the last build or drift), SPH_E_HIP. Does not synchronise.
+ */
+sph_status sph_get_balsara(sph_ctx* ctx, float* balsara, void* stream);
 
 /* Copy the durations of the last calls into *out (host). Errors: SPH_E_ARG. */
 sph_status sph_get_timings(const sph_ctx* ctx, sph_timings* out);

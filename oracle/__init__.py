@@ -135,20 +135,21 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
 
 
 def divcurl(pos, vel, mass, h, rho, L: float = 1.0, targets=None, threads: int = 0) -> dict:
-    """Velocity divergence ``div``, curl ``curl`` (n, 3) and the gross scale
-    ``gross`` (sum of |m_j v_ij D_i| / rho_i) of the targets (all when None),
-    as in the Balsara paragraph of the header of ``sph_oracle.c``."""
+    """Velocity divergence ``div``, curl ``curl`` (n, 3) and their error scale
+    ``scale`` (sum of m_j |v_ij| / rho_i times the kernel's largest slope) of
+    the targets (all when None), as in the Balsara paragraph of the header of
+    ``sph_oracle.c``."""
     lib = _load()
     pos = _f64(pos, (-1, 3))
     n = pos.shape[0]
     vel = _f64(vel, (-1, 3))
     mass, h, rho = _f64(mass), _f64(h), _f64(rho)
     tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
-    out = {"div": np.full(n, np.nan), "curl": np.full((n, 3), np.nan), "gross": np.full(n, np.nan)}
+    out = {"div": np.full(n, np.nan), "curl": np.full((n, 3), np.nan), "scale": np.full(n, np.nan)}
     bad = ctypes.c_int64(-1)
     rc = lib.orc_divcurl(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(h), _ptr(rho), float(L),
                          0 if tg is None else tg.size, _ptr(tg), _ptr(out["div"]), _ptr(out["curl"]),
-                         _ptr(out["gross"]), int(threads), ctypes.byref(bad))
+                         _ptr(out["scale"]), int(threads), ctypes.byref(bad))
     if rc:
         raise RuntimeError("oracle divcurl: %s (particle %d)" % (_ERR.get(rc, rc), bad.value))
     return out
@@ -156,11 +157,13 @@ def divcurl(pos, vel, mass, h, rho, L: float = 1.0, targets=None, threads: int =
 
 def balsara_factor(div, curl, u, h, gamma: float = GAMMA):
     """B = |div v| / (|div v| + |curl v| + 1e-4 c / h), c the sound speed of
-    the ideal gas at u (the Gadget-2 form of the Balsara switch)."""
+    the ideal gas at u (the Gadget-2 form of the Balsara switch); 0 where the
+    denominator is 0 (no motion and no sound speed: nothing to damp)."""
     a = np.abs(np.asarray(div, dtype=np.float64))
     w = np.linalg.norm(np.asarray(curl, dtype=np.float64).reshape(-1, 3), axis=1)
     c = np.sqrt(gamma * (gamma - 1.0) * np.asarray(u, dtype=np.float64))
-    return a / (a + w + 1e-4 * c / np.asarray(h, dtype=np.float64))
+    den = a + w + 1e-4 * c / np.asarray(h, dtype=np.float64)
+    return np.where(den > 0, a / np.where(den > 0, den, 1.0), 0.0)
 
 
 def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: float = GAMMA,
@@ -168,7 +171,8 @@ def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: floa
     """Density then force for every particle of one periodic box, with the
     conservation sums of the box and the wall time of the two phases. With
     ``balsara`` the force applies the Balsara switch; the factors are
-    returned as ``balsara``, div v and curl v as ``div`` and ``curl``."""
+    returned as ``balsara``, div v and curl v as ``div`` and ``curl`` (their
+    error scale as ``scale_dc``)."""
     t0 = time.perf_counter()
     d = density(pos, mass, L, n_ngb, h_start=h_start, threads=threads)
     t1 = time.perf_counter()
@@ -176,7 +180,7 @@ def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: floa
     if balsara:
         dc = divcurl(pos, vel, mass, d["h"], d["rho"], L, threads=threads)
         B = balsara_factor(dc["div"], dc["curl"], u, d["h"], gamma)
-        d.update(div=dc["div"], curl=dc["curl"], gross_dc=dc["gross"], balsara=B)
+        d.update(div=dc["div"], curl=dc["curl"], scale_dc=dc["scale"], balsara=B)
     fo = force(pos, vel, mass, u, d["h"], d["rho"], d["f"], L, gamma, alpha, threads=threads, balsara=B)
     t2 = time.perf_counter()
     d.update(fo)
@@ -207,7 +211,7 @@ def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPH
     """Oracle over every box of a workload dict (see the ``workloads``
     package); per-particle outputs are concatenated in input order."""
     keys = ("h", "rho", "f", "nw", "nngb", "acc", "dudt", "gross_a", "gross_u", "scale_a", "scale_u",
-            "npair", "vsig") + (("div", "curl", "gross_dc", "balsara") if balsara else ())
+            "npair", "vsig") + (("div", "curl", "scale_dc", "balsara") if balsara else ())
     parts = {k: [] for k in keys}
     cons = []
     t_d = t_f = 0.0

@@ -466,13 +466,15 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
  * over the neighbours j != i with 0 < r_ij < h_i, divided by rho_i.
  *   div_out       (div v)_i
  *   curl_out      (curl v)_i, 3 per particle
- *   gross_out     sum_j m_j |v_ij| |D_i| / rho_i, which bounds both sums'
- *                 terms (the scale their rounding errors are judged by)
+ *   scale_out     sum_j m_j |v_ij| Dm_i / rho_i with Dm_i = 16 / (pi h_i^4),
+ *                 the terms at full kernel slope (max|w'| = 2): it bounds
+ *                 both sums' terms and does not shrink at the kernel edge,
+ *                 so it is the scale their rounding errors are judged by
  * h and rho must be valid for every particle within h of a target.
  */
 int orc_divcurl(int64_t n, const double *pos, const double *vel, const double *mass,
                 const double *h, const double *rho, double L, int64_t n_targets, const int64_t *targets,
-                double *div_out, double *curl_out, double *gross_out, int nthreads, int64_t *bad)
+                double *div_out, double *curl_out, double *scale_out, int nthreads, int64_t *bad)
 {
     if (n <= 0 || !pos || !vel || !mass || !h || !rho || !div_out || !curl_out) return ORC_E_ARG;
     if (nthreads > 0) {
@@ -522,13 +524,13 @@ int orc_divcurl(int64_t n, const double *pos, const double *vel, const double *m
                 cx += mD * (wy * ez - wz * ey);
                 cy += mD * (wz * ex - wx * ez);
                 cz += mD * (wx * ey - wy * ex);
-                g += fabs(mD) * sqrt(wx * wx + wy * wy + wz * wz);
+                g += mass[j] * 16.0 / (ORC_PI * hi_ * hi_ * hi_ * hi_) * sqrt(wx * wx + wy * wy + wz * wz);
             }
             div_out[i] = dv / rho[i];
             curl_out[3 * i + 0] = cx / rho[i];
             curl_out[3 * i + 1] = cy / rho[i];
             curl_out[3 * i + 2] = cz / rho[i];
-            if (gross_out) gross_out[i] = g / rho[i];
+            if (scale_out) scale_out[i] = g / rho[i];
         }
         cand_free(&c);
     }

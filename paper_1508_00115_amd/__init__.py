@@ -28,7 +28,7 @@ SPH_E_STATE = 6
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
            "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info",
-           "sph_kick", "sph_drift", "sph_timestep")
+           "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara")
 
 
 class sph_params(ctypes.Structure):
@@ -39,7 +39,7 @@ class sph_params(ctypes.Structure):
                 ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("queue_batch", ctypes.c_int32),
                 ("tile_cap", ctypes.c_int32), ("cell_order", ctypes.c_int32),
-                ("signal_velocity", ctypes.c_int32)]
+                ("signal_velocity", ctypes.c_int32), ("balsara", ctypes.c_int32)]
 
 
 class sph_stats(ctypes.Structure):
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_drift.restype = ctypes.c_int
     lib.sph_timestep.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
     lib.sph_timestep.restype = ctypes.c_int
+    lib.sph_get_balsara.argtypes = [P, P, P]
+    lib.sph_get_balsara.restype = ctypes.c_int
     lib.sph_struct_size.argtypes = [ctypes.c_int32]
     lib.sph_struct_size.restype = ctypes.c_int32
     _lib = lib
@@ -199,6 +201,10 @@ def sph_drift(ctx, dt, vel, pos, stream) -> int:
 
 def sph_timestep(ctx, courant, dt_out, stream) -> int:
     return load_library().sph_timestep(ctx, courant, dt_out, stream)
+
+
+def sph_get_balsara(ctx, balsara, stream) -> int:
+    return load_library().sph_get_balsara(ctx, balsara, stream)
 
 
 def sph_get_timings(ctx, out) -> int:
@@ -363,6 +369,16 @@ class Context:
         rc = sph_timestep(self.ctx, float(courant), ctypes.byref(out), _stream(stream))
         _check(rc, self.ctx)
         return out.value
+
+    def balsara(self, out=None, stream=None):
+        """sph_get_balsara: the Balsara factors of the last force pass, in
+        input order (float32, (n,), on the context's device)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        rc = sph_get_balsara(self.ctx, _dev(out, torch.float32, (self.n,), "balsara"), _stream(stream))
+        _check(rc, self.ctx)
+        return out
 
     def step(self, dt, pos, mass, h, vel, u, acc, dudt, rho=None, f=None, stream=None) -> dict:
         """One kick-drift-kick step of length dt (every array in place): acc

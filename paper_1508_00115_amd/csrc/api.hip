@@ -118,7 +118,7 @@ void sph_destroy(sph_ctx* c)
                        &c->nd_level, &c->nd_coord, &c->nflag, &c->nscan, &c->top, &c->lf_start, &c->lf_count,
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->status,
-                       &c->st_s, &c->jf, &c->vsig_s, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
+                       &c->st_s, &c->jf, &c->vsig_s, &c->bal_s, &c->jf4, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
                        &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom,
                        &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
@@ -203,6 +203,15 @@ sph_status sph_timestep(sph_ctx* c, double courant, double* dt, void* stream)
         SPH_REQUIRE(dt, SPH_E_ARG, "null dt");
         set_device(c);
         *dt = sph::timestep(c, courant, (hipStream_t)stream);
+    });
+}
+
+sph_status sph_get_balsara(sph_ctx* c, float* balsara, void* stream)
+{
+    if (!c) return SPH_E_ARG;
+    return guarded(c, [&] {
+        set_device(c);
+        sph::balsara_unsort(c, balsara, (hipStream_t)stream);
     });
 }
 

@@ -896,6 +896,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     c->built = true;
     c->drift_pending = false;
     c->vsig_valid = false;  // signal velocities belong to the cells of the last force pass
+    c->bal_valid = false;
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
     c->density64_done = false;

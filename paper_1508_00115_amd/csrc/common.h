@@ -196,6 +196,9 @@ struct sph_ctx {
     sph::Buf jf;             // 3 float4 per particle for the force loop
     sph::Buf vsig_s;         // float, sorted: signal velocity of the last force pass
     bool vsig_valid = false; // vsig_s matches the current cells and h
+    sph::Buf bal_s;          // float, sorted: Balsara factor of the last force pass
+    sph::Buf jf4;            // 4 float4 per particle: jf and (B, 0, 0, 0), for the switch
+    bool bal_valid = false;  // bal_s matches the current cells and h
     sph::Buf counters;       // int64[CT_COUNT]
     sph::Buf cons_d;         // double, 4 per box (FP32 force loop)
     sph::Buf cons_part;      // double, 4 per leaf: each cell's share of cons_d
@@ -378,6 +381,8 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
 // Allocate what one density pass / force pass needs (never under capture).
 void density_buffers(sph_ctx* c);
 double* force_buffers(sph_ctx* c, bool cons);
+// Input-order Balsara factors of the last force pass into out (device, n).
+void balsara_unsort(sph_ctx* c, float* out, hipStream_t s);
 // Kernel launches only: no allocation, memset or host synchronisation, so
 // they may run under stream capture. events: record the timing events.
 // ghost (density_enqueue, with vel and u): the density kernels also write

@@ -15,6 +15,13 @@
 // in FP64: each wave stores its cell's share (plain stores, no atomics) and a
 // second kernel adds the shares of each box's cells in a fixed order, so the
 // sums are also reproducible.
+//
+// With the Balsara switch (not in the paper; the Gadget-2 form) the same loop
+// first runs in a gather mode that sums the velocity divergence and curl of
+// each particle over its neighbours inside h_i and stores the factor
+// B = |div v| / (|div v| + |curl v| + 1e-4 c / h); a fourth float4 per
+// particle, (B, 0, 0, 0), then carries it into the force loop, which scales
+// each pair's viscosity by (B_i + B_j) / 2.
 #include "common.h"
 #include "tiles.h"
 
@@ -61,6 +68,7 @@ struct ForceArgs {
     float* dudt;
     double* cons_part;  // 4 per leaf, may be null
     float* vsig;        // sorted: signal velocity per particle (k_force<true> only)
+    float* bal;         // sorted: Balsara factor per particle (written in the FM_DIVCURL mode)
     const float* drift; // [0]: bound on the drift since the build (cell boxes widen by it)
     int64_t* ctr;
     WorkSched W;
@@ -108,12 +116,39 @@ __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
     wave_sync_lds();
 }
 
+// What a pass of k_force computes: the force; the force with the Balsara
+// switch (4 float4 per particle); the Balsara factors (3 float4 per particle,
+// no force, no counters).
+enum { FM_FORCE = 0, FM_BALSARA = 1, FM_DIVCURL = 2 };
+
+// (B, 0, 0, 0) after the three float4 of each particle, for FM_BALSARA.
+__global__ void k_pack_balsara(int64_t n, const float4* __restrict__ jf, const float* __restrict__ bal,
+                               float4* __restrict__ jf4)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    jf4[4 * p + 0] = jf[3 * p + 0];
+    jf4[4 * p + 1] = jf[3 * p + 1];
+    jf4[4 * p + 2] = jf[3 * p + 2];
+    jf4[4 * p + 3] = make_float4(bal[p], 0.0f, 0.0f, 0.0f);
+}
+
+// Input-order copy of the sorted Balsara factors.
+__global__ void k_unsort_f32(int64_t n, const uint32_t* __restrict__ perm, const float* __restrict__ src,
+                             float* __restrict__ dst)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) dst[perm[p]] = src[p];
+}
+
 // VSIG: also record each particle's signal velocity max(c_i, max_j (c_i +
 // c_j - 3 w_ij)) over its pairs, for the Courant time step.
-template <bool VSIG>
+template <bool VSIG, int MODE>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
-    __shared__ float4 tile[3 * FCAP];
+    constexpr int NF = MODE == FM_BALSARA ? 4 : 3;
+    constexpr bool DC = MODE == FM_DIVCURL;
+    __shared__ float4 tile[NF * FCAP];
     __shared__ uint8_t lists[FSLOTS * 64];
     __shared__ uint8_t marks[FCAP];  // record starts of the chunk being fetched
     const int lane = threadIdx.x & 63;
@@ -147,9 +182,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const int gi = ib + g;
             const bool valid = gi < ni;
             const int i = i0 + (valid ? gi : 0);
-            const float4 i0v = A.jf[3 * (int64_t)i + 0];
-            const float4 i1v = A.jf[3 * (int64_t)i + 1];
-            const float4 i2v = A.jf[3 * (int64_t)i + 2];
+            const float4 i0v = A.jf[NF * (int64_t)i + 0];
+            const float4 i1v = A.jf[NF * (int64_t)i + 1];
+            const float4 i2v = A.jf[NF * (int64_t)i + 2];
+            const float bal_i = MODE == FM_BALSARA ? A.jf[NF * (int64_t)i + 3].x : 1.0f;
             const float h2_i = i0v.w;
             const float hinv_i = i2v.w;
             const float hinv2_i = hinv_i * hinv_i;
@@ -158,7 +194,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
             float vmax = 0.f;  // (VSIG) largest c_i + c_j - 3 w_ij of this lane's pairs
             int cnt = 0;
-            ChunkRegs<3, FCAP> R;
+            ChunkRegs<NF, FCAP> R;
             const bool stream_chunks = !(single_tile && loaded);
             int len, kept = 0;  // candidates of this chunk; kept by the cell-box test (all chunks)
             for (int c0 = 0; c0 < nj; c0 += len) {
@@ -201,6 +237,18 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float4 p2 = sj[2 * FCAP + k];
                     const float dx = i0v.x - p0.x, dy = i0v.y - p0.y, dz = i0v.z - p0.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if constexpr (DC) {
+                        // rho_i div v_i = -sum m_j D_i (v_i - v_j) . rhat, rho_i curl v_i =
+                        // sum m_j D_i (v_i - v_j) x rhat; D_i is 0 from r = h_i on
+                        const float rinv = __builtin_amdgcn_rsqf(r2);
+                        const float mD = p1.w * Ki * spline_dw_r(r2 * rinv, hinv_i) * rinv;
+                        const float wx = i1v.x - p1.x, wy = i1v.y - p1.y, wz = i1v.z - p1.z;
+                        du = fmaf(mD, fmaf(wx, dx, fmaf(wy, dy, wz * dz)), du);
+                        ax = fmaf(mD, wy * dz - wz * dy, ax);
+                        ay = fmaf(mD, wz * dx - wx * dz, ay);
+                        az = fmaf(mD, wx * dy - wy * dx, az);
+                        continue;
+                    }
                     const float hinv_j = p2.w;
                     const float hinv2_j = hinv_j * hinv_j;
                     const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 > 0 (phase A), far from denormal
@@ -210,7 +258,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float vr = ((i1v.x - p1.x) * dx + (i1v.y - p1.y) * dy + (i1v.z - p1.z) * dz) * rinv;
                     const float wv_ = fminf(vr, 0.0f);
                     const float vsig_ij = c_i + p2.z - 3.0f * wv_;
-                    const float visc = -A.alpha * vsig_ij * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
+                    float visc = -A.alpha * vsig_ij * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
+                    if constexpr (MODE == FM_BALSARA) visc *= 0.5f * (bal_i + sj[3 * FCAP + k].x);
                     if constexpr (VSIG) vmax = fmaxf(vmax, vsig_ij);
                     const float Dbar = 0.5f * (Di + Dj);
                     const float G = fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
@@ -232,6 +281,15 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             cnt = group_sum_i(cnt, lpi);
             if constexpr (VSIG) vmax = group_max(vmax, lpi);
             const bool leader = valid && sub == 0;
+            if constexpr (DC) {
+                if (leader) {
+                    const float ad = fabsf(du) / rho_i;
+                    const float den = ad + sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az))) / rho_i +
+                                      1.0e-4f * c_i * hinv_i;
+                    A.bal[i] = den > 0.0f ? ad / den : 0.0f;  // no motion and no sound: no viscosity
+                }
+                continue;
+            }
             cand_acc += (int64_t)wave_count(leader) * kept;
             double cm[4] = {0.0, 0.0, 0.0, 0.0};
             if (leader) {
@@ -258,14 +316,16 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 }
             }
         }
-        if (A.cons_part && lane == 0) {
+        if (!DC && A.cons_part && lane == 0) {
             const int leaf = A.cell_aux[slot].x;
 #pragma unroll
             for (int k = 0; k < 4; ++k) A.cons_part[4 * (int64_t)leaf + k] = cm_cell[k];
         }
     }
-    ctr_wave_add(A.ctr, CT_FORCE_INTER, inter_acc);
-    ctr_add_uniform(A.ctr, CT_FORCE_CAND, cand_acc);  // already a wavefront total
+    if constexpr (!DC) {
+        ctr_wave_add(A.ctr, CT_FORCE_INTER, inter_acc);
+        ctr_add_uniform(A.ctr, CT_FORCE_CAND, cand_acc);  // already a wavefront total
+    }
 }
 
 // Per-box sums of the cells' shares: block b adds the shares of its leaves
@@ -336,17 +396,33 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.cons_part = cons_d ? static_cast<double*>(c->cons_part.p) : nullptr;
     const bool vsig = c->prm.signal_velocity != 0;
     A.vsig = vsig ? static_cast<float*>(c->vsig_s.p) : nullptr;
+    A.bal = static_cast<float*>(c->bal_s.p);
     A.drift = static_cast<float*>(c->drift.p);
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
     A.list_work = (float)(4.0 * c->prm.n_ngb);  // ~n_ngb pairs per particle at ~4 tests' cost each
     if (events) ev_record(c, EV_FORCE_K0, s);
-    if (vsig)
-        k_force<true><<<grid, BS, 0, s>>>(A);
-    else
-        k_force<false><<<grid, BS, 0, s>>>(A);
+    const bool bal = c->prm.balsara != 0 && A.alpha > 0.0f;
+    if (bal) {
+        k_force<false, FM_DIVCURL><<<grid, BS, 0, s>>>(A);
+        SPH_HIP(hipGetLastError());
+        float4* jf4 = static_cast<float4*>(c->jf4.p);
+        k_pack_balsara<<<blocks_for(n, 256), 256, 0, s>>>(n, jf, A.bal, jf4);
+        SPH_HIP(hipGetLastError());
+        if (c->prm.schedule == 1) fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);  // the force pass pops the queues again
+        A.jf = jf4;
+        if (vsig)
+            k_force<true, FM_BALSARA><<<grid, BS, 0, s>>>(A);
+        else
+            k_force<false, FM_BALSARA><<<grid, BS, 0, s>>>(A);
+    } else if (vsig) {
+        k_force<true, FM_FORCE><<<grid, BS, 0, s>>>(A);
+    } else {
+        k_force<false, FM_FORCE><<<grid, BS, 0, s>>>(A);
+    }
     SPH_HIP(hipGetLastError());
+    c->bal_valid = bal;
     c->vsig_valid = vsig;
     if (events) ev_record(c, EV_FORCE_K1, s);
     if (cons_d) {
@@ -359,6 +435,10 @@ double* force_buffers(sph_ctx* c, bool cons)
 {
     ensure<float4>(c, c->jf, 3 * c->n);
     if (c->prm.signal_velocity) ensure<float>(c, c->vsig_s, c->n);
+    if (c->prm.balsara) {
+        ensure<float>(c, c->bal_s, c->n);
+        ensure<float4>(c, c->jf4, 4 * c->n);
+    }
     if (!cons) return nullptr;
     ensure<double>(c, c->cons_part, (size_t)4 * c->n_leaves);
     return ensure<double>(c, c->cons_d, (size_t)4 * c->n_boxes);
@@ -388,6 +468,17 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
         c->tm.force_kernel_ms = ev_ms(c, EV_FORCE_K0, EV_FORCE_K1);
         c->tm.force_call_ms = ev_ms(c, EV_FORCE_C0, EV_FORCE_C1);
     }
+}
+
+void balsara_unsort(sph_ctx* c, float* out, hipStream_t s)
+{
+    SPH_REQUIRE(out, SPH_E_ARG, "null output");
+    SPH_REQUIRE(c->built && c->bal_valid, SPH_E_STATE,
+                "sph_get_balsara needs a force pass with sph_params.balsara (and viscosity) since the last build or drift");
+    if (c->n == 0) return;
+    k_unsort_f32<<<blocks_for(c->n, 256), 256, 0, s>>>(c->n, static_cast<uint32_t*>(c->perm.p),
+                                                      static_cast<float*>(c->bal_s.p), out);
+    SPH_HIP(hipGetLastError());
 }
 
 }  // namespace sph

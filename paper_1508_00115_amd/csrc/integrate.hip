@@ -140,6 +140,7 @@ void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s)
     c->density_done = false;
     c->density64_done = false;
     c->vsig_valid = false;
+    c->bal_valid = false;
 }
 
 void check_drift(sph_ctx* c, const float* h_caller, hipStream_t s)

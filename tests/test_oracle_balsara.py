@@ -37,7 +37,7 @@ def _interior_field(A):
 def test_expansion_has_divergence_and_no_curl():
     a = 0.7
     dc, inner, _ = _interior_field(a * np.eye(3))
-    g = dc["gross"][inner]
+    g = dc["scale"][inner]
     kappa = dc["div"][inner] / (3 * a)
     assert np.all(np.abs(np.linalg.norm(dc["curl"][inner], axis=1)) < 1e-12 * g)
     assert np.ptp(kappa) < 1e-12
@@ -51,7 +51,7 @@ def test_rotation_has_curl_along_its_axis_and_no_divergence():
     om = np.array([0.3, -0.5, 0.2])
     A = np.array([[0, -om[2], om[1]], [om[2], 0, -om[0]], [-om[1], om[0], 0]])  # A x = om x x
     dc, inner, _ = _interior_field(A)
-    g = dc["gross"][inner]
+    g = dc["scale"][inner]
     assert np.all(np.abs(dc["div"][inner]) < 1e-12 * g)
     dce, _, _ = _interior_field(np.eye(3))
     kappa = dce["div"][inner][0] / 3.0
@@ -66,7 +66,7 @@ def test_shear_splits_into_its_divergence_and_curl():
     dc, inner, _ = _interior_field(A)
     dce, _, _ = _interior_field(np.eye(3))
     kappa = dce["div"][inner][0] / 3.0
-    g = dc["gross"][inner]
+    g = dc["scale"][inner]
     assert np.all(np.abs(dc["div"][inner]) < 1e-12 * g)
     assert np.allclose(dc["curl"][inner], kappa * np.array([0.0, 0.0, -s])[None, :], rtol=1e-12,
                        atol=1e-12 * g.max())
@@ -81,8 +81,8 @@ def test_uniform_motion_changes_nothing():
     a = oracle.divcurl(pos, vel, mass, de["h"], de["rho"])
     b = oracle.divcurl(pos, vel + np.array([3.0, -1.0, 2.0]), mass, de["h"], de["rho"])
     c = oracle.divcurl(pos, -vel, mass, de["h"], de["rho"])
-    assert np.max(np.abs(a["div"] - b["div"]) / a["gross"]) < 1e-11
-    assert np.max(np.abs(a["curl"] - b["curl"]) / a["gross"][:, None]) < 1e-11
+    assert np.max(np.abs(a["div"] - b["div"]) / a["scale"]) < 1e-11
+    assert np.max(np.abs(a["curl"] - b["curl"]) / a["scale"][:, None]) < 1e-11
     assert np.allclose(c["div"], -a["div"], rtol=0, atol=0)
     assert np.allclose(c["curl"], -a["curl"], rtol=0, atol=0)
     # random motion has both, and the factor lies in [0, 1]
@@ -97,6 +97,7 @@ def test_factor_of_pure_compression_and_pure_rotation():
     assert oracle.balsara_factor([-2.0], [[0, 0, 0]], u, h)[0] == pytest.approx(2.0 / (2.0 + 1e-4 * c / 0.1), rel=1e-15)
     assert oracle.balsara_factor([0.0], [[0, 3.0, 0]], u, h)[0] == 0.0
     assert oracle.balsara_factor([1.0], [[0, 0, -1.0]], u, h)[0] == pytest.approx(1.0 / (2.0 + 1e-4 * c / 0.1), rel=1e-15)
+    assert oracle.balsara_factor([0.0], [[0, 0, 0]], [0.0], h)[0] == 0.0  # at rest and cold
 
 
 @pytest.mark.parametrize("b", [(0.0, 0.0), (1.0, 1.0), (0.25, 0.9), (1.0, 0.0)])
