@@ -258,6 +258,23 @@ def main() -> int:
     ms_step64 = e0.elapsed_time(e1) / args.fp64_steps
     value64 = inter / (ms_step64 * 1e-3)
 
+    # ---- the same captured pass with the Balsara switch (not part of `value`):
+    #      the div/curl pass, the packing and the four-float4 force loop ------------
+    ctx_b = sph.Context(0, balsara=1, **params)
+    ctx_b.build_cells(pos, h0, d["box_first"], d["box_len"])
+    for _ in range(max(args.warmup, 1)):
+        step(ctx_b)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step(ctx_b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bal = e0.elapsed_time(e1) / args.steps
+    ctx_b.close()
+    bal = {"ms_per_step": ms_bal, "vs_pass": ms_bal / ms_step, "steps": args.steps,
+           "note": "the timed pass with sph_params.balsara = 1 on the same cells"}
+
     # ---- one leapfrog step (not part of `value`): half kick, drift, prediction,
     #      cell build, pass, half kick and the Courant step, on a context that
     #      records signal velocities --------------------------------------------------------
@@ -339,6 +356,7 @@ def main() -> int:
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
         "speedup_vs_fp64_plain": value / value64,
         "leapfrog": lf,
+        "balsara": bal,
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
         "autotune_top5": None if tuned is None else [
