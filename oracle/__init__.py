@@ -57,7 +57,7 @@ def _load():
         lib.orc_density.argtypes = [I64, P, P, D, D, I64, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.orc_density.restype = ctypes.c_int
         lib.orc_force.argtypes = [I64, P, P, P, P, P, P, P, D, D, D, I64, P,
-                                  P, P, P, P, P, P, P, P, P, ctypes.c_int, P]
+                                  P, P, P, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, P]
         lib.orc_force.restype = ctypes.c_int
         lib.orc_divcurl.argtypes = [I64, P, P, P, P, P, D, I64, P, P, P, P, ctypes.c_int, P]
         lib.orc_divcurl.restype = ctypes.c_int
@@ -105,13 +105,14 @@ def density(pos, mass, L: float = 1.0, n_ngb: float = N_NGB, targets=None, h_sta
 
 
 def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
-          alpha: float = ALPHA, targets=None, threads: int = 0, balsara=None) -> dict:
+          alpha: float = ALPHA, targets=None, threads: int = 0, balsara=None, form: int = 0) -> dict:
     """Acceleration, du/dt, their gross scales (sum of |pair term|), their
     kernel scales (pair terms at full kernel slope), the ordered pair count
     #{j != i: r < max(h_i, h_j)} and the signal velocity
     max(c_i, max_j (c_i + c_j - 3 min(v_ij . rhat, 0))) of the targets (all
     when None). ``balsara``: per-particle Balsara factors that scale the
-    viscosity of each pair by their mean (None: no switch)."""
+    viscosity of each pair by their mean (None: no switch). ``form`` 1: the
+    paper's Eq. 2 pressure sum in place of the grad-h terms (f unused)."""
     lib = _load()
     pos = _f64(pos, (-1, 3))
     n = pos.shape[0]
@@ -126,7 +127,8 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
                        float(alpha), 0 if tg is None else tg.size, _ptr(tg), _ptr(acc),
                        _ptr(out["dudt"]), _ptr(out["gross_a"]), _ptr(out["gross_u"]),
                        _ptr(out["scale_a"]), _ptr(out["scale_u"]), _ptr(npair), _ptr(out["vsig"]),
-                       _ptr(None if balsara is None else _f64(balsara)), int(threads), ctypes.byref(bad))
+                       _ptr(None if balsara is None else _f64(balsara)), int(form), int(threads),
+                       ctypes.byref(bad))
     if rc:
         raise RuntimeError("oracle force: %s (particle %d)" % (_ERR.get(rc, rc), bad.value))
     out["acc"] = acc
@@ -167,7 +169,8 @@ def balsara_factor(div, curl, u, h, gamma: float = GAMMA):
 
 
 def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: float = GAMMA,
-            alpha: float = ALPHA, h_start=None, threads: int = 0, balsara: bool = False) -> dict:
+            alpha: float = ALPHA, h_start=None, threads: int = 0, balsara: bool = False,
+            form: int = 0) -> dict:
     """Density then force for every particle of one periodic box, with the
     conservation sums of the box and the wall time of the two phases. With
     ``balsara`` the force applies the Balsara switch; the factors are
@@ -181,7 +184,8 @@ def run_box(pos, vel, mass, u, L: float = 1.0, n_ngb: float = N_NGB, gamma: floa
         dc = divcurl(pos, vel, mass, d["h"], d["rho"], L, threads=threads)
         B = balsara_factor(dc["div"], dc["curl"], u, d["h"], gamma)
         d.update(div=dc["div"], curl=dc["curl"], scale_dc=dc["scale"], balsara=B)
-    fo = force(pos, vel, mass, u, d["h"], d["rho"], d["f"], L, gamma, alpha, threads=threads, balsara=B)
+    fo = force(pos, vel, mass, u, d["h"], d["rho"], d["f"], L, gamma, alpha, threads=threads, balsara=B,
+               form=form)
     t2 = time.perf_counter()
     d.update(fo)
     d.update(conservation(mass, vel, fo["acc"], fo["dudt"]))
@@ -207,7 +211,7 @@ def conservation(mass, vel, acc, dudt) -> dict:
 
 
 def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPHA,
-        threads: int = 0, balsara: bool = False) -> dict:
+        threads: int = 0, balsara: bool = False, form: int = 0) -> dict:
     """Oracle over every box of a workload dict (see the ``workloads``
     package); per-particle outputs are concatenated in input order."""
     keys = ("h", "rho", "f", "nw", "nngb", "acc", "dudt", "gross_a", "gross_u", "scale_a", "scale_u",
@@ -226,7 +230,7 @@ def run(d: dict, n_ngb: float = N_NGB, gamma: float = GAMMA, alpha: float = ALPH
             continue
         r = run_box(d["pos"][s:e], d["vel"][s:e], d["mass"][s:e], d["u"][s:e],
                     float(d["box_len"][b]), n_ngb, gamma, alpha, h_start=d["h0"][s:e],
-                    threads=threads, balsara=balsara)
+                    threads=threads, balsara=balsara, form=form)
         for k in keys:
             parts[k].append(r[k])
         cons.append((r["mom"], r["energy"], r["mom_scale"], r["energy_scale"]))

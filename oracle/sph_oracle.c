@@ -29,6 +29,12 @@
  *              G = Phi_i D_i + Phi_j D_j + Pi_ij (D_i + D_j) / 2
  *              a_i    -= m_j G rhat
  *              du_i/dt += m_j (Phi_i D_i + Pi_ij (D_i + D_j) / 4) (v_ij . rhat)
+ *   Eq. 2 form (optional, form = 1) the paper's own illustration of the
+ *              pressure sum in place of the grad-h terms:
+ *              G = (P_i / rho_i^2 + P_j / rho_j^2) D_i + Pi_ij (D_i + D_j) / 2
+ *              and du_i/dt += m_j (P_i / rho_i^2 D_i + Pi_ij (D_i + D_j) / 4)
+ *              (v_ij . rhat), the first law with the Eq. 1 density's rate at
+ *              fixed h_i; f plays no part
  *   Balsara    (optional) Pi_ij is scaled by (B_i + B_j) / 2 with the
  *              Balsara factor B_k = |div v|_k / (|div v|_k + |curl v|_k +
  *              1e-4 c_k / h_k) (the Gadget-2 form; not in the paper), from
@@ -351,13 +357,14 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
  *                 paper's force form follows)
  *   balsara       per-particle Balsara factors B (see the header) scaling the
  *                 viscosity by (B_i + B_j) / 2; NULL: no switch
+ *   form          0: the grad-h Gadget-2 pressure terms; 1: the Eq. 2 form
  */
 int orc_force(int64_t n, const double *pos, const double *vel, const double *mass,
               const double *u, const double *h, const double *rho, const double *f,
               double L, double gamma, double alpha, int64_t n_targets, const int64_t *targets,
               double *acc_out, double *dudt_out, double *gross_a_out, double *gross_u_out,
               double *scale_a_out, double *scale_u_out, int64_t *npair_out, double *vsig_out,
-              const double *balsara, int nthreads, int64_t *bad)
+              const double *balsara, int form, int nthreads, int64_t *bad)
 {
     if (n <= 0 || !pos || !vel || !mass || !u || !h || !rho || !f || !acc_out || !dudt_out)
         return ORC_E_ARG;
@@ -402,7 +409,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             const double hi_ = h[i];
             const double Pi_ = (gamma - 1.0) * rho[i] * u[i];
             const double ci = sqrt(gamma * (gamma - 1.0) * u[i]);
-            const double Phii = f[i] * Pi_ / (rho[i] * rho[i]);
+            const double Phii = (form == 1 ? 1.0 : f[i]) * Pi_ / (rho[i] * rho[i]);
             double ax = 0, ay = 0, az = 0, du = 0, ga = 0, gu = 0, sa = 0, su = 0;
             double vsig = ci;
             int64_t np = 0;
@@ -419,7 +426,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                 double Dj = 8.0 / (ORC_PI * hj * hj * hj * hj) * dw_shape(r / hj);
                 double Pj = (gamma - 1.0) * rho[j] * u[j];
                 double cj = sqrt(gamma * (gamma - 1.0) * u[j]);
-                double Phij = f[j] * Pj / (rho[j] * rho[j]);
+                double Phij = (form == 1 ? 1.0 : f[j]) * Pj / (rho[j] * rho[j]);
                 double vr = (vel[3 * i + 0] - vel[3 * j + 0]) * ex +
                             (vel[3 * i + 1] - vel[3 * j + 1]) * ey +
                             (vel[3 * i + 2] - vel[3 * j + 2]) * ez;
@@ -429,7 +436,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                 double vs = ci + cj - 3.0 * wv;
                 if (vs > vsig) vsig = vs;
                 double Dbar = 0.5 * (Di + Dj);
-                double G = Phii * Di + Phij * Dj + Pv * Dbar;
+                double G = Phii * Di + Phij * (form == 1 ? Di : Dj) + Pv * Dbar;
                 double mj = mass[j];
                 ax -= mj * G * ex;
                 ay -= mj * G * ey;
@@ -440,7 +447,7 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                 gu += fabs(e);
                 double Dmi = r < hi_ ? 2.0 * 8.0 / (ORC_PI * hi_ * hi_ * hi_ * hi_) : 0.0;
                 double Dmj = r < hj ? 2.0 * 8.0 / (ORC_PI * hj * hj * hj * hj) : 0.0;
-                sa += mj * (fabs(Phii) * Dmi + fabs(Phij) * Dmj + fabs(Pv) * 0.5 * (Dmi + Dmj));
+                sa += mj * (fabs(Phii) * Dmi + fabs(Phij) * (form == 1 ? Dmi : Dmj) + fabs(Pv) * 0.5 * (Dmi + Dmj));
                 su += mj * (fabs(Phii) * Dmi + 0.25 * fabs(Pv) * (Dmi + Dmj)) * fabs(vr);
             }
             acc_out[3 * i + 0] = ax;
