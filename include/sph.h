@@ -124,6 +124,17 @@ typedef struct {
                              The Gadget-2 form of the switch; the paper has
                              no switch. Not in sph_force_f64 (SPH_E_ARG). One
                              more pass over the pairs (0: off) */
+    int32_t force_form;   /* pressure terms of the FP32 force: 0 = the grad-h
+                             Gadget-2 form (default); 1 = the sum the paper
+                             prints as its illustration (section 2, Eq. 2):
+                             a_i -= sum_j m_j (P_i / rho_i^2 + P_j / rho_j^2)
+                             grad_i W(r_ij, h_i), no grad-h factor, with
+                             du_i/dt += sum_j m_j P_i / rho_i^2 grad_i W(h_i)
+                             . v_ij and the same viscosity. Pairs with
+                             h_i <= r < h_j add only viscosity to i.
+                             interactions_force still counts the pairs
+                             inside max(h_i, h_j). Not with balsara, not in
+                             sph_force_f64 (SPH_E_ARG) */
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP

@@ -39,7 +39,8 @@ class sph_params(ctypes.Structure):
                 ("workspace_limit", ctypes.c_int64), ("timing", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("queue_batch", ctypes.c_int32),
                 ("tile_cap", ctypes.c_int32), ("cell_order", ctypes.c_int32),
-                ("signal_velocity", ctypes.c_int32), ("balsara", ctypes.c_int32)]
+                ("signal_velocity", ctypes.c_int32), ("balsara", ctypes.c_int32),
+                ("force_form", ctypes.c_int32)]
 
 
 class sph_stats(ctypes.Structure):

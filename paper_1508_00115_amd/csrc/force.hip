@@ -22,6 +22,11 @@
 // B = |div v| / (|div v| + |curl v| + 1e-4 c / h); a fourth float4 per
 // particle, (B, 0, 0, 0), then carries it into the force loop, which scales
 // each pair's viscosity by (B_i + B_j) / 2.
+//
+// sph_params.force_form = 1 swaps the grad-h pressure terms for the sum the
+// paper prints as its illustration (Eq. 2): (P_i / rho_i^2 + P_j / rho_j^2)
+// times the gradient of particle i's kernel, with no grad-h factor (the
+// prologue then stores Phi = P / rho^2).
 #include "common.h"
 #include "tiles.h"
 
@@ -35,8 +40,8 @@ constexpr int FSLOTS = FCAP / 4;  // a lane (4+ lanes per particle) tests at mos
 __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ jd,
                                  const float* __restrict__ hs, const float* __restrict__ rhos,
                                  const float* __restrict__ fs, const float* __restrict__ vel,
-                                 const float* __restrict__ u, float gamma, float4* __restrict__ jf,
-                                 int64_t* __restrict__ ctr)
+                                 const float* __restrict__ u, float gamma, int with_f,
+                                 float4* __restrict__ jf, int64_t* __restrict__ ctr)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -50,7 +55,7 @@ __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, c
         atomicAdd((unsigned long long*)&ctr_slot(ctr)[CT_BAD_INPUT], 1ull);
     const float P = (gamma - 1.0f) * rho * uu;
     const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
-    const float phi = fs[p] * P / (rho * rho);
+    const float phi = (with_f ? fs[p] : 1.0f) * P / (rho * rho);
     jf[3 * p + 0] = make_float4(x.x, x.y, x.z, h * h);
     jf[3 * p + 1] = make_float4(vx, vy, vz, x.w);
     jf[3 * p + 2] = make_float4(rho, phi, c, 1.0f / h);
@@ -118,8 +123,8 @@ __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
 
 // What a pass of k_force computes: the force; the force with the Balsara
 // switch (4 float4 per particle); the Balsara factors (3 float4 per particle,
-// no force, no counters).
-enum { FM_FORCE = 0, FM_BALSARA = 1, FM_DIVCURL = 2 };
+// no force, no counters); the force in the Eq. 2 form.
+enum { FM_FORCE = 0, FM_BALSARA = 1, FM_DIVCURL = 2, FM_EQ2 = 3 };
 
 // (B, 0, 0, 0) after the three float4 of each particle, for FM_BALSARA.
 __global__ void k_pack_balsara(int64_t n, const float4* __restrict__ jf, const float* __restrict__ bal,
@@ -262,7 +267,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     if constexpr (MODE == FM_BALSARA) visc *= 0.5f * (bal_i + sj[3 * FCAP + k].x);
                     if constexpr (VSIG) vmax = fmaxf(vmax, vsig_ij);
                     const float Dbar = 0.5f * (Di + Dj);
-                    const float G = fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
+                    const float G = MODE == FM_EQ2 ? fmaf(phi_i + p2.y, Di, visc * Dbar)
+                                                   : fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
                     const float mGr = p1.w * G * rinv;
                     ax = fmaf(-mGr, dx, ax);
                     ay = fmaf(-mGr, dy, ay);
@@ -374,13 +380,14 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
         fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);
     else if (c->prm.schedule == 1)
         fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);
-    if (prologue) {  // else the density kernels wrote the streams (ghost step fused)
+    const bool eq2 = c->prm.force_form == 1;
+    if (prologue || eq2) {  // else the density kernels wrote the streams (ghost step fused)
         k_force_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
                                                              static_cast<float4*>(c->jd.p),
                                                              static_cast<float*>(c->hs.p),
                                                              static_cast<float*>(c->rhos.p),
                                                              static_cast<float*>(c->fs.p), vel, u,
-                                                             (float)c->prm.gamma, jf, ctr);
+                                                             (float)c->prm.gamma, eq2 ? 0 : 1, jf, ctr);
         SPH_HIP(hipGetLastError());
     }
     ForceArgs A;
@@ -416,6 +423,11 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
             k_force<true, FM_BALSARA><<<grid, BS, 0, s>>>(A);
         else
             k_force<false, FM_BALSARA><<<grid, BS, 0, s>>>(A);
+    } else if (eq2) {
+        if (vsig)
+            k_force<true, FM_EQ2><<<grid, BS, 0, s>>>(A);
+        else
+            k_force<false, FM_EQ2><<<grid, BS, 0, s>>>(A);
     } else if (vsig) {
         k_force<true, FM_FORCE><<<grid, BS, 0, s>>>(A);
     } else {
@@ -433,6 +445,9 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
 
 double* force_buffers(sph_ctx* c, bool cons)
 {
+    SPH_REQUIRE(c->prm.force_form == 0 || c->prm.force_form == 1, SPH_E_ARG, "sph_params.force_form must be 0 or 1");
+    SPH_REQUIRE(!(c->prm.force_form == 1 && c->prm.balsara), SPH_E_ARG,
+                "the Eq. 2 force form (force_form = 1) has no Balsara switch");
     ensure<float4>(c, c->jf, 3 * c->n);
     if (c->prm.signal_velocity) ensure<float>(c, c->vsig_s, c->n);
     if (c->prm.balsara) {

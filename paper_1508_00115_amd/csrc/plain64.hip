@@ -425,6 +425,7 @@ void force_f64(sph_ctx* c, const double* vel, const double* u, double* acc, doub
     SPH_REQUIRE(c->built && c->density64_done, SPH_E_STATE, "sph_force_f64 needs a successful sph_density_f64");
     SPH_REQUIRE(vel && u && acc && dudt, SPH_E_ARG, "null vel/u/acc/dudt");
     SPH_REQUIRE(c->prm.balsara == 0, SPH_E_ARG, "sph_force_f64 has no Balsara switch (sph_params.balsara)");
+    SPH_REQUIRE(c->prm.force_form == 0, SPH_E_ARG, "sph_force_f64 has the grad-h form only (sph_params.force_form)");
     const int64_t n = c->n;
     int64_t* ctr = static_cast<int64_t*>(c->counters.p);
     double* m_s = static_cast<double*>(c->m64s.p);
