@@ -381,6 +381,10 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
 // Allocate what one density pass / force pass needs (never under capture).
 void density_buffers(sph_ctx* c);
 double* force_buffers(sph_ctx* c, bool cons);
+// Record on the host what a force pass leaves in the sorted arrays (signal
+// velocities, Balsara factors). Every path that runs the force loop calls it,
+// the replay of a captured pass included, which runs no host code of its own.
+void mark_force_outputs(sph_ctx* c);
 // Input-order Balsara factors of the last force pass into out (device, n).
 void balsara_unsort(sph_ctx* c, float* out, hipStream_t s);
 // Kernel launches only: no allocation, memset or host synchronisation, so

@@ -368,6 +368,12 @@ namespace sph {
 
 int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_cu, WorkSched& W);
 
+void mark_force_outputs(sph_ctx* c)
+{
+    c->vsig_valid = c->prm.signal_velocity != 0;
+    c->bal_valid = c->prm.balsara != 0 && c->prm.alpha_visc > 0;
+}
+
 void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt, double* cons_d,
                    bool clear_all, bool events, hipStream_t s, bool prologue)
 {
@@ -434,8 +440,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
         k_force<false, FM_FORCE><<<grid, BS, 0, s>>>(A);
     }
     SPH_HIP(hipGetLastError());
-    c->bal_valid = bal;
-    c->vsig_valid = vsig;
+    mark_force_outputs(c);
     if (events) ev_record(c, EV_FORCE_K1, s);
     if (cons_d) {
         k_cons_reduce<<<c->n_boxes, 256, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);

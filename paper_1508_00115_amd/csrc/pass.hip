@@ -116,6 +116,7 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
         c->tm.pass_call_ms = ev_ms(c, EV_DENS_C0, EV_FORCE_C1);
     }
     c->density_done = true;
+    mark_force_outputs(c);  // a replayed graph ran force_enqueue's kernels, not its host code
 }
 
 }  // namespace sph

@@ -274,3 +274,35 @@ def test_sedov_taylor_blast(gpu_lib, balsara):
     assert abs(r_peak - R) <= 2.0 * h_post
     assert prof.max() >= 2.0
     assert abs(E1 / E0 - 1.0) < 1e-2
+
+
+def test_flags_after_a_replayed_pass(gpu_lib):
+    """sph_pass replays its captured graph when the cells and every array are
+    unchanged, as after a short drift: the signal velocities and Balsara
+    factors that the replay leaves must still serve sph_timestep and
+    sph_get_balsara (a replay runs no host code of the force call)."""
+    import torch
+    d = workloads.lattice_box(16, [1508, 980], jitter=0.3, u=1.0, vel_sigma=0.3)
+    t = _tensors(d)
+    ctx = gpu_lib.Context(0, signal_velocity=1, balsara=1, h_margin=1.3)
+    try:
+        pos, vel, u, h = t["pos"].clone(), t["vel"].clone(), t["u"].clone(), t["h0"].clone()
+        ctx.build_cells(pos, h, d["box_first"], d["box_len"])
+        rho, f, nw, dudt = (torch.empty_like(h) for _ in range(4))
+        acc = torch.empty_like(vel)
+        kw = dict(rho=rho, f=f, nw=nw, acc=acc, dudt=dudt)
+        ctx.pass_(t["mass"], h, vel, u, **kw)
+        dt0 = ctx.timestep(0.3)
+        B0 = ctx.balsara().clone()
+        cells = ctx.build_info()["n_cells"]
+        for k in range(3):
+            print("replay", k, flush=True)
+            ctx.drift(1e-3 * dt0, vel, pos)  # far inside the drift budget: the cells stay
+            with pytest.raises(gpu_lib.SphError):
+                ctx.timestep(0.3)
+            ctx.pass_(t["mass"], h, vel, u, **kw)
+            assert ctx.timestep(0.3) == pytest.approx(dt0, rel=1e-2)
+            assert torch.allclose(ctx.balsara(), B0, atol=1e-2)
+        assert ctx.build_info()["n_cells"] == cells
+    finally:
+        ctx.close()
