@@ -385,11 +385,21 @@ class Context:
         """One kick-drift-kick step of length dt (every array in place): acc
         and dudt hold the rates at the start and hold those at the end on
         return. The sequence of sph.h (half kick, drift, prediction, pass,
-        half kick; the library keeps or rebuilds the cells); the predicted v
-        and u live in two scratch tensors."""
+        half kick; the library keeps or rebuilds the cells). The predicted v
+        and u, and rho and f when not given, live in
+        scratch tensors that the next step reuses (copy them to keep them):
+        with the same arrays every step, a step that keeps the cells replays
+        the captured pass instead of capturing it again."""
         import torch
-        vel_p = torch.empty_like(vel)
-        u_p = torch.empty_like(u)
+        key = (vel.shape, vel.dtype, vel.device, u.shape, u.dtype)
+        sc = getattr(self, "_step_scratch", None)
+        if sc is None or sc["key"] != key:
+            sc = {"key": key, "vel_p": torch.empty_like(vel), "u_p": torch.empty_like(u),
+                  "rho": torch.empty_like(u), "f": torch.empty_like(u)}
+            self._step_scratch = sc
+        vel_p, u_p = sc["vel_p"], sc["u_p"]
+        rho = sc["rho"] if rho is None else rho
+        f = sc["f"] if f is None else f
         self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
         self.drift(dt, vel, pos, stream=stream)
         self.kick(0.5 * dt, acc, dudt, vel, u, vel_p, u_p, stream=stream)
