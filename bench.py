@@ -1,22 +1,35 @@
 """Benchmark: particle-neighbour interactions per second of one SPH
-density + force pass on one MI355X.
+density + force pass on one MI355X, FP32 batched against the plain FP64 form.
 
-A step is one full pass of the hot path over the Sedov-blast set (64^3
-particles on a jittered lattice in a periodic unit box, u = 1e-5 except
-total energy 1 in the 32 central particles, v = 0): the density loop with
-the smoothing-length solve to convergence, then the ghost step and the force
-loop, issued as one sph_pass (a captured launch sequence with one host
-synchronisation). The cells are built once before timing (the build is
-reported separately), the starting h is restored before every step, and all
-inputs are resident in HBM. The roofline's kernel durations are averages
-over as many passes with the same kernels, launched uncaptured by a timing
-context with HIP events on their stream. The interaction count of a pass is
+A step is one full pass of the hot path over the batched set: 256
+independent periodic unit boxes of 20^3..40^3 particles (7,234,361 in all;
+box sizes log-uniform, seeded), each a jittered lattice with Gaussian
+velocities (sigma 0.1) and u = 1. One pass runs, for every self and pair
+cell task of every box in single launches captured in one HIP graph:
 
-    #{(i, j), j != i: r_ij < h_i}  +  #{(i, j), j != i: r_ij < max(h_i, h_j)}
+  - the density loop with the smoothing-length solve to convergence,
+  - the ghost step (folded into the density kernels),
+  - the force loop (acceleration and du/dt),
+  - the per-box FP64 momentum and energy rates (the conservation sums),
+
+issued as one sph_pass with one host synchronisation. Cell parameters come
+from the stored autotuning table for the set. The cells are built once before
+timing (the build is reported separately), the starting h is restored before
+every step inside the timed region, and all inputs are resident in HBM. The
+interaction count of a pass is
+
+    #{(i, j), j != i: r_ij < h_i}  +  #{(i, j), j != i: 0 < r_ij < max(h_i, h_j)}
 
 counted once per pass however many Newton sweeps h needed. The same pass in
-the plain FP64 form is timed beside it, and the FP64 CPU oracle on the
-host's cores.
+the plain FP64 form (one thread per particle, FP64 positions, with the same
+conservation sums) is timed on the same cells and reported beside it, with
+the speedup. The FP64 CPU oracle is timed on the host's cores, on the whole
+set with every core and on a seeded sample of boxes with one thread.
+
+The roofline's kernel durations are averages over as many passes with the
+same kernels, launched uncaptured by a timing context with HIP events on
+their stream. Extra keys report the Sedov blast (64^3) and the 2^24
+log-normal set the same way (their own stored cell parameters).
 
 Prints one JSON line.
 """
@@ -48,36 +61,60 @@ FLOP_REJECT = 8
 FLOP_DENSITY = 26
 FLOP_FORCE = 61
 
+WORKLOADS = {
+    # name: (generator, description, profile tag)
+    "batched": ("batched", "batched: 256 periodic unit boxes of 20^3..40^3 jittered-lattice particles "
+                           "(7,234,361 in all, sizes log-uniform), v ~ N(0, 0.1^2), u = 1, gamma = 5/3, "
+                           "cubic spline, 48 weighted neighbours; all boxes in one captured pass",
+                "batched"),
+    "sedov": ("sedov", "sedov blast 64^3: 262,144 equal-mass particles, jittered lattice, periodic unit "
+                       "box, u=1e-5 with total energy 1 in the 32 central particles, v=0", "sedov64"),
+    "large": ("lognormal", "log-normal 256^3: 16,777,216 particles from a log-normal density field "
+                           "(P(k) ~ k^-2, sigma_ln 1.5), velocities from the same field, u=1", "large"),
+    "clustered": ("clustered", "clustered: 2^19 uniform + 64 Plummer spheres x 8192, periodic unit box",
+                  "clustered"),
+    "small": ("small", "small 16^3 jittered lattice, u=1, v=0", "small"),
+}
 
-def _workload(name: str):
+
+def _workload(name: str) -> tuple:
     import workloads
-    if name == "sedov":
-        return workloads.sedov(), ("sedov blast 64^3: 262,144 equal-mass particles, jittered lattice, "
-                                   "periodic unit box, u=1e-5 with total energy 1 in the 32 central "
-                                   "particles, v=0, gamma=5/3, cubic spline, 48 weighted neighbours")
-    if name == "small":
-        return workloads.small(), "small 16^3 jittered lattice, u=1, v=0"
-    if name == "batched":
-        return workloads.batched(), "256 periodic boxes of 20^3..40^3 jittered-lattice particles, v~N(0,0.1)"
-    if name == "clustered":
-        return workloads.clustered(), "2^19 uniform + 64 Plummer spheres x 8192, periodic unit box"
-    if name == "large":
-        return workloads.lognormal(), "256^3 particles from a log-normal density field"
-    raise SystemExit("unknown workload " + name)
+    if name not in WORKLOADS:
+        raise SystemExit("unknown workload " + name)
+    gen, desc, tag = WORKLOADS[name]
+    return getattr(workloads, gen)(), desc, tag
 
 
-def cpu_baseline(d: dict, min_seconds: float) -> dict:
+def cpu_baseline(d: dict, min_seconds: float, one_thread_seconds: float) -> dict:
+    """The FP64 oracle (untuned) on the host: every box with every core, then
+    a seeded sample of boxes with one thread (boxes are independent, so a
+    sample of boxes is a sample of the same work)."""
     import oracle
+    cores = oracle.max_threads()
     reps, t_tot, inter = 0, 0.0, 0
-    while reps < 1 or (t_tot < min_seconds and reps < 200):
-        r = oracle.run(d)
+    while reps < 1 or (t_tot < min_seconds and reps < 50):
+        r = oracle.run(d, threads=cores)
         t_tot += r["t_density"] + r["t_force"]
         inter = int(r["nngb"].sum() + r["npair"].sum())
         reps += 1
-    return {"value": inter * reps / t_tot, "unit": "interactions/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": "the full workload (every particle, density with h solved to 1e-13 + force), "
-                      "%d repetition(s), %.1f s" % (reps, t_tot)}
+    out = {"value": inter * reps / t_tot, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+           "sample": "the whole workload (every particle of every box: density with h solved to "
+                     "1e-13, then force), %d repetition(s), %.1f s on %d threads" % (reps, t_tot, cores)}
+    nb = len(d["box_len"])
+    order = np.random.default_rng([1508, 3, 1000]).permutation(nb)
+    t1, i1, boxes = 0.0, 0, 0
+    import workloads
+    for b in order:
+        r = oracle.run(workloads.box_slice(d, int(b)), threads=1)
+        t1 += r["t_density"] + r["t_force"]
+        i1 += int(r["nngb"].sum() + r["npair"].sum())
+        boxes += 1
+        if t1 >= one_thread_seconds:
+            break
+    out["value_1thread"] = i1 / t1
+    out["sample_1thread"] = "%d of the %d boxes (seeded order), %.1f s on 1 thread" % (boxes, nb, t1)
+    oracle.run(workloads.box_slice(d, int(order[0])), threads=cores)  # leave the library at all cores
+    return out
 
 
 KERNEL_SOURCES = {
@@ -95,12 +132,13 @@ def _kernel_hash(kname: str) -> str:
     return h.hexdigest()
 
 
-def _traffic(kname: str, params: dict):
-    """HBM bytes per launch of kernel kname from its committed counter profile
-    (FETCH_SIZE and WRITE_SIZE, each divided by the factor the same counter
-    reads for a device copy of known size), or None when there is no profile,
-    or the kernel sources or cell parameters changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "%s_sedov64_traffic.txt" % kname)
+def _traffic(kname: str, tag: str, params: dict):
+    """HBM bytes per launch of kernel kname on workload `tag` from its
+    committed counter profile (FETCH_SIZE and WRITE_SIZE, each divided by the
+    factor the same counter reads for a device copy of known size), or None
+    when there is no profile, or the kernel sources or cell parameters
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kname, tag))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -119,17 +157,162 @@ def _traffic(kname: str, params: dict):
     return {"bytes": fetch + write}
 
 
+def _params_for(d: dict, args) -> tuple:
+    if args.params:
+        return json.loads(args.params), "--params", None
+    if args.no_tune:
+        return {}, "library defaults", None
+    from paper_1508_00115_amd import tune
+    tuned = None if args.tune else tune.lookup(d)
+    src = "stored tuning table"
+    if tuned is None:
+        tuned = tune.autotune(d, 0)
+        src = "autotuned in this run"
+        if args.tune_out:
+            tune.save(d, tuned, args.tune_out)
+    return tuned["best"], src, tuned
+
+
+class Inputs:
+    """A workload resident on the GPU with its output buffers."""
+
+    def __init__(self, d: dict, dev):
+        import torch
+        self.d = d
+        self.n = d["pos"].shape[0]
+        self.pos = torch.from_numpy(d["pos"]).to(dev)
+        self.h0 = torch.from_numpy(d["h0"]).to(dev)
+        self.mass = torch.from_numpy(d["mass"]).to(dev)
+        self.vel = torch.from_numpy(d["vel"]).to(dev)
+        self.u = torch.from_numpy(d["u"]).to(dev)
+        self.h = self.h0.clone()
+        self.rho = torch.empty_like(self.h)
+        self.f = torch.empty_like(self.h)
+        self.acc = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        self.dudt = torch.empty_like(self.h)
+
+    def context(self, sph, **params):
+        ctx = sph.Context(0, **params)
+        ctx.build_cells(self.pos, self.h0, self.d["box_first"], self.d["box_len"])
+        return ctx
+
+    def step(self, ctx, cons: bool = True) -> dict:
+        self.h.copy_(self.h0)
+        return ctx.pass_(self.mass, self.h, self.vel, self.u, rho=self.rho, f=self.f, acc=self.acc,
+                         dudt=self.dudt, cons=cons)["stats"]
+
+
+def time_pass(inp: Inputs, ctx, steps: int, warmup: int, stream) -> tuple:
+    """HIP events on the stream around `steps` captured passes (after
+    `warmup`): ms per step and the stats of the last pass."""
+    import torch
+    for _ in range(warmup):
+        inp.step(ctx)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        sp = inp.step(ctx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, sp
+
+
+def kernel_times(inp: Inputs, sph, params: dict, steps: int, warmup: int) -> dict:
+    """The same passes (the same kernels, the ghost step in the density
+    kernels, the conservation sums) launched uncaptured by a timing context,
+    with HIP events on the stream they run on; averages over `steps`."""
+    import torch
+    ctx_t = inp.context(sph, timing=1, **params)
+    build_ms = ctx_t.timings()["build_ms"]
+    for _ in range(max(warmup, 1)):
+        inp.step(ctx_t)
+    dk, dr, fk, pc = [], [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = inp.step(ctx_t)
+        t = ctx_t.timings()
+        dk.append(t["density_kernel_ms"] - t["density_rescan_ms"])
+        dr.append(t["density_rescan_ms"])
+        fk.append(t["force_kernel_ms"])
+        pc.append(t["pass_call_ms"])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ctx_t.close()
+    return {"density_kernel": float(np.mean(dk)), "density_rescan_kernel": float(np.mean(dr)),
+            "force_kernel": float(np.mean(fk)), "pass_gpu": float(np.mean(pc)), "build": build_ms,
+            "ms_per_step_uncaptured_with_events": wall, "stats": st}
+
+
+def roofline(stats: dict, km: dict, tag: str, params: dict) -> dict:
+    """Algorithmic FP32 work of the slower hot kernel over its average
+    duration, against the FP32 vector peak."""
+    dens_ms, force_ms = km["density_kernel"], km["force_kernel"]
+    dens_alg = FLOP_DENSITY * stats["sweep_interactions_density"] + \
+        FLOP_REJECT * (stats["candidates_density"] - stats["sweep_interactions_density"])
+    force_alg = FLOP_FORCE * stats["interactions_force"] + \
+        FLOP_REJECT * (stats["candidates_force"] - stats["interactions_force"])
+    if dens_ms >= force_ms:
+        kname, kms, alg = "k_density", dens_ms, dens_alg
+    else:
+        kname, kms, alg = "k_force", force_ms, force_alg
+    achieved = alg / (kms * 1e-3) / 1e12
+    traffic = _traffic(kname, tag, params)
+    other = {"k_density": (dens_alg, dens_ms), "k_force": (force_alg, force_ms)}
+    return {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None if traffic is None else traffic["bytes"],
+            "traffic_unit": "bytes per launch (HBM, from hardware counters)",
+            "traffic_gbs": None if traffic is None else traffic["bytes"] / (kms * 1e-3) / 1e9,
+            "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg,
+            "per_kernel": {k: {"algorithmic_flop_per_launch": a, "avg_kernel_ms": ms,
+                               "frac": a / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+                           for k, (a, ms) in other.items()},
+            "useful_tflops": (FLOP_DENSITY * stats["sweep_interactions_density"] +
+                              FLOP_FORCE * stats["interactions_force"]) / ((dens_ms + force_ms) * 1e-3) / 1e12}
+
+
+def extra_set(name: str, sph, args, stream, dev) -> dict:
+    """The captured pass on another workload, with its kernel times."""
+    import torch
+    d, desc, tag = _workload(name)
+    params, src, _ = _params_for(d, args)
+    inp = Inputs(d, dev)
+    ctx = inp.context(sph, **params)
+    ms, sp = time_pass(inp, ctx, args.extra_steps, 1, stream)
+    ctx.close()
+    km = kernel_times(inp, sph, params, args.extra_steps, 1)
+    inter = sp["interactions_density"] + sp["interactions_force"]
+    out = {"workload": desc, "particles": inp.n, "value": inter / (ms * 1e-3), "unit": "interactions/s",
+           "ms_per_step": ms, "steps": args.extra_steps, "interactions_per_pass": inter,
+           "kernels_ms": {k: v for k, v in km.items() if k != "stats"},
+           "roofline": roofline(sp, km, tag, params), "sweeps": sp["sweeps"],
+           "candidates_per_interaction_density": sp["candidates_density"] / max(1, sp["interactions_density"]),
+           "candidates_per_interaction_force": sp["candidates_force"] / max(1, sp["interactions_force"]),
+           "cell_params": params or "library defaults", "cell_params_from": src}
+    del inp
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sedov")
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="least oracle time on every core (whole set, repeated)")
+    ap.add_argument("--cpu-1thread-seconds", type=float, default=12.0,
+                    help="oracle time on one thread (a seeded sample of boxes)")
+    ap.add_argument("--extra", default="sedov,large",
+                    help="other workloads timed after the headline, comma separated ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--leapfrog-steps", type=int, default=10,
-                    help="leapfrog steps timed after the pass (0: none)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+                    help="leapfrog steps timed on the Sedov blast (0: none)")
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of the autotuner")
     ap.add_argument("--tune", action="store_true", help="re-run the autotuner instead of the stored table")
     ap.add_argument("--tune-out", default=None, help="merge a fresh tuning result into this JSON file")
@@ -158,86 +341,26 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    d, desc = _workload(args.workload)
-    n = d["pos"].shape[0]
+    d, desc, tag = _workload(args.workload)
+    params, tune_source, tuned = _params_for(d, args)
     stream = torch.cuda.current_stream(dev)
-    pos = torch.from_numpy(d["pos"]).to(dev)
-    h0 = torch.from_numpy(d["h0"]).to(dev)
-    mass = torch.from_numpy(d["mass"]).to(dev)
-    vel = torch.from_numpy(d["vel"]).to(dev)
-    u = torch.from_numpy(d["u"]).to(dev)
-    h = h0.clone()
-    rho = torch.empty_like(h)
-    f = torch.empty_like(h)
-    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
-    dudt = torch.empty_like(h)
+    inp = Inputs(d, dev)
+    n = inp.n
 
-    tuned = None
-    params = {}
-    tune_source = "library defaults"
-    if args.params:
-        params = json.loads(args.params)
-        tune_source = "--params"
-    elif not args.no_tune:
-        from paper_1508_00115_amd import tune
-        tuned = None if args.tune else tune.lookup(d)
-        tune_source = "stored tuning table"
-        if tuned is None:
-            tuned = tune.autotune(d, 0)
-            tune_source = "autotuned in this run"
-            if args.tune_out:
-                tune.save(d, tuned, args.tune_out)
-        params = tuned["best"]
-    # the timed region: density + force as one captured launch sequence (the
-    # production configuration)
-    ctx = sph.Context(0, **params)
-    ctx.build_cells(pos, h0, d["box_first"], d["box_len"])
-
-    def step(c):
-        h.copy_(h0)
-        return c.pass_(mass, h, vel, u, rho=rho, f=f, acc=acc, dudt=dudt)["stats"]
-
-    for _ in range(args.warmup):
-        step(ctx)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        sp = step(ctx)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    # ---- the timed region: density + force + conservation sums as one
+    #      captured launch sequence (the production configuration) ----------------------
+    ctx = inp.context(sph, **params)
+    ms_step, sp = time_pass(inp, ctx, args.steps, args.warmup, stream)
     inter = sp["interactions_density"] + sp["interactions_force"]
     value = inter / (ms_step * 1e-3)
 
-    # kernel durations: the same passes (the same kernels, the ghost step in
-    # the density kernels) launched uncaptured by a timing context, with HIP
-    # events on the stream they run on; averages over as many steps
-    ctx_t = sph.Context(0, timing=1, **params)
-    ctx_t.build_cells(pos, h0, d["box_first"], d["box_len"])
-    build_ms = ctx_t.timings()["build_ms"]
-    for _ in range(max(args.warmup, 1)):
-        step(ctx_t)
-    dk, dr, fk, pc = [], [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st_t = step(ctx_t)
-        t = ctx_t.timings()
-        dk.append(t["density_kernel_ms"] - t["density_rescan_ms"])
-        dr.append(t["density_rescan_ms"])
-        fk.append(t["force_kernel_ms"])
-        pc.append(t["pass_call_ms"])
-    torch.cuda.synchronize()
-    ms_step_uncaptured = (time.perf_counter() - t0) * 1e3 / args.steps
-    ctx_t.close()
-    assert st_t["interactions_density"] == sp["interactions_density"]
-    assert st_t["interactions_force"] == sp["interactions_force"]
-    sd = sf = sp
+    km = kernel_times(inp, sph, params, args.steps, args.warmup)
+    assert km["stats"]["interactions_density"] == sp["interactions_density"]
+    assert km["stats"]["interactions_force"] == sp["interactions_force"]
 
-    # ---- plain FP64 form on the same cells -------------------------------------------
-    mass64, vel64, u64 = mass.double(), vel.double(), u.double()
-    h0_64 = h0.double()
+    # ---- plain FP64 form on the same cells, with the conservation sums -------------------
+    mass64, vel64, u64 = inp.mass.double(), inp.vel.double(), inp.u.double()
+    h0_64 = inp.h0.double()
     h64 = h0_64.clone()
     rho64, f64 = torch.empty_like(h64), torch.empty_like(h64)
     acc64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -245,81 +368,32 @@ def main() -> int:
 
     def step64():
         h64.copy_(h0_64)
-        ctx.density_f64(mass64, h64, rho64, f64)
-        ctx.force_f64(vel64, u64, acc64, dudt64, cons=False)
+        sd = ctx.density_f64(mass64, h64, rho64, f64)["stats"]
+        return sd, ctx.force_f64(vel64, u64, acc64, dudt64, cons=True)["stats"]
 
     step64()
     torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.fp64_steps):
-        step64()
+        sd64, sf64 = step64()
     e1.record(stream)
     torch.cuda.synchronize()
     ms_step64 = e0.elapsed_time(e1) / args.fp64_steps
-    value64 = inter / (ms_step64 * 1e-3)
+    inter64 = sd64["interactions_density"] + sf64["interactions_force"]
+    value64 = inter64 / (ms_step64 * 1e-3)
+    del mass64, vel64, u64, h0_64, h64, rho64, f64, acc64, dudt64
 
     # ---- the same captured pass with the Balsara switch (not part of `value`):
     #      the div/curl pass, the packing and the four-float4 force loop ------------
-    ctx_b = sph.Context(0, balsara=1, **params)
-    ctx_b.build_cells(pos, h0, d["box_first"], d["box_len"])
-    for _ in range(max(args.warmup, 1)):
-        step(ctx_b)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step(ctx_b)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_bal = e0.elapsed_time(e1) / args.steps
+    ctx_b = inp.context(sph, balsara=1, **params)
+    ms_bal, _ = time_pass(inp, ctx_b, args.steps, max(args.warmup, 1), stream)
     ctx_b.close()
     bal = {"ms_per_step": ms_bal, "vs_pass": ms_bal / ms_step, "steps": args.steps,
            "note": "the timed pass with sph_params.balsara = 1 on the same cells"}
 
-    # ---- one leapfrog step (not part of `value`): half kick, drift, prediction,
-    #      cell build, pass, half kick and the Courant step, on a context that
-    #      records signal velocities --------------------------------------------------------
-    lf = None
-    if args.leapfrog_steps > 0:
-        ctx_l = sph.Context(0, signal_velocity=1, **params)
-        pos_l, vel_l, u_l, h_l = pos.clone(), vel.clone(), u.clone(), h0.clone()
-        ctx_l.build_cells(pos_l, h_l, d["box_first"], d["box_len"])
-        rl = ctx_l.pass_(mass, h_l, vel_l, u_l)
-        acc_l, dudt_l, rho_l = rl["acc"], rl["dudt"], rl["rho"]
-
-        def leap():
-            dt = ctx_l.timestep(0.3)
-            ctx_l.step(dt, pos_l, mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
-            return dt
-
-        leap()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.leapfrog_steps):
-            dt_last = leap()
-        torch.cuda.synchronize()
-        lf = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
-              "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
-              "build_ms": ctx_l.timings()["build_ms"],
-              "note": "wall time per step from the host (kick, drift, kick, pass with a cell rebuild "
-                      "when the drift bound requires one, kick, time step), after one untimed step"}
-        ctx_l.close()
-
-    # ---- roofline of the dominant kernel ------------------------------------------------
-    dens_ms = float(np.mean(dk))  # the list kernel alone (the re-scan kernel is timed apart)
-    force_ms = float(np.mean(fk))
-    dens_alg = FLOP_DENSITY * sd["sweep_interactions_density"] + \
-        FLOP_REJECT * (sd["candidates_density"] - sd["sweep_interactions_density"])
-    force_alg = FLOP_FORCE * sf["interactions_force"] + \
-        FLOP_REJECT * (sf["candidates_force"] - sf["interactions_force"])
-    if dens_ms >= force_ms:
-        kname, kms, alg = "k_density", dens_ms, dens_alg
-    else:
-        kname, kms, alg = "k_force", force_ms, force_alg
-    achieved = alg / (kms * 1e-3) / 1e12
-    traffic = _traffic(kname, params)
-    useful = (FLOP_DENSITY * sd["sweep_interactions_density"] + FLOP_FORCE * sf["interactions_force"]) / \
-        ((dens_ms + force_ms) * 1e-3) / 1e12
-
+    rl = roofline(sp, km, tag, params)
     out = {
         "metric": METRIC,
         "value": value,
@@ -333,29 +407,27 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "particles": n, "interactions_per_pass": inter,
-                   "density_interactions": sd["interactions_density"],
-                   "force_interactions": sf["interactions_force"], "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None if traffic is None else traffic["bytes"],
-                     "traffic_unit": "bytes per launch (HBM, from hardware counters)",
-                     "traffic_gbs": None if traffic is None else traffic["bytes"] / (kms * 1e-3) / 1e9,
-                     "avg_kernel_ms": kms, "algorithmic_flop_per_launch": alg},
-        "ms_per_step_uncaptured_with_events": ms_step_uncaptured,
-        "kernels_ms": {"density_kernel": dens_ms, "density_rescan_kernel": float(np.mean(dr)),
-                       "force_kernel": force_ms, "pass_gpu": float(np.mean(pc)), "build": build_ms},
-        "useful_tflops": useful,
-        "density": {"sweeps": sd["sweeps"], "rebuilds": sd["rebuilds"],
-                    "candidates": sd["candidates_density"],
-                    "sweep_interactions": sd["sweep_interactions_density"],
-                    "candidates_per_interaction": sd["candidates_density"] / max(1, sd["interactions_density"]),
-                    "cells": sd["n_cells"], "cell_pairs": sd["n_pairs"]},
-        "force": {"candidates": sf["candidates_force"],
-                  "candidates_per_interaction": sf["candidates_force"] / max(1, sf["interactions_force"])},
-        "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps},
+        "config": {"workload": desc, "particles": n, "boxes": len(d["box_len"]),
+                   "interactions_per_pass": inter,
+                   "density_interactions": sp["interactions_density"],
+                   "force_interactions": sp["interactions_force"],
+                   "conservation_sums_in_timed_pass": True, "parallelism": "single GPU"},
+        "roofline": rl,
+        "ms_per_step_uncaptured_with_events": km["ms_per_step_uncaptured_with_events"],
+        "kernels_ms": {k: v for k, v in km.items() if k not in ("stats", "ms_per_step_uncaptured_with_events")},
+        "useful_tflops": rl["useful_tflops"],
+        "density": {"sweeps": sp["sweeps"], "rebuilds": sp["rebuilds"],
+                    "candidates": sp["candidates_density"],
+                    "sweep_interactions": sp["sweep_interactions_density"],
+                    "candidates_per_interaction": sp["candidates_density"] / max(1, sp["interactions_density"]),
+                    "rescanned": sp["rescanned_density"],
+                    "cells": sp["n_cells"], "cell_pairs": sp["n_pairs"]},
+        "force": {"candidates": sp["candidates_force"],
+                  "candidates_per_interaction": sp["candidates_force"] / max(1, sp["interactions_force"])},
+        "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps,
+                       "interactions_per_pass": inter64,
+                       "note": "sph_density_f64 + sph_force_f64 with the conservation sums, same cells"},
         "speedup_vs_fp64_plain": value / value64,
-        "leapfrog": lf,
         "balsara": bal,
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
@@ -364,9 +436,49 @@ def main() -> int:
             for t in sorted((t for t in tuned["table"] if t["ms"] is not None), key=lambda t: t["ms"])[:5]],
         "autotune_settings": None if tuned is None else len(tuned["table"]),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
     ctx.close()
+    del inp
+    torch.cuda.empty_cache()
+
+    # ---- one leapfrog step on the Sedov blast (not part of `value`): half kick,
+    #      drift, prediction, cell build when needed, pass, half kick and the
+    #      Courant step, on a context that records signal velocities -----------------
+    if args.leapfrog_steps > 0:
+        ds, _, _ = _workload("sedov")
+        params_s, _, _ = _params_for(ds, args)
+        li = Inputs(ds, dev)
+        ctx_l = sph.Context(0, signal_velocity=1, **params_s)
+        pos_l, vel_l, u_l, h_l = li.pos.clone(), li.vel.clone(), li.u.clone(), li.h0.clone()
+        ctx_l.build_cells(pos_l, h_l, ds["box_first"], ds["box_len"])
+        r0 = ctx_l.pass_(li.mass, h_l, vel_l, u_l)
+        acc_l, dudt_l, rho_l = r0["acc"], r0["dudt"], r0["rho"]
+
+        def leap():
+            dt = ctx_l.timestep(0.3)
+            ctx_l.step(dt, pos_l, li.mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
+            return dt
+
+        leap()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.leapfrog_steps):
+            dt_last = leap()
+        torch.cuda.synchronize()
+        out["leapfrog"] = {
+            "workload": "sedov blast 64^3", "ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
+            "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
+            "build_ms": ctx_l.timings()["build_ms"],
+            "note": "wall time per step from the host (kick, drift, kick, pass with a cell rebuild "
+                    "when the drift bound requires one, kick, time step), after one untimed step"}
+        ctx_l.close()
+        del li
+        torch.cuda.empty_cache()
+
+    for name in [x for x in args.extra.split(",") if x and x != args.workload]:
+        out[name] = extra_set(name, sph, args, stream, dev)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, args.cpu_1thread_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -157,7 +157,10 @@ typedef struct {
     int32_t rebuilds;           /* cell rebuilds forced by h outgrowing its cell */
     int64_t unconverged;        /* particles whose h did not converge */
     int64_t interactions_density; /* #{(i, j), j != i : r_ij < h_i} at the final h */
-    int64_t interactions_force;   /* #{(i, j), j != i : r_ij < max(h_i, h_j)} */
+    int64_t interactions_force;   /* #{(i, j), j != i : 0 < r_ij < max(h_i, h_j)}: the
+                                     pairs that carry a force term (a coincident
+                                     pair has no direction and adds nothing; it
+                                     still counts in interactions_density) */
     int64_t candidates_density; /* (i, j) candidate pairs tested, summed over sweeps */
     int64_t candidates_force;   /* (i, j) candidate pairs tested by the force loop
                                    (candidates staged within reach of i's cell) */

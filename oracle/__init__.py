@@ -30,7 +30,8 @@ ALPHA = 0.8
 N_NGB = 48.0
 
 _ERR = {1: "bad argument", 2: "out of memory", 3: "smoothing length reaches L/2",
-        4: "root finder did not converge"}
+        4: "root finder did not converge",
+        5: "a neighbour inside the target's h has no smoothing length (sample not closed)"}
 
 _lib = None
 
@@ -108,7 +109,7 @@ def force(pos, vel, mass, u, h, rho, f, L: float = 1.0, gamma: float = GAMMA,
           alpha: float = ALPHA, targets=None, threads: int = 0, balsara=None, form: int = 0) -> dict:
     """Acceleration, du/dt, their gross scales (sum of |pair term|), their
     kernel scales (pair terms at full kernel slope), the ordered pair count
-    #{j != i: r < max(h_i, h_j)} and the signal velocity
+    #{j != i: 0 < r < max(h_i, h_j)} and the signal velocity
     max(c_i, max_j (c_i + c_j - 3 min(v_ij . rhat, 0))) of the targets (all
     when None). ``balsara``: per-particle Balsara factors that scale the
     viscosity of each pair by their mean (None: no switch). ``form`` 1: the

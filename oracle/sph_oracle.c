@@ -66,7 +66,7 @@
 
 #define ORC_PI 3.14159265358979323846
 
-enum { ORC_OK = 0, ORC_E_ARG = 1, ORC_E_NOMEM = 2, ORC_E_RADIUS = 3, ORC_E_ROOT = 4 };
+enum { ORC_OK = 0, ORC_E_ARG = 1, ORC_E_NOMEM = 2, ORC_E_RADIUS = 3, ORC_E_ROOT = 4, ORC_E_MISSING = 5 };
 
 /* ---- cubic-spline kernel (shape only, support 1) ---------------------- */
 
@@ -340,8 +340,12 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
 
 /*
  * Acceleration and du/dt of the listed targets (all when targets == NULL).
- * h, rho, f must be valid for every particle within reach of a target; a
- * particle with h <= 0 is treated as unknown and skipped.
+ * h, rho, f must be valid for every particle within reach of a target. A
+ * particle with h <= 0 (or NaN) is treated as unknown: it is skipped when it
+ * lies at or beyond h_i of the target (it then pairs only through its own h,
+ * which the caller vouches is not the case), and it is an error
+ * (ORC_E_MISSING, *bad = the target) when it lies inside h_i, where it pairs
+ * whatever its h.
  *   gross_a_out   sum_j |m_j G|, the scale the acceleration error is judged by
  *   gross_u_out   sum_j |m_j (Phi_i D_i + Pi Dbar / 2)(v_ij . rhat)|
  *   scale_a_out   sum_j m_j (|Phi_i| Dm_i + |Phi_j| Dm_j + |Pi| (Dm_i + Dm_j) / 2), where
@@ -350,7 +354,9 @@ int orc_density(int64_t n, const double *pos, const double *mass, double L, doub
  *                 shrink where w'(q) -> 0 at the kernel edge, so errors are judged
  *                 against a scale that rounding in q cannot exceed.
  *   scale_u_out   sum_j m_j (|Phi_i| Dm_i + |Pi| (Dm_i + Dm_j) / 4) |v_ij . rhat|
- *   npair_out     #{j != i : r_ij < max(h_i, h_j)}
+ *   npair_out     #{j != i : 0 < r_ij < max(h_i, h_j)}: the pairs that carry a
+ *                 force term (a coincident pair has no direction and adds
+ *                 nothing, so it is not a force interaction)
  *   vsig_out      signal velocity max(c_i, max_j (c_i + c_j - 3 w_ij)) over the
  *                 pairs with 0 < r_ij < max(h_i, h_j): the speed in the Courant
  *                 condition of the time step (the Gadget-2 choice that the
@@ -413,14 +419,19 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
             double ax = 0, ay = 0, az = 0, du = 0, ga = 0, gu = 0, sa = 0, su = 0;
             double vsig = ci;
             int64_t np = 0;
+            int missing = 0;
             for (int64_t k = 0; k < c.n; ++k) {
                 int64_t j = c.j[k];
                 double r = c.r[k];
-                if (j == i || !(h[j] > 0)) continue;
+                if (j == i) continue;
+                if (!(h[j] > 0)) {
+                    if (r < hi_) { missing = 1; break; } /* a partner whose h is unknown */
+                    continue;
+                }
                 double hj = h[j];
                 if (!(r < hi_ || r < hj)) continue;
-                np += 1;
                 if (r == 0.0) continue; /* coincident: no direction, no force */
+                np += 1;
                 double ex = c.dx[3 * k + 0] / r, ey = c.dx[3 * k + 1] / r, ez = c.dx[3 * k + 2] / r;
                 double Di = 8.0 / (ORC_PI * hi_ * hi_ * hi_ * hi_) * dw_shape(r / hi_);
                 double Dj = 8.0 / (ORC_PI * hj * hj * hj * hj) * dw_shape(r / hj);
@@ -449,6 +460,11 @@ int orc_force(int64_t n, const double *pos, const double *vel, const double *mas
                 double Dmj = r < hj ? 2.0 * 8.0 / (ORC_PI * hj * hj * hj * hj) : 0.0;
                 sa += mj * (fabs(Phii) * Dmi + fabs(Phij) * (form == 1 ? Dmi : Dmj) + fabs(Pv) * 0.5 * (Dmi + Dmj));
                 su += mj * (fabs(Phii) * Dmi + 0.25 * fabs(Pv) * (Dmi + Dmj)) * fabs(vr);
+            }
+            if (missing) {
+#pragma omp critical
+                { if (status == ORC_OK) { status = ORC_E_MISSING; *bad = i; } }
+                continue;
             }
             acc_out[3 * i + 0] = ax;
             acc_out[3 * i + 1] = ay;

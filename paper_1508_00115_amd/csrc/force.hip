@@ -440,7 +440,6 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
         k_force<false, FM_FORCE><<<grid, BS, 0, s>>>(A);
     }
     SPH_HIP(hipGetLastError());
-    mark_force_outputs(c);
     if (events) ev_record(c, EV_FORCE_K1, s);
     if (cons_d) {
         k_cons_reduce<<<c->n_boxes, 256, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);
@@ -470,6 +469,9 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     SPH_REQUIRE(c->built && c->density_done, SPH_E_STATE, "sph_force needs a successful sph_density first");
     SPH_REQUIRE(vel && u && acc && dudt, SPH_E_ARG, "null vel/u/acc/dudt");
     double* cons_d = force_buffers(c, cons != nullptr);
+    // the sorted signal velocities and Balsara factors are rewritten below:
+    // they are valid again only once this pass has succeeded
+    c->vsig_valid = c->bal_valid = false;
     ev_record(c, EV_FORCE_C0, s);
     force_enqueue(c, vel, u, acc, dudt, cons_d, true, true, s);
     if (cons || st) {
@@ -483,6 +485,7 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
             st->n_pairs = c->n_pairs;
         }
     }
+    mark_force_outputs(c);
     ev_record(c, EV_FORCE_C1, s);
     if (c->prm.timing) {
         c->tm.force_kernel_ms = ev_ms(c, EV_FORCE_K0, EV_FORCE_K1);

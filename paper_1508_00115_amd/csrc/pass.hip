@@ -35,6 +35,9 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
     SPH_REQUIRE(mass && h && rho && f && vel && u && acc && dudt, SPH_E_ARG, "null input or output");
     check_drift(c, h, s);
     c->density_done = false;
+    // the pass rewrites the sorted h, signal velocities and Balsara factors:
+    // they are valid again only once it has succeeded
+    c->vsig_valid = c->bal_valid = false;
     c->rebuilds = 0;
     density_buffers(c);
     double* cons_d = force_buffers(c, cons != nullptr);

@@ -1,6 +1,8 @@
 """Shared helpers of the GPU parity tests: error measures against the oracle,
 with the tolerances of the FP32 and FP64 forms."""
 
+import math
+
 import numpy as np
 from scipy.spatial import cKDTree
 
@@ -48,42 +50,54 @@ def assert_within(e: dict, tol: dict, label: str = ""):
     assert not bad, "%s exceeds tolerance: %s" % (label, bad)
 
 
-def oracle_sample(d: dict, targets, radius: float, box: int = 0) -> dict:
-    """Oracle values at `targets` of one box: h, rho, f of the targets and of
-    every particle within `radius` of them (so the force of each target sees
-    every neighbour's h), then the force of the targets. Arrays are full
-    length with NaN away from the sample."""
-    s, e = int(d["box_first"][box]), int(d["box_first"][box + 1])
-    pos = d["pos"][s:e]
-    L = float(d["box_len"][box])
-    tree = cKDTree(np.mod(pos, L), boxsize=L)
-    near = tree.query_ball_point(np.mod(pos[targets], L), radius)
-    need = np.unique(np.concatenate([np.asarray(targets)] + [np.asarray(x, dtype=np.int64) for x in near]))
-    r = oracle.density(pos, d["mass"][s:e], L, targets=need, h_start=d["h0"][s:e])
-    fo = oracle.force(pos, d["vel"][s:e], d["mass"][s:e], d["u"][s:e], r["h"], r["rho"], r["f"], L,
-                      targets=np.asarray(targets, dtype=np.int64))
-    r.update(fo)
-    return r
+def h_upper_bound(pos, L: float, n_ngb: float = 48.0, chunk: int = 1 << 20):
+    """An upper bound on every particle's smoothing length from the positions
+    alone. w(q) >= w(1/2) = 1/4 for q <= 1/2, so K other particles within a
+    radius rho give S0(2 rho) >= 1 + K/4; with K = ceil((3 n_ngb / 32 - 1) * 4)
+    (14 for 48 neighbours) that reaches the target, and since S0 grows with h
+    the root h_i is at most twice the distance to i's K-th nearest neighbour
+    (scipy's cKDTree, periodic)."""
+    K = int(math.ceil((3.0 * n_ngb / 32.0 - 1.0) * 4.0 - 1e-9))
+    tree = cKDTree(pos, boxsize=L)
+    out = np.empty(pos.shape[0])
+    for a in range(0, pos.shape[0], chunk):
+        dk, _ = tree.query(pos[a:a + chunk], k=K + 1, workers=-1)  # K + 1: the particle itself included
+        out[a:a + chunk] = 2.0 * dk[:, K]
+    return out * (1.0 + 1e-9), tree
 
 
-def oracle_sample_exact(d: dict, targets, h_near, box: int = 0) -> dict:
-    """Like oracle_sample, but the sample is every particle j that pairs with a
-    target i (r_ij < max(h_i, h_j), with 2% slack), found from the smoothing
-    lengths h_near (any close estimate, e.g. the GPU's; they only choose the
-    sample, the oracle solves its own h). Suits sets whose h spans decades,
-    where one radius would either miss neighbours or take most of the box."""
+# bounds of the positions already seen (a 2^24-particle set takes tens of
+# seconds), keyed by the position array, which the entry keeps alive
+_BOUNDS = {}
+
+
+def oracle_sample_exact(d: dict, targets, box: int = 0) -> dict:
+    """Oracle values at `targets` of one box, solving h only where needed:
+    the targets, and every particle that can pair with one. Nothing here
+    comes from the GPU. A partner j of target i has r_ij < max(h_i, h_j):
+    either it lies inside the target's oracle h_i, or inside its own h_j,
+    which h_upper_bound caps from the positions alone; the sample takes
+    every particle within its bound of some target. The oracle force then
+    refuses (rather than skips) any neighbour inside h_i left unsolved.
+    Suits sets whose h spans decades, where one radius would either miss
+    neighbours or take most of the box."""
     s, e = int(d["box_first"][box]), int(d["box_first"][box + 1])
     L = float(d["box_len"][box])
     pos = np.mod(d["pos"][s:e], L)
-    hn = np.asarray(h_near[s:e], dtype=np.float64) * 1.02
+    mass = d["mass"][s:e]
     targets = np.asarray(targets, dtype=np.int64)
-    # j within its own h of some target (scipy takes one radius per query point)
-    hits = cKDTree(pos[targets], boxsize=L).query_ball_point(pos, hn, return_length=True)
-    # j within the target's h
-    near = cKDTree(pos, boxsize=L).query_ball_point(pos[targets], hn[targets])
+    key = (id(d["pos"]), box)
+    if key not in _BOUNDS or _BOUNDS[key][0] is not d["pos"]:
+        _BOUNDS[key] = (d["pos"],) + h_upper_bound(pos, L)
+    _, hb, tree = _BOUNDS[key]
+    rt = oracle.density(pos, mass, L, targets=targets, h_start=d["h0"][s:e])
+    # j within the target's own h
+    near = tree.query_ball_point(pos[targets], rt["h"][targets] * (1.0 + 1e-9))
+    # j whose bound on h_j reaches some target (scipy takes one radius per query point)
+    hits = cKDTree(pos[targets], boxsize=L).query_ball_point(pos, hb, return_length=True)
     need = np.unique(np.concatenate([targets, np.nonzero(hits)[0]] + [np.asarray(x, dtype=np.int64) for x in near]))
-    r = oracle.density(pos, d["mass"][s:e], L, targets=need, h_start=d["h0"][s:e])
-    fo = oracle.force(pos, d["vel"][s:e], d["mass"][s:e], d["u"][s:e], r["h"], r["rho"], r["f"], L,
+    r = oracle.density(pos, mass, L, targets=need, h_start=d["h0"][s:e])
+    fo = oracle.force(pos, d["vel"][s:e], mass, d["u"][s:e], r["h"], r["rho"], r["f"], L,
                       targets=targets)
     r.update(fo)
     r["n_sample"] = len(need)

