@@ -190,6 +190,7 @@ struct sph_ctx {
     // ---- density / force state (sorted order) ---------------------------------
     sph::Buf jd;             // float4 (x, y, z, m)
     sph::Buf hs, rhos, fs;   // float, sorted
+    sph::Buf u_s;            // float, sorted u (the pass's fused ghost step)
     sph::Buf status;         // uint8, caller order
     sph::Buf st_s;           // uint8, sorted copy of status
     sph::Buf scan_cells;     // int: leaves holding particles left to the re-scan

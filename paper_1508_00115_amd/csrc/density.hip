@@ -53,15 +53,16 @@ struct DensArgs {
     float* rhos;
     float* fs;
     uint8_t* st_s;           // sorted state
+    const uint32_t* perm;    // sorted index -> caller index
+    float* h_out;            // caller order: h (on an overflow, the larger guess
+                             // the rebuild starts from)
+    float* rho_out;
+    float* f_out;
+    float* nw_out;           // weighted neighbour count (null: not wanted)
+    uint8_t* status;         // caller order
     const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
-    const uint32_t* perm;
-    float* h_out;
-    float* rho_out;
-    float* f_out;
-    float* nw_out;
-    uint8_t* status;
     int64_t* ctr;
     int* scan_cells;         // schedule slots queued for k_density_scan (ctr[CT_SCAN_CELLS] of them)
     WorkSched W;             // which wavefront takes which cell
@@ -72,9 +73,9 @@ struct DensArgs {
     int lpi_min;             // fewest lanes per particle (a power of two): spreads a list over enough slots
     float nl_est;            // expected list length of a particle: n_ngb * h_margin^3
     // ghost step fused into the outputs (null jf: not fused): the force
-    // loop's streams from the final h, rho, f and the caller's v, u
-    const float* vel;
-    const float* u;
+    // loop's streams from the final h, rho, f and u (the prologue has put
+    // (v, m) into each particle's second float4 and u into u_s)
+    const float* u_s;
     float4* jf;
     float gamma;
     const float* drift;      // [0]: bound on the drift since the build (search Hs - 2 drift)
@@ -82,15 +83,19 @@ struct DensArgs {
 
 // Sorted copies of position (cell frame), mass, h and state. fresh: every
 // particle starts active; otherwise the caller-order state of the previous
-// pass is kept (an overflowed particle starts again).
+// pass is kept (an overflowed particle starts again). With vel and u (the
+// pass's fused ghost step) also the force loop's (v, m) stream and the sorted
+// u, with their checks, so that the density kernels' ghost step reads only
+// sorted data.
 __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm,
                                                        const float4* __restrict__ xrel,
                                                        const float* __restrict__ mass,
                                                        const float* __restrict__ h_in,
                                                        const uint8_t* __restrict__ status, int fresh,
-                                                       float4* __restrict__ jd,
-                                                       float* __restrict__ hs, uint8_t* __restrict__ st_s,
-                                                       int64_t* __restrict__ ctr)
+                                                       const float* __restrict__ vel, const float* __restrict__ u,
+                                                       float4* __restrict__ jd, float* __restrict__ hs,
+                                                       uint8_t* __restrict__ st_s, float4* __restrict__ jf,
+                                                       float* __restrict__ u_s, int64_t* __restrict__ ctr)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
@@ -104,6 +109,13 @@ __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t
         const uint8_t st = fresh ? (uint8_t)ST_ACTIVE : status[o];
         st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
         bad = !((m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h));
+        if (jf) {
+            const float uu = u[o];
+            const float vx = vel[3 * (int64_t)o], vy = vel[3 * (int64_t)o + 1], vz = vel[3 * (int64_t)o + 2];
+            bad |= !(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz);
+            jf[3 * p + 1] = make_float4(vx, vy, vz, m);
+            u_s[p] = uu;
+        }
     }
     // one count per block instead of per-particle atomics on a shared counter
     const int n_bad = __syncthreads_count(bad);
@@ -189,16 +201,18 @@ __device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float
     s.h = hn;
 }
 
-// Outputs of one particle at its final h (sums M0 = sum m w, M1 = sum m q w').
+// Outputs of one particle at its final h (sums M0 = sum m w, M1 = sum m q w'):
+// sorted copies for the force loop, caller-order outputs at o = perm[i]
+// (loaded with the particle, so the stores wait for nothing).
 template <class I>
-__device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSolve& s, float S0, float M0,
-                                             float M1, int cnt, I& inter_acc, I& n_over, I& n_unconv,
-                                             int& max_ev)
+__device__ __forceinline__ void write_result(const DensArgs& A, int i, uint32_t o, const HSolve& s, float S0,
+                                             float M0, float M1, int cnt, I& inter_acc, I& n_over,
+                                             I& n_unconv, int& max_ev)
 {
-    const uint32_t o = A.perm[i];
     float h_report = s.h;
     if (s.state == ST_OVERFLOW) {
         // propose the radius at which a uniform density would hold the target
+        // (the rebuild starts this particle from there)
         h_report = s.h * fmaxf(cbrtf(A.target / S0), 1.0f) * 1.05f;
     }
     // (selects, not branches: a branch here makes the compiler keep the two
@@ -221,19 +235,16 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, const HSo
     max_ev = max(max_ev, s.nev);
     if (A.jf) {
         // the ghost step of this particle (the same arithmetic as the force
-        // loop's ghost kernel, so both give the same bits)
+        // loop's ghost kernel, so both give the same bits); the second float4,
+        // (v, m), was written by the prologue
         const float4 x = A.jd[i];
         const float h = s.h;
-        const float uu = A.u[o];
-        const float vx = A.vel[3 * (int64_t)o], vy = A.vel[3 * (int64_t)o + 1], vz = A.vel[3 * (int64_t)o + 2];
-        if (!(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz))
-            atomicAdd((unsigned long long*)&ctr_slot(A.ctr)[CT_BAD_INPUT], 1ull);
+        const float uu = A.u_s[i];
         const float gamma = A.gamma;
         const float P = (gamma - 1.0f) * rho * uu;
         const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
         const float phi = f * P / (rho * rho);
         A.jf[3 * (int64_t)i + 0] = make_float4(x.x, x.y, x.z, h * h);
-        A.jf[3 * (int64_t)i + 1] = make_float4(vx, vy, vz, x.w);
         A.jf[3 * (int64_t)i + 2] = make_float4(rho, phi, c, 1.0f / h);
     }
 }
@@ -307,13 +318,71 @@ __device__ __forceinline__ void scan_chunk(const float4* tc, int len, float xx, 
     }
 }
 
+// The first 64 neighbour records of a cell (lane q: record q), loaded with
+// independent loads. A wavefront with a next cell loads them for that cell
+// while it computes the current one; the particles of a cell are loaded
+// together with its first chunk of candidates. So the chain cell -> records
+// -> candidates costs about one memory latency per cell, not three.
+struct CellRecs {
+    int4 ci;      // first particle, count, first record, records
+    int2 rec;     // p_rec of record `lane`
+    float4 sh;    // p_shift of record `lane`
+};
+
+__device__ __forceinline__ void cell_recs(const DensArgs& A, CellRecs& P)
+{
+    const int lane = threadIdx.x & 63;
+    const int pb0 = P.ci.z, np = P.ci.w;
+    P.rec = make_int2(0, 0);
+    P.sh = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < np) {
+        P.rec = A.p_rec[pb0 + lane];
+        P.sh = A.p_shift[pb0 + lane];
+    }
+}
+
+// One evaluation of the sums over a lane's list at 1/h = hinv. w(q) = 2 t^3 -
+// 8 u^3 and q w'(q) = q (24 u^2 - 6 t^2) with t = max(1 - q, 0), u =
+// max(1/2 - q, 0): the cubic spline as truncated powers, no branch and no
+// select (both clamps are the FMA's clamp to [0, 1]). FIRST: the list still
+// holds r^2; each entry is replaced by r as it is read.
+template <bool FIRST>
+__device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float& S0, float& S1, int& cnt)
+{
+    float At = 0.f, Au = 0.f, Bt = 0.f, Bu = 0.f;
+    int c = 0;
+#pragma unroll 2
+    for (int e = 0; e < len; ++e) {
+        float r = lst[e * 64];
+        if (FIRST) {
+            r = __builtin_amdgcn_sqrtf(r);
+            lst[e * 64] = r;
+        }
+        const float q = r * hinv;
+        const float t = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+        const float u = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
+        const float t2 = t * t, u2 = u * u;
+        At = fmaf(t2, t, At);
+        Au = fmaf(u2, u, Au);
+        Bt = fmaf(q, t2, Bt);
+        Bu = fmaf(q, u2, Bu);
+        c += t > 0.0f ? 1 : 0;  // r < h
+    }
+    S0 = fmaf(2.0f, At, -8.0f * Au);
+    S1 = fmaf(24.0f, Bu, -6.0f * Bt);
+    cnt = c;
+}
+
 // One wavefront per cell. TCAP: candidates the LDS tile holds; a cell with at
 // most TCAP candidates stages them once and keeps them for all its passes,
 // a larger one streams them through the first DCH slots in every pass.
-// At most 128 VGPRs: four wavefronts per SIMD (the kernel waits on memory
-// more than it computes, so resident wavefronts matter more than registers).
-template <int TCAP>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_density(DensArgs A)
+// PERSIST (the per-XCD queues): a wavefront takes cell after cell and loads
+// the next cell's records while it computes the current one; the registers
+// that takes leave three wavefronts per SIMD, which then cover the memory
+// latency the prefetch does not. Hardware dispatch (one cell per wavefront)
+// has no next cell: at most 128 VGPRs, four wavefronts per SIMD.
+template <int TCAP, bool PERSIST>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
     __shared__ float4 tile[TCAP];
     __shared__ float lists[(DSLOTS + 1) * 64];
@@ -329,17 +398,41 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
     int inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0, list_acc = 0;
     int max_ev = 0;
 
-    for (;;) {
-        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
-        const int slot = a_cur++;
-        const int4 ci = A.cells[slot];
-        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
-        // the cell's own particles are among its candidates: when every
-        // candidate has this mass, so has every particle of the cell
-        const float m0 = ni > 0 ? A.jd[i0].w : 0.0f;
+    // the next schedule slot of this wavefront (wave-uniform), if any
+    auto next_slot = [&](int& sl) -> bool {
+        if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) return false;
+        sl = __builtin_amdgcn_readfirstlane(a_cur++);
+        return true;
+    };
+
+    int slot = 0;
+    bool have = next_slot(slot);
+    CellRecs cur;
+    if (have) {
+        cur.ci = A.cells[slot];
+        cell_recs(A, cur);
+    }
+    while (have) {
+        int nslot = 0;
+        const bool have_next = PERSIST && next_slot(nslot);
+        CellRecs nxt;
+        if (have_next) nxt.ci = A.cells[nslot];  // in flight while this cell is staged
+        const int i0 = cur.ci.x, ni = cur.ci.y, pb0 = cur.ci.z, np_all = cur.ci.w;
+        // the cell's first 64 particles, one per lane (in flight with the first chunk)
+        float4 px = make_float4(0.f, 0.f, 0.f, 0.f);
+        float ph = 0.f, pH = 0.f;
+        int pst = ST_DONE;
+        uint32_t pperm = 0;
+        if (lane < ni) {
+            px = A.jd[i0 + lane];
+            ph = A.hs[i0 + lane];
+            pH = A.Hs[i0 + lane] - two_delta;
+            pst = A.st_s[i0 + lane];
+            pperm = A.perm[i0 + lane];
+        }
         int n_flag = 0;  // this lane's particles of the cell left to the re-scan
         NbrCursor cu;
-        cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
+        cursor_init_from(cu, nbr_from(cur.rec, cur.sh, min(np_all, 64)), pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         // resident: one block of neighbour records and at most TCAP candidates,
         // staged once at fixed tile slots of DCH
@@ -351,14 +444,36 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         const int sub = lane & (lpi - 1);
         bool loaded = false;  // (resident) every candidate is in the tile
         bool mixed = false;   // a candidate with another mass was staged
+        bool pre_issued = false;
+        float m0 = 0.0f;      // the mass of the cell's first particle
 
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
             const bool valid = gi < ni;
             const int i = i0 + (valid ? gi : 0);
-            const float4 xi = A.jd[i];
-            const uint8_t st0 = A.st_s[i];
-            HSolve s = hsolve_init(A.hs[i], A.Hs[i] - two_delta, !valid || st0 != ST_ACTIVE, st0);
+            float4 xi;
+            float h_start, H_i;
+            int st_i;
+            uint32_t o_i;
+            if (ib + per_pass <= 64) {
+                // the particles of this pass were loaded with the cell
+                const int src = valid ? gi : 0;
+                xi.x = __shfl(px.x, src, 64);
+                xi.y = __shfl(px.y, src, 64);
+                xi.z = __shfl(px.z, src, 64);
+                h_start = __shfl(ph, src, 64);
+                H_i = __shfl(pH, src, 64);
+                st_i = __shfl(pst, src, 64);
+                o_i = (uint32_t)__shfl((int)pperm, src, 64);
+            } else {
+                xi = A.jd[i];
+                h_start = A.hs[i];
+                H_i = A.Hs[i] - two_delta;
+                st_i = A.st_s[i];
+                o_i = A.perm[i];
+            }
+            const uint8_t st0 = (uint8_t)st_i;
+            HSolve s = hsolve_init(h_start, H_i, !valid || st0 != ST_ACTIVE, st0);
             const int active_groups = wave_count(!s.done && sub == 0);
             if (active_groups == 0) continue;
 
@@ -372,6 +487,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     cursor_seek(cu, A.p_rec, A.p_shift, 0);
                     fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH), marks);
                 }
+                if (have_next && !pre_issued) {
+                    // the next cell's records, in flight from here on
+                    cell_recs(A, nxt);
+                    pre_issued = true;
+                }
+                // the cell's own particles are among its candidates: when
+                // every candidate has this mass, so has every particle of it
+                m0 = __shfl(px.w, 0, 64);
                 int len;
                 for (int c0 = 0; c0 < nj; c0 += len) {
                     len = stream ? R.len : min(DCH, nj - c0);
@@ -399,7 +522,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 loaded = true;
                 cand_acc += (int64_t)active_groups * nj;
             }
-            const int nl = (int)((o - o_lane) >> 8);
+            int nl = (int)((o - o_lane) >> 8);
             if (mixed) {
                 // lists hold no masses: the cell's remaining particles re-scan
                 // (every candidate is staged in the first pass that streams,
@@ -416,39 +539,27 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     ++n_flag;
                 }
             }
+            if (s.done) nl = 0;
+            wave_sync_lds();
+            nl = balance_lists(lists, nl, lpi);  // phase B's trip count follows the mean, not the longest list
 
             // ---- phase B: Newton iteration on h over the list --------------------
             // (fS0, fS1, fcnt: the sums of this particle's last evaluation; a
-            // finished particle skips its list while others still iterate)
-            float S0 = 0.f, S1 = 0.f, fS0 = 0.f, fS1 = 0.f;
-            int cnt = 0, fcnt = 0;
-            // r^2 -> r once, so that no evaluation takes a square root
-            for (int e = 0, len_l = s.done ? 0 : nl; e < len_l; ++e) lst[e * 64] = __builtin_amdgcn_sqrtf(lst[e * 64]);
+            // finished particle skips its list while others still iterate; the
+            // first evaluation also turns r^2 into r)
+            float fS0 = 0.f, fS1 = 0.f;
+            int fcnt = 0;
+            bool first = true;
             while (__any(!s.done)) {
                 const float hinv = __builtin_amdgcn_rcpf(s.h);
-                cnt = 0;
                 const int len_l = s.done ? 0 : nl;
-                // w(q) = 2 t^3 - 8 u^3 and q w'(q) = q (24 u^2 - 6 t^2) with
-                // t = max(1 - q, 0), u = max(1/2 - q, 0): the cubic spline as
-                // truncated powers, no branch and no select (both clamps are
-                // the FMA's clamp to [0, 1]); the four sums are combined after
-                // the loop
-                float At = 0.f, Au = 0.f, Bt = 0.f, Bu = 0.f;
-#pragma unroll 2
-                for (int e = 0; e < len_l; ++e) {
-                    const float r = lst[e * 64];
-                    const float q = r * hinv;
-                    const float t = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
-                    const float u = __builtin_amdgcn_fmed3f(fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
-                    const float t2 = t * t, u2 = u * u;
-                    At = fmaf(t2, t, At);
-                    Au = fmaf(u2, u, Au);
-                    Bt = fmaf(q, t2, Bt);
-                    Bu = fmaf(q, u2, Bu);
-                    cnt += t > 0.0f ? 1 : 0;  // r < h
-                }
-                S0 = fmaf(2.0f, At, -8.0f * Au);
-                S1 = fmaf(24.0f, Bu, -6.0f * Bt);
+                float S0, S1;
+                int cnt;
+                if (first)
+                    eval_list<true>(lst, len_l, hinv, S0, S1, cnt);
+                else
+                    eval_list<false>(lst, len_l, hinv, S0, S1, cnt);
+                first = false;
                 list_acc += len_l;
                 S0 = group_sum(S0, lpi);
                 S1 = group_sum(S1, lpi);
@@ -461,10 +572,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
             }
             if (valid && sub == 0 && st0 == ST_ACTIVE && fits)
-                write_result(A, i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
+                write_result(A, i, o_i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
         }
+        if (have_next && !pre_issued) cell_recs(A, nxt);  // (no pass had an active particle)
         enqueue_scan(A, slot, n_flag);
         n_scan += n_flag;
+        cur = nxt;
+        slot = nslot;
+        have = have_next;
     }
     flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
 }
@@ -583,7 +698,7 @@ __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, f
         if (sub == 0) sweep_acc += cnt;
         hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
     }
-    if (active && sub == 0) write_result(A, i, s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
+    if (active && sub == 0) write_result(A, i, A.perm[i], s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
 }
 
 __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
@@ -679,7 +794,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                     hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
                 }
                 if (listed && sub == 0)
-                    write_result(A, i, s, fS0, fM0, fM1, fcnt, inter_acc, n_over, n_unconv, max_ev);
+                    write_result(A, i, A.perm[i], s, fS0, fM0, fM1, fcnt, inter_acc, n_over, n_unconv, max_ev);
 
                 // ---- lists too short: re-test every candidate per evaluation -------
                 const bool rewalk = valid && !fits;
@@ -722,10 +837,14 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     float* rhos = static_cast<float*>(c->rhos.p);
     float* fs = static_cast<float*>(c->fs.p);
     uint8_t* st_s = static_cast<uint8_t*>(c->st_s.p);
+    const bool ghost = ghost_vel && ghost_u;
+    float4* jf = ghost ? static_cast<float4*>(c->jf.p) : nullptr;
+    float* u_s = ghost ? static_cast<float*>(c->u_s.p) : nullptr;
     fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);  // sums, spread slots, queue heads
     k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
-                                                        static_cast<float4*>(c->xrel.p), mass, h, status, fresh ? 1 : 0,
-                                                        jd, hs, st_s, ctr);
+                                                        static_cast<float4*>(c->xrel.p), mass, h, status,
+                                                        fresh ? 1 : 0, ghost_vel, ghost_u, jd, hs, st_s, jf, u_s,
+                                                        ctr);
     SPH_HIP(hipGetLastError());
     DensArgs A;
     A.jd = jd;
@@ -734,15 +853,15 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.rhos = rhos;
     A.fs = fs;
     A.st_s = st_s;
-    A.cells = static_cast<int4*>(c->cells.p);
-    A.p_rec = static_cast<int2*>(c->p_rec.p);
-    A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.perm = static_cast<uint32_t*>(c->perm.p);
     A.h_out = h;
     A.rho_out = rho;
     A.f_out = f;
     A.nw_out = nw;
     A.status = status;
+    A.cells = static_cast<int4*>(c->cells.p);
+    A.p_rec = static_cast<int2*>(c->p_rec.p);
+    A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.ctr = ctr;
     A.target = (float)(3.0 * c->prm.n_ngb / 32.0);
     A.inv_target = (float)(32.0 / (3.0 * c->prm.n_ngb));
@@ -756,21 +875,21 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.lpi_min = 2;
     while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
     A.scan_cells = static_cast<int*>(c->scan_cells.p);
-    A.vel = ghost_vel;
-    A.u = ghost_u;
-    A.jf = ghost_vel && ghost_u ? static_cast<float4*>(c->jf.p) : nullptr;
+    A.u_s = u_s;
+    A.jf = jf;
     A.gamma = (float)c->prm.gamma;
     A.drift = static_cast<float*>(c->drift.p);
     const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
     // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
     const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
     if (events) ev_record(c, EV_DENS_K0, s);
+    const bool pers = A.W.persistent != 0;
     if (c->prm.tile_cap == 512)
-        k_density<512><<<grid, BS, 0, s>>>(A);
+        pers ? k_density<512, true><<<grid, BS, 0, s>>>(A) : k_density<512, false><<<grid, BS, 0, s>>>(A);
     else if (c->prm.tile_cap == 256)
-        k_density<256><<<grid, BS, 0, s>>>(A);
+        pers ? k_density<256, true><<<grid, BS, 0, s>>>(A) : k_density<256, false><<<grid, BS, 0, s>>>(A);
     else
-        k_density<128><<<grid, BS, 0, s>>>(A);
+        pers ? k_density<128, true><<<grid, BS, 0, s>>>(A) : k_density<128, false><<<grid, BS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_DENS_KM, s);
     k_density_scan<<<scan_grid, BS, 0, s>>>(A);
@@ -786,6 +905,7 @@ void density_buffers(sph_ctx* c)
     ensure<float>(c, c->hs, n);
     ensure<float>(c, c->rhos, n);
     ensure<float>(c, c->fs, n);
+    ensure<float>(c, c->u_s, n);
     ensure<uint8_t>(c, c->st_s, n);
     ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
 }
@@ -796,7 +916,6 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
     check_drift(c, h, s);
-    const int64_t n = c->n;
     int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;
     int32_t sweeps = 0;
     c->rebuilds = 0;
@@ -836,8 +955,10 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
                 st->n_pairs = c->n_pairs;
             }
             if (c->rebuilds > 0) {
-                k_dens_regather<<<blocks_for(n, 256), 256, 0, s>>>(
-                    n, static_cast<uint32_t*>(c->perm.p), h, rho, f, static_cast<float*>(c->hs.p),
+                // sorted copies of every particle's final values (those solved
+                // before the last rebuild were not touched by its pass)
+                k_dens_regather<<<blocks_for(c->n, 256), 256, 0, s>>>(
+                    c->n, static_cast<uint32_t*>(c->perm.p), h, rho, f, static_cast<float*>(c->hs.p),
                     static_cast<float*>(c->rhos.p), static_cast<float*>(c->fs.p));
                 SPH_HIP(hipGetLastError());
             }

@@ -190,6 +190,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float4 i0v = A.jf[NF * (int64_t)i + 0];
             const float4 i1v = A.jf[NF * (int64_t)i + 1];
             const float4 i2v = A.jf[NF * (int64_t)i + 2];
+            const uint32_t o_i = DC ? 0u : A.perm[i];  // loaded here so the stores wait for nothing
             const float bal_i = MODE == FM_BALSARA ? A.jf[NF * (int64_t)i + 3].x : 1.0f;
             const float h2_i = i0v.w;
             const float hinv_i = i2v.w;
@@ -299,11 +300,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             cand_acc += (int64_t)wave_count(leader) * kept;
             double cm[4] = {0.0, 0.0, 0.0, 0.0};
             if (leader) {
-                const uint32_t o = A.perm[i];
-                A.acc[3 * (int64_t)o + 0] = ax;
-                A.acc[3 * (int64_t)o + 1] = ay;
-                A.acc[3 * (int64_t)o + 2] = az;
-                A.dudt[o] = du;
+                A.acc[3 * (int64_t)o_i + 0] = ax;
+                A.acc[3 * (int64_t)o_i + 1] = ay;
+                A.acc[3 * (int64_t)o_i + 2] = az;
+                A.dudt[o_i] = du;
                 if constexpr (VSIG) A.vsig[i] = fmaxf(vmax, c_i);
                 inter_acc += cnt;
                 const double m = i1v.w;

@@ -146,6 +146,37 @@ __device__ __forceinline__ int group_sum_i(int v, int lpi)
     return v;
 }
 
+// Even out the list lengths of the lpi lanes of each particle (aligned groups
+// of lanes; lane l's list is lists[l], lists[l + 64], ...), whose phase B
+// trip count is the longest list in the wavefront: at distance m = 1, 2, ...
+// the lane of each pair with more entries hands the surplus half to its
+// partner, which copies them from the end of the giver's list to the end of
+// its own (the giver only shortens its count, so no lane reads a slot that
+// is being written). After log2(lpi) steps the lists of a particle differ by
+// at most one entry; the set of entries, and so every sum, is unchanged (only
+// the order in which the lanes add them, as with any split of the
+// candidates). No list grows beyond the longest one. Returns the lane's new
+// length; the whole wavefront must be active.
+template <class T>
+__device__ __forceinline__ int balance_lists(T* lists, int nl, int lpi)
+{
+    const int lane = threadIdx.x & 63;
+    for (int m = 1; m < lpi; m <<= 1) {
+        const int nl_p = __shfl_xor(nl, m, 64);
+        const int tot = nl + nl_p;
+        const int mine = (lane & m) ? (tot >> 1) : tot - (tot >> 1);
+        const int take = mine - nl;  // > 0: copy that many from the partner's end
+        const T* src = lists + (lane ^ m) + (nl_p - take) * 64;
+        T* dst = lists + lane + nl * 64;
+        for (int t = 0; t < take; ++t) dst[t * 64] = src[t * 64];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        nl = mine;
+    }
+    return nl;
+}
+
 // Number of lanes for which c holds (a scalar bit count of the ballot).
 __device__ __forceinline__ int wave_count(bool c)
 {
@@ -176,6 +207,28 @@ struct NbrLanes {
     float sx, sy, sz;
     int np, nj;
 };
+
+// The records already in registers (lane q: record q, zero beyond np).
+__device__ __forceinline__ NbrLanes nbr_from(int2 rec, float4 sh, int np)
+{
+    const int lane = threadIdx.x & 63;
+    NbrLanes nb;
+    nb.bs = rec.x;
+    nb.bc = rec.y;
+    nb.sx = sh.x;
+    nb.sy = sh.y;
+    nb.sz = sh.z;
+    int inc = nb.bc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    nb.off = inc - nb.bc;
+    nb.nj = __shfl(inc, 63, 64);
+    nb.np = np;
+    return nb;
+}
 
 __device__ __forceinline__ NbrLanes load_nbr(const int2* __restrict__ p_rec, const float4* __restrict__ p_shift,
                                              int pb0, int np)
@@ -225,6 +278,16 @@ __device__ __forceinline__ void cursor_init(NbrCursor& cu, const int2* __restric
     cu.b0 = 0;
     cu.off0 = 0;
     cu.nb = load_nbr(p_rec, p_shift, pb0, min(np_all, 64));
+}
+
+// The cursor on a cell whose first block of records is already in registers.
+__device__ __forceinline__ void cursor_init_from(NbrCursor& cu, const NbrLanes& nb, int pb0, int np_all)
+{
+    cu.pb0 = pb0;
+    cu.np_all = np_all;
+    cu.b0 = 0;
+    cu.off0 = 0;
+    cu.nb = nb;
 }
 
 // Move the cursor to the block holding candidate c (c at or after the
