@@ -340,6 +340,20 @@ sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, voi
 sph_status sph_timestep(sph_ctx* ctx, double courant, double* dt, void* stream);
 
 /*
+ * sph_timestep without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid it). Same arguments, result and errors as sph_timestep (bit for bit
+ * the same dt). Its reduction scratch is a static device array of 16 KB per
+ * GPU (4096 per-workgroup minima and the result), whose address the library
+ * takes when a context is created on that GPU; any particle count fits (the
+ * workgroups stride over the particles). All calls on one GPU share that
+ * array: calls that overlap on one GPU (other streams or host threads at the
+ * same time) race and must be serialised by the caller. Synchronises
+ * `stream`.
+ */
+sph_status sph_timestep_noalloc(sph_ctx* ctx, double courant, double* dt, void* stream);
+
+/*
  * Balsara factors B of the last force pass (see sph_params.balsara), in the
  * caller's particle order.
  *   balsara  device, n floats, out (caller-owned)

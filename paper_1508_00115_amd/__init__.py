@@ -28,7 +28,7 @@ SPH_E_STATE = 6
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
            "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info",
-           "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara")
+           "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara", "sph_timestep_noalloc")
 
 
 class sph_params(ctypes.Structure):
@@ -126,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_drift.restype = ctypes.c_int
     lib.sph_timestep.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
     lib.sph_timestep.restype = ctypes.c_int
+    lib.sph_timestep_noalloc.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
+    lib.sph_timestep_noalloc.restype = ctypes.c_int
     lib.sph_get_balsara.argtypes = [P, P, P]
     lib.sph_get_balsara.restype = ctypes.c_int
     lib.sph_struct_size.argtypes = [ctypes.c_int32]
@@ -202,6 +204,10 @@ def sph_drift(ctx, dt, vel, pos, stream) -> int:
 
 def sph_timestep(ctx, courant, dt_out, stream) -> int:
     return load_library().sph_timestep(ctx, courant, dt_out, stream)
+
+
+def sph_timestep_noalloc(ctx, courant, dt_out, stream) -> int:
+    return load_library().sph_timestep_noalloc(ctx, courant, dt_out, stream)
 
 
 def sph_get_balsara(ctx, balsara, stream) -> int:
@@ -368,6 +374,14 @@ class Context:
         """sph_timestep: courant * min h / v_sig after the last force pass."""
         out = ctypes.c_double()
         rc = sph_timestep(self.ctx, float(courant), ctypes.byref(out), _stream(stream))
+        _check(rc, self.ctx)
+        return out.value
+
+    def timestep_noalloc(self, courant, stream=None) -> float:
+        """sph_timestep_noalloc: sph_timestep with its scratch in the
+        library's static device array (no allocation)."""
+        out = ctypes.c_double()
+        rc = sph_timestep_noalloc(self.ctx, float(courant), ctypes.byref(out), _stream(stream))
         _check(rc, self.ctx)
         return out.value
 

@@ -96,6 +96,7 @@ sph_status sph_create(const sph_params* params, int hip_device, sph_ctx** out)
             for (auto& e : c->ev) SPH_HIP(hipEventCreate(&e));
         sph::ensure<int64_t>(c, c->counters, CT_COUNT);
         SPH_HIP(hipHostMalloc((void**)&c->h_counters, CT_COUNT * sizeof(int64_t), hipHostMallocDefault));
+        sph::scratch_setup(hip_device);  // the static scratch of sph_timestep_noalloc on this device
     });
     if (st != SPH_OK) {
         g_create_error = c->err;
@@ -203,6 +204,16 @@ sph_status sph_timestep(sph_ctx* c, double courant, double* dt, void* stream)
         SPH_REQUIRE(dt, SPH_E_ARG, "null dt");
         set_device(c);
         *dt = sph::timestep(c, courant, (hipStream_t)stream);
+    });
+}
+
+sph_status sph_timestep_noalloc(sph_ctx* c, double courant, double* dt, void* stream)
+{
+    if (!c) return SPH_E_ARG;
+    return guarded(c, [&] {
+        SPH_REQUIRE(dt, SPH_E_ARG, "null dt");
+        set_device(c);
+        *dt = sph::timestep_noalloc(c, courant, (hipStream_t)stream);
     });
 }
 

@@ -406,6 +406,11 @@ void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const floa
           float* vel_out, float* u_out, hipStream_t s);
 void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s);
 double timestep(sph_ctx* c, double courant, hipStream_t s);
+// The same step with the reduction scratch in a static device array
+// (noalloc.hip); scratch_setup takes that array's address on `device` (which
+// must be current) once per device.
+double timestep_noalloc(sph_ctx* c, double courant, hipStream_t s);
+void scratch_setup(int device);
 // Offsets from the leaf centres from the current positions (build.hip).
 void refresh_offsets(sph_ctx* c, hipStream_t s);
 // Before a density pass after a drift: reject non-finite positions, and
