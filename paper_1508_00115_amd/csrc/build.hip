@@ -394,11 +394,16 @@ __device__ __forceinline__ void node_geom(int id, const int* nd_coord, const int
 
 // Walk the tree from the 27 top cells around leaf a and list every leaf whose
 // cell box lies within max(Hmax_a, Hmax_leaf) of a's cell box. fill == false
-// counts, fill == true writes the list at p_start[a]. The top cells are
-// visited in three classes of (dx + dy + dz) mod 3, nine cells each, every
-// class spread over the whole 3x3x3 block: the hot kernels stage the list in
-// consecutive chunks, and a chunk that samples the whole neighbourhood gives
-// every particle a similar share of its neighbours (even lane lists).
+// counts (all records into p_cnt, the density's into p_cntd), fill == true
+// writes the list at p_start[a]. The list is split in two: first the leaves
+// within Hmax_a of a's box (p_cntd[a] of them), then those that only reach a
+// with their own radius. The density of a's particles (a gather over j
+// inside h_i <= Hmax_a) needs only the first part; the force (pairs inside
+// max(h_i, h_j)) takes both. The top cells are visited in three classes of
+// (dx + dy + dz) mod 3, nine cells each, every class spread over the whole
+// 3x3x3 block: the hot kernels stage the list in consecutive chunks, and a
+// chunk that samples the whole neighbourhood gives every particle a similar
+// share of its neighbours (even lane lists).
 __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* __restrict__ lf_node,
                            const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
                            const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
@@ -408,7 +413,8 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                            const double* __restrict__ box_len, const uint32_t* __restrict__ p_start,
                            int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
                            int2* __restrict__ p_rec, const int* __restrict__ lf_start,
-                           const int* __restrict__ lf_count, int64_t* __restrict__ ctr)
+                           const int* __restrict__ lf_count, const uint32_t* __restrict__ p_cntd,
+                           uint32_t& cnt_dens, int64_t* __restrict__ ctr)
 {
     const int A = lf_node[a];
     const int b = nd_box[A];
@@ -421,8 +427,9 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
     const int lA = nd_level[A];
     const int tA[3] = {nd_coord[3 * A] >> lA, nd_coord[3 * A + 1] >> lA, nd_coord[3 * A + 2] >> lA};
     const double eps = 1e-9 * wtop;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, cd = 0;  // records so far: all, and those within Hmax_a
     const uint32_t base = fill ? p_start[a] : 0u;
+    const uint32_t base_f = fill ? base + p_cntd[a] : 0u;  // first record only the force needs
     int stack[MAX_STACK];
     for (int cls = 0; cls < 3; ++cls)
     for (int dx = -1; dx <= 1; ++dx)
@@ -457,8 +464,9 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                     if (d2 >= R * R) continue;
                     const int lf = nd_leaf[X];
                     if (lf >= 0) {
+                        const bool dens = d2 < (double)HA * (double)HA;
                         if (fill) {
-                            const uint32_t o = base + cnt;
+                            const uint32_t o = dens ? base + cd : base_f + (cnt - cd);
                             p_leaf[o] = lf;
                             p_rec[o] = make_int2(lf_start[lf], lf_count[lf]);
                             p_shift[o] = make_float4((float)(cX[0] + S[0] - cA[0]), (float)(cX[1] + S[1] - cA[1]),
@@ -466,6 +474,7 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                             p_code[o] = image_code(s[0], s[1], s[2]);
                         }
                         ++cnt;
+                        cd += dens ? 1u : 0u;
                     } else {
                         const int c0 = nd_child0[X], c1 = nd_child1[X];
                         if (sp + (c1 - c0 + 1) > MAX_STACK) {
@@ -476,6 +485,7 @@ __device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* 
                     }
                 }
             }
+    cnt_dens = cd;
     return cnt;
 }
 
@@ -487,19 +497,22 @@ __global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ l
                            const int* __restrict__ nd_child1, const int* __restrict__ top,
                            const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
                            const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
-                           const uint32_t* __restrict__ p_start, int* __restrict__ p_leaf,
-                           float4* __restrict__ p_shift, int* __restrict__ p_code, int2* __restrict__ p_rec,
-                           const int* __restrict__ lf_start, const int* __restrict__ lf_count,
-                           int64_t* __restrict__ ctr)
+                           uint32_t* __restrict__ p_cntd, const uint32_t* __restrict__ p_start,
+                           int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
+                           int2* __restrict__ p_rec, const int* __restrict__ lf_start,
+                           const int* __restrict__ lf_count, int64_t* __restrict__ ctr)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, cnt_dens = 0;
     if (a < n_leaves)
         cnt = partners_of(a, fill, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf, nd_child0, nd_child1,
                           top, box_top_base, box_G, box_len, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
-                          lf_count, ctr);
+                          lf_count, p_cntd, cnt_dens, ctr);
     if (!fill) {
-        if (a < n_leaves) p_cnt[a] = cnt;
+        if (a < n_leaves) {
+            p_cnt[a] = cnt;
+            p_cntd[a] = cnt_dens;
+        }
         // the records of all leaves in 64 bits: the list offsets are a 32-bit scan
         int64_t v = cnt;
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -548,7 +561,8 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, i
                              const int* __restrict__ lf_node, const int* __restrict__ nd_box,
                              const int* __restrict__ nd_level, const int* __restrict__ box_G,
                              const double* __restrict__ box_len, const float* __restrict__ lf_hmax,
-                             int4* __restrict__ cells, int2* __restrict__ cell_aux, float2* __restrict__ cell_geom)
+                             const uint32_t* __restrict__ p_cntd, int4* __restrict__ cells,
+                             int2* __restrict__ cell_aux, float2* __restrict__ cell_geom, int4* __restrict__ cells_d)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nl) return;
@@ -558,6 +572,7 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, i
     const int b = nd_box[node];
     cells[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)(p_start[a + 1] - p_start[a]));
     cell_aux[slot] = make_int2(a, b);
+    cells_d[slot] = make_int4(lf_start[a], lf_count[a], (int)p_start[a], (int)p_cntd[a]);
     const double w = box_len[b] / box_G[b] / (double)(1u << nd_level[node]);
     cell_geom[slot] = make_float2((float)(0.5 * w), lf_hmax[a]);
 }
@@ -808,6 +823,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
 
     // ---- neighbour lists ------------------------------------------------------------------------
     uint32_t* p_cnt = ensure<uint32_t>(c, c->p_cnt, nl + 1);
+    uint32_t* p_cntd = ensure<uint32_t>(c, c->p_cntd, nl + 1);
     uint32_t* p_start = ensure<uint32_t>(c, c->p_start, nl + 1);
     const int* nd_coord = static_cast<int*>(c->nd_coord.p);
     const int* nd_level = static_cast<int*>(c->nd_level.p);
@@ -818,8 +834,8 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     const int* nd_child1 = static_cast<int*>(c->nd_child1.p);
     k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 0, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
                                                  nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                 nullptr, ctr);
+                                                 p_cnt, p_cntd, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                 nullptr, nullptr, ctr);
     SPH_HIP(hipGetLastError());
     scan_exclusive(c, p_cnt, p_start, nl, p_start + nl, s);
     uint32_t np = 0;
@@ -839,7 +855,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     int2* p_rec = ensure<int2>(c, c->p_rec, np);
     k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 1, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
                                                  nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
+                                                 p_cnt, p_cntd, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
                                                  lf_count, ctr);
     SPH_HIP(hipGetLastError());
 
@@ -859,11 +875,12 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
         float2* cell_geom = ensure<float2>(c, c->cell_geom, nl);
+        int4* cells_d = ensure<int4>(c, c->cells_d, nl);
         k_sched_fill<<<blocks_for(nl, BS), BS, 0, s>>>(nl, by_cost ? sv : nullptr, order == 0 ? 1 : 0, lf_start,
                                                        lf_count, p_start, lf_node, nd_box, nd_level,
                                                        static_cast<int*>(c->box_G.p),
-                                                       static_cast<double*>(c->box_len.p), lf_hmax, cells,
-                                                       cell_aux, cell_geom);
+                                                       static_cast<double*>(c->box_len.p), lf_hmax, p_cntd, cells,
+                                                       cell_aux, cell_geom, cells_d);
         SPH_HIP(hipGetLastError());
     }
 

@@ -175,6 +175,8 @@ struct sph_ctx {
     // neighbour lists
     sph::Buf p_start;        // uint32 n_leaves + 1
     sph::Buf p_cnt;          // uint32 n_leaves
+    sph::Buf p_cntd;         // uint32 n_leaves: the first p_cntd[a] records of leaf a are
+                             // within its largest search radius (all the density needs)
     sph::Buf p_leaf;         // int
     sph::Buf p_rec;          // int2 per record: first particle and count of the neighbour leaf
     sph::Buf p_shift;        // float4 (dx, dy, dz, 0): leaf-centre frame offset
@@ -183,6 +185,7 @@ struct sph_ctx {
     sph::Buf cells;          // int4 per slot: first particle, count, first neighbour entry, neighbour entries
     sph::Buf cell_aux;       // int2 per slot: leaf index, box
     sph::Buf cell_geom;      // float2 per slot: half width of the leaf, largest search radius in it
+    sph::Buf cells_d;        // int4 per slot as `cells`, with the density's record count (a prefix)
     sph::Buf sched_key, sched_key_alt, sched_val, sched_val_alt;  // cost sort
     sph::Buf scan_tmp;       // scan workspace
     sph::Buf sort_hist;      // radix-sort histograms

@@ -60,7 +60,10 @@ struct DensArgs {
     float* f_out;
     float* nw_out;           // weighted neighbour count (null: not wanted)
     uint8_t* status;         // caller order
-    const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, entries
+    const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, and
+                             // the entries within the leaf's largest search radius (a prefix of its
+                             // list: the density needs no others)
+    const float2* cell_geom; // per schedule slot: half width of the leaf, largest search radius in it
     const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     int64_t* ctr;
@@ -446,6 +449,11 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         bool mixed = false;   // a candidate with another mass was staged
         bool pre_issued = false;
         float m0 = 0.0f;      // the mass of the cell's first particle
+        unsigned kept_pack = 0;  // (resident) candidates kept of each staged chunk, 8 bits each
+        const bool cull = np_all > 27;  // neighbour cells of other sizes than the cell's own
+        float2 geom = make_float2(0.f, 0.f);  // half width of the cell, its largest search radius
+        if (cull) geom = A.cell_geom[slot];
+        const float hw = cull_half_width(geom.x + 0.5f * two_delta);
 
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
@@ -482,6 +490,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
             {
                 const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
                 const bool stream = !(resident && loaded);
+                // staging keeps only the candidates within reach of the cell's
+                // box (widened by the drift): the largest search radius of this
+                // pass, or of the whole cell when the tile stays for later
+                // passes. A cell of a uniform grid (27 neighbour cells, all as
+                // wide as the reach) loses only the block's corners, which
+                // costs about what it saves, so it keeps every candidate.
+                const float reach2 = !cull ? 0.0f : cull_reach2(resident ? geom.y : wave_max(s.done ? 0.0f : s.Hi));
+                int kept_tot = 0;
                 ChunkRegs<1, DCH> R;
                 if (stream) {
                     cursor_seek(cu, A.p_rec, A.p_shift, 0);
@@ -499,28 +515,40 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                 for (int c0 = 0; c0 < nj; c0 += len) {
                     len = stream ? R.len : min(DCH, nj - c0);
                     const float4* tc = resident ? sj + c0 : sj;
+                    int slen;  // candidates of this chunk within reach
                     if (stream) {
                         mixed |= chunk_mass_differs(R, m0);
-                        // store this chunk (padded to DCH), put the next in flight
-                        commit_chunk_padded(sj + (resident ? c0 : 0), R);
+                        // store this chunk's candidates within reach (padded to
+                        // DCH), put the next chunk in flight
+                        if (cull) {
+                            slen = commit_chunk_culled_padded(sj + (resident ? c0 : 0), R, hw, reach2);
+                        } else {
+                            commit_chunk_padded(sj + (resident ? c0 : 0), R);
+                            slen = len;
+                        }
+                        // (a resident tile is scanned again by later passes)
+                        if (resident) kept_pack |= (unsigned)slen << (8 * (c0 / DCH));
                         const int nx = c0 + len;
                         if (nx < nj) {
                             cursor_seek(cu, A.p_rec, A.p_shift, nx);
                             fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH), marks);
                         }
+                    } else {
+                        slen = (int)((kept_pack >> (8 * (c0 / DCH))) & 0xffu);
                     }
+                    kept_tot += slen;
                     if (lpi == 2)
-                        scan_chunk<2>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
+                        scan_chunk<2>(tc + sub, slen, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else if (lpi == 4)
-                        scan_chunk<4>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
+                        scan_chunk<4>(tc + sub, slen, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else if (lpi == 8)
-                        scan_chunk<8>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
+                        scan_chunk<8>(tc + sub, slen, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     else
-                        scan_chunk<16>(tc + sub, len, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
+                        scan_chunk<16>(tc + sub, slen, xi.x, xi.y, xi.z, H2, lists, o, o_cap);
                     if (!resident) wave_sync_lds();
                 }
                 loaded = true;
-                cand_acc += (int64_t)active_groups * nj;
+                cand_acc += (int64_t)active_groups * kept_tot;
             }
             int nl = (int)((o - o_lane) >> 8);
             if (mixed) {
@@ -726,7 +754,8 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         if (lane == 0) k = (int)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_POP], 1ull);
         k = __shfl(k, 0, 64);
         if (k >= n_queued) break;
-        const int4 ci = A.cells[A.scan_cells[k]];
+        const int slot = A.scan_cells[k];
+        const int4 ci = A.cells[slot];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         NbrCursor cu;  // neighbour records 64 at a time
         cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
@@ -859,7 +888,8 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.f_out = f;
     A.nw_out = nw;
     A.status = status;
-    A.cells = static_cast<int4*>(c->cells.p);
+    A.cells = static_cast<int4*>(c->cells_d.p);
+    A.cell_geom = static_cast<float2*>(c->cell_geom.p);
     A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.ctr = ctr;

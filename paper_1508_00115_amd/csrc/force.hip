@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         bool loaded = false;
         int kept_single = 0;  // (single tile) candidates kept by the cell-box test
         const float2 geom = A.cell_geom[slot];
-        const float hw = cull_half_width(geom.x + delta), reach2 = cull_reach2(geom.y);
+        const float hw = cull_half_width(geom.x + delta), reach2_cell = cull_reach2(geom.y);
         double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};  // this cell's share of the box sums (lane 0)
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
@@ -194,6 +194,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float bal_i = MODE == FM_BALSARA ? A.jf[NF * (int64_t)i + 3].x : 1.0f;
             const float h2_i = i0v.w;
             const float hinv_i = i2v.w;
+            // candidates staged for this pass alone need only reach its
+            // particles' largest h (or their own); a tile kept for every pass
+            // reaches the cell's largest search radius
+            const float reach2 = single_tile ? reach2_cell : cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f)));
             const float hinv2_i = hinv_i * hinv_i;
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;

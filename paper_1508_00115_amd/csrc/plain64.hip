@@ -29,6 +29,7 @@ struct D64Args {
     const int* nd_box;
     const double* box_len;
     const uint32_t* p_start;
+    const uint32_t* p_cntd;   // per leaf: its records within its largest search radius (a prefix)
     const int* p_leaf;
     const int* p_code;
     const uint32_t* perm;
@@ -80,7 +81,7 @@ __device__ __forceinline__ void density64_one(const D64Args& A, int64_t i, D64Co
     int nev = 0;
     double S0, S1, M0, M1;
     int64_t cnt;
-    const uint32_t q0 = A.p_start[a], q1 = A.p_start[a + 1];
+    const uint32_t q0 = A.p_start[a], q1 = q0 + A.p_cntd[a];  // the density needs only this prefix
     int64_t cand = 0;
     for (;;) {
         S0 = S1 = M0 = M1 = 0.0;
@@ -354,6 +355,7 @@ void density_f64(sph_ctx* c, const double* mass, double* h, double* rho, double*
         A.nd_box = static_cast<int*>(c->nd_box.p);
         A.box_len = static_cast<double*>(c->box_len.p);
         A.p_start = static_cast<uint32_t*>(c->p_start.p);
+        A.p_cntd = static_cast<uint32_t*>(c->p_cntd.p);
         A.p_leaf = static_cast<int*>(c->p_leaf.p);
         A.p_code = static_cast<int*>(c->p_code.p);
         A.perm = static_cast<uint32_t*>(c->perm.p);

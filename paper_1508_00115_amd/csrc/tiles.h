@@ -454,6 +454,49 @@ __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<N
     return n;
 }
 
+// Store a fetched one-float4 chunk (x, y, z, m; shifted into the cell frame)
+// keeping only the candidates within reach of the cell's box (box_dist2 <
+// reach2), packed from slot 0, and fill the rest of the CAP slots with a far
+// position, so a loop may run to a multiple of its stride without a bounds
+// test. Returns how many were kept. A candidate farther from the box than
+// every search radius of the cell pairs with none of its particles.
+template <int CAP>
+__device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const ChunkRegs<1, CAP>& R, float hw,
+                                                          float reach2)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        float4 a = R.v[r][0];
+        a.x += R.s[r][0];
+        a.y += R.s[r][1];
+        a.z += R.s[r][2];
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < reach2;
+        const uint64_t m = __ballot(keep);
+        if (keep) sj[n + lanes_below(m)] = a;
+        n += __popcll(m);
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        if (t >= n) sj[t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return n;
+}
+
+// Largest v over the wavefront (every lane active).
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
 // the neighbour cell of each of its candidates by a binary search over the
 // lane-held prefix offsets, so all global loads of the chunk are independent
