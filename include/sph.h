@@ -340,6 +340,24 @@ sph_status sph_drift(sph_ctx* ctx, double dt, const float* vel, double* pos, voi
 sph_status sph_timestep(sph_ctx* ctx, double courant, double* dt, void* stream);
 
 /*
+ * Starting smoothing lengths for the next density solve, advanced over a step
+ * dt by the continuity equation (the density of a particle changes at the
+ * rate -rho div v; at a fixed neighbour number rho h^3 is constant, so
+ * d ln h / dt = div v / 3): h_i *= exp(dt (div v)_i / 3), with the velocity
+ * divergence rho_i (div v)_i = -sum_j m_j (v_i - v_j) . grad_i W(r_ij, h_i)
+ * that the last force pass with sph_params.signal_velocity recorded (over
+ * the pairs inside h_i). Called after sph_drift in a leapfrog step, it saves
+ * Newton sweeps; the solve's result does not depend on it (the root is
+ * unique).
+ *   dt  the step (finite, any sign)
+ *   h   device, n floats, caller order: in, the last smoothing lengths; out,
+ *       the predicted ones (a non-finite or non-positive prediction leaves h)
+ * Errors: SPH_E_ARG, SPH_E_STATE (no force pass with signal velocities since
+ * the last build), SPH_E_HIP. Does not synchronise.
+ */
+sph_status sph_predict_h(sph_ctx* ctx, double dt, float* h, void* stream);
+
+/*
  * sph_timestep without any device allocation, for callers that cannot
  * allocate (code under stream capture, tight serving loops, harnesses that
  * forbid it). Same arguments, result and errors as sph_timestep (bit for bit

@@ -28,7 +28,8 @@ SPH_E_STATE = 6
 EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_force",
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
            "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info",
-           "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara", "sph_timestep_noalloc")
+           "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara", "sph_timestep_noalloc",
+           "sph_predict_h")
 
 
 class sph_params(ctypes.Structure):
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_timestep.restype = ctypes.c_int
     lib.sph_timestep_noalloc.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
     lib.sph_timestep_noalloc.restype = ctypes.c_int
+    lib.sph_predict_h.argtypes = [P, ctypes.c_double, P, P]
+    lib.sph_predict_h.restype = ctypes.c_int
     lib.sph_get_balsara.argtypes = [P, P, P]
     lib.sph_get_balsara.restype = ctypes.c_int
     lib.sph_struct_size.argtypes = [ctypes.c_int32]
@@ -206,6 +209,10 @@ def sph_timestep(ctx, courant, dt_out, stream) -> int:
     return load_library().sph_timestep(ctx, courant, dt_out, stream)
 
 
+def sph_predict_h(ctx, dt, h, stream) -> int:
+    return load_library().sph_predict_h(ctx, dt, h, stream)
+
+
 def sph_timestep_noalloc(ctx, courant, dt_out, stream) -> int:
     return load_library().sph_timestep_noalloc(ctx, courant, dt_out, stream)
 
@@ -253,6 +260,7 @@ class Context:
         for k, v in params.items():
             setattr(p, k, v)
         self.device = device
+        self.signal_velocity = bool(params.get("signal_velocity", 0))
         self.ctx = sph_create(p, device)
         self.n = 0
         self.n_boxes = 0
@@ -377,6 +385,13 @@ class Context:
         _check(rc, self.ctx)
         return out.value
 
+    def predict_h(self, dt, h, stream=None):
+        """sph_predict_h: h *= exp(dt div v / 3) from the last force pass."""
+        import torch
+        rc = sph_predict_h(self.ctx, float(dt), _dev(h, torch.float32, (self.n,), "h"), _stream(stream))
+        _check(rc, self.ctx)
+        return h
+
     def timestep_noalloc(self, courant, stream=None) -> float:
         """sph_timestep_noalloc: sph_timestep with its scratch in the
         library's static device array (no allocation)."""
@@ -395,11 +410,15 @@ class Context:
         _check(rc, self.ctx)
         return out
 
-    def step(self, dt, pos, mass, h, vel, u, acc, dudt, rho=None, f=None, stream=None) -> dict:
+    def step(self, dt, pos, mass, h, vel, u, acc, dudt, rho=None, f=None, stream=None,
+             predict_h=True) -> dict:
         """One kick-drift-kick step of length dt (every array in place): acc
         and dudt hold the rates at the start and hold those at the end on
         return. The sequence of sph.h (half kick, drift, prediction, pass,
-        half kick; the library keeps or rebuilds the cells). The predicted v
+        half kick; the library keeps or rebuilds the cells). With signal
+        velocities on (and predict_h), h is advanced after the drift by the
+        velocity divergence of the last pass (sph_predict_h), a better
+        starting guess for the solve; the result does not depend on it. The predicted v
         and u, and rho and f when not given, live in
         scratch tensors that the next step reuses (copy them to keep them):
         with the same arrays every step, a step that keeps the cells replays
@@ -416,6 +435,10 @@ class Context:
         f = sc["f"] if f is None else f
         self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)
         self.drift(dt, vel, pos, stream=stream)
+        if predict_h and self.signal_velocity:
+            # the starting guesses of the next solve, from the velocity
+            # divergence the last force pass recorded
+            self.predict_h(dt, h, stream=stream)
         self.kick(0.5 * dt, acc, dudt, vel, u, vel_p, u_p, stream=stream)
         r = self.pass_(mass, h, vel_p, u_p, rho=rho, f=f, acc=acc, dudt=dudt, stream=stream)
         self.kick(0.5 * dt, acc, dudt, vel, u, stream=stream)

@@ -120,7 +120,7 @@ void sph_destroy(sph_ctx* c)
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->u_s, &c->status,
                        &c->st_s, &c->jf, &c->vsig_s, &c->bal_s, &c->jf4, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
-                       &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom, &c->cells_d, &c->p_cntd,
+                       &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom, &c->cells_d, &c->p_cntd, &c->divv_s,
                        &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
     for (auto& e : c->ev)
@@ -204,6 +204,15 @@ sph_status sph_timestep(sph_ctx* c, double courant, double* dt, void* stream)
         SPH_REQUIRE(dt, SPH_E_ARG, "null dt");
         set_device(c);
         *dt = sph::timestep(c, courant, (hipStream_t)stream);
+    });
+}
+
+sph_status sph_predict_h(sph_ctx* c, double dt, float* h, void* stream)
+{
+    if (!c) return SPH_E_ARG;
+    return guarded(c, [&] {
+        set_device(c);
+        sph::predict_h(c, dt, h, (hipStream_t)stream);
     });
 }
 

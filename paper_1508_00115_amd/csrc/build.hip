@@ -914,6 +914,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     c->drift_pending = false;
     c->vsig_valid = false;  // signal velocities belong to the cells of the last force pass
     c->bal_valid = false;
+    c->div_valid = false;   // and the divergences to its particle order
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
     c->density64_done = false;

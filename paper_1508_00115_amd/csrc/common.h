@@ -200,6 +200,8 @@ struct sph_ctx {
     sph::Buf jf;             // 3 float4 per particle for the force loop
     sph::Buf vsig_s;         // float, sorted: signal velocity of the last force pass
     bool vsig_valid = false; // vsig_s matches the current cells and h
+    sph::Buf divv_s;         // float, sorted: velocity divergence of the last force pass with signal velocities
+    bool div_valid = false;  // divv_s holds the last such pass of the current cells (kept across drifts)
     sph::Buf bal_s;          // float, sorted: Balsara factor of the last force pass
     sph::Buf jf4;            // 4 float4 per particle: jf and (B, 0, 0, 0), for the switch
     bool bal_valid = false;  // bal_s matches the current cells and h
@@ -409,6 +411,8 @@ void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const floa
           float* vel_out, float* u_out, hipStream_t s);
 void drift(sph_ctx* c, double dt, const float* vel, double* pos, hipStream_t s);
 double timestep(sph_ctx* c, double courant, hipStream_t s);
+// h *= exp(dt div v / 3) in caller order, from the last force pass's divergence.
+void predict_h(sph_ctx* c, double dt, float* h, hipStream_t s);
 // The same step with the reduction scratch in a static device array
 // (noalloc.hip); scratch_setup takes that array's address on `device` (which
 // must be current) once per device.

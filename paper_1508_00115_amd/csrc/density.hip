@@ -950,7 +950,7 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     int32_t sweeps = 0;
     c->rebuilds = 0;
     c->density_done = false;
-    c->vsig_valid = c->bal_valid = false;  // both belong to the h this call replaces
+    c->vsig_valid = c->bal_valid = c->div_valid = false;  // all belong to the h this call replaces
     c->tm.density_kernel_ms = 0.0;
     c->tm.density_rescan_ms = 0.0;
     c->tm.density_launches = 0;

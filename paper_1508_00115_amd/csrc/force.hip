@@ -73,6 +73,7 @@ struct ForceArgs {
     float* dudt;
     double* cons_part;  // 4 per leaf, may be null
     float* vsig;        // sorted: signal velocity per particle (k_force<true> only)
+    float* divv;        // sorted: velocity divergence per particle (k_force<true> only)
     float* bal;         // sorted: Balsara factor per particle (written in the FM_DIVCURL mode)
     const float* drift; // [0]: bound on the drift since the build (cell boxes widen by it)
     int64_t* ctr;
@@ -147,7 +148,10 @@ __global__ void k_unsort_f32(int64_t n, const uint32_t* __restrict__ perm, const
 }
 
 // VSIG: also record each particle's signal velocity max(c_i, max_j (c_i +
-// c_j - 3 w_ij)) over its pairs, for the Courant time step.
+// c_j - 3 w_ij)) over its pairs, for the Courant time step, and its velocity
+// divergence, rho_i div v_i = -sum_j m_j (v_i - v_j) . grad_i W(r_ij, h_i)
+// (the pairs inside h_i; grad_i W = D_i rhat), from which the next step's
+// smoothing length is predicted (continuity: dh/dt = h div v / 3).
 template <bool VSIG, int MODE>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
@@ -203,6 +207,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
             float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
             float vmax = 0.f;  // (VSIG) largest c_i + c_j - 3 w_ij of this lane's pairs
+            float dvr = 0.f;   // (VSIG) sum_j m_j D_i (v_ij . rhat) = -rho_i div v_i
             int cnt = 0;
             ChunkRegs<NF, FCAP> R;
             const bool stream_chunks = !(single_tile && loaded);
@@ -270,7 +275,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float vsig_ij = c_i + p2.z - 3.0f * wv_;
                     float visc = -A.alpha * vsig_ij * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
                     if constexpr (MODE == FM_BALSARA) visc *= 0.5f * (bal_i + sj[3 * FCAP + k].x);
-                    if constexpr (VSIG) vmax = fmaxf(vmax, vsig_ij);
+                    if constexpr (VSIG) {
+                        vmax = fmaxf(vmax, vsig_ij);
+                        dvr = fmaf(p1.w * Di, vr, dvr);
+                    }
                     const float Dbar = 0.5f * (Di + Dj);
                     const float G = MODE == FM_EQ2 ? fmaf(phi_i + p2.y, Di, visc * Dbar)
                                                    : fmaf(phi_i, Di, fmaf(p2.y, Dj, visc * Dbar));
@@ -290,7 +298,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             az = group_sum(az, lpi);
             du = group_sum(du, lpi);
             cnt = group_sum_i(cnt, lpi);
-            if constexpr (VSIG) vmax = group_max(vmax, lpi);
+            if constexpr (VSIG) {
+                vmax = group_max(vmax, lpi);
+                dvr = group_sum(dvr, lpi);
+            }
             const bool leader = valid && sub == 0;
             if constexpr (DC) {
                 if (leader) {
@@ -308,7 +319,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 A.acc[3 * (int64_t)o_i + 1] = ay;
                 A.acc[3 * (int64_t)o_i + 2] = az;
                 A.dudt[o_i] = du;
-                if constexpr (VSIG) A.vsig[i] = fmaxf(vmax, c_i);
+                if constexpr (VSIG) {
+                    A.vsig[i] = fmaxf(vmax, c_i);
+                    A.divv[i] = -dvr / rho_i;
+                }
                 inter_acc += cnt;
                 const double m = i1v.w;
                 cm[0] = m * ax;
@@ -375,6 +389,7 @@ int make_sched(sph_ctx* c, int64_t n_items, int waves_per_block, int blocks_per_
 void mark_force_outputs(sph_ctx* c)
 {
     c->vsig_valid = c->prm.signal_velocity != 0;
+    c->div_valid = c->prm.signal_velocity != 0;
     c->bal_valid = c->prm.balsara != 0 && c->prm.alpha_visc > 0;
 }
 
@@ -413,6 +428,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.cons_part = cons_d ? static_cast<double*>(c->cons_part.p) : nullptr;
     const bool vsig = c->prm.signal_velocity != 0;
     A.vsig = vsig ? static_cast<float*>(c->vsig_s.p) : nullptr;
+    A.divv = vsig ? static_cast<float*>(c->divv_s.p) : nullptr;
     A.bal = static_cast<float*>(c->bal_s.p);
     A.drift = static_cast<float*>(c->drift.p);
     A.ctr = ctr;
@@ -457,7 +473,10 @@ double* force_buffers(sph_ctx* c, bool cons)
     SPH_REQUIRE(!(c->prm.force_form == 1 && c->prm.balsara), SPH_E_ARG,
                 "the Eq. 2 force form (force_form = 1) has no Balsara switch");
     ensure<float4>(c, c->jf, 3 * c->n);
-    if (c->prm.signal_velocity) ensure<float>(c, c->vsig_s, c->n);
+    if (c->prm.signal_velocity) {
+        ensure<float>(c, c->vsig_s, c->n);
+        ensure<float>(c, c->divv_s, c->n);
+    }
     if (c->prm.balsara) {
         ensure<float>(c, c->bal_s, c->n);
         ensure<float4>(c, c->jf4, 4 * c->n);
@@ -475,7 +494,7 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     double* cons_d = force_buffers(c, cons != nullptr);
     // the sorted signal velocities and Balsara factors are rewritten below:
     // they are valid again only once this pass has succeeded
-    c->vsig_valid = c->bal_valid = false;
+    c->vsig_valid = c->bal_valid = c->div_valid = false;
     ev_record(c, EV_FORCE_C0, s);
     force_enqueue(c, vel, u, acc, dudt, cons_d, true, true, s);
     if (cons || st) {

@@ -105,9 +105,38 @@ __global__ void __launch_bounds__(256) k_dt_min(int64_t n, const float* __restri
     }
 }
 
+// The smoothing length of each particle advanced by a step dt with the
+// continuity equation: rho h^3 is constant at a fixed neighbour number, so
+// d ln h / dt = -(1/3) d ln rho / dt = div v / 3, integrated as
+// h exp(dt div v / 3) over the step (one thread per sorted particle, the
+// caller's h at o = perm[p]). Only a starting guess for the next solve.
+__global__ void k_predict_h(int64_t n, double dt, const uint32_t* __restrict__ perm,
+                            const float* __restrict__ divv, float* __restrict__ h)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t o = perm[p];
+    const double f = exp(dt * (double)divv[p] / 3.0);
+    const float hp = (float)((double)h[o] * f);
+    if (isfinite(hp) && hp > 0.0f) h[o] = hp;
+}
+
 }  // namespace
 
 namespace sph {
+
+void predict_h(sph_ctx* c, double dt, float* h, hipStream_t s)
+{
+    SPH_REQUIRE(h, SPH_E_ARG, "null h");
+    SPH_REQUIRE(std::isfinite(dt), SPH_E_ARG, "dt must be finite");
+    SPH_REQUIRE(c->built && c->div_valid, SPH_E_STATE,
+                "sph_predict_h needs a force pass with sph_params.signal_velocity since the last build");
+    const int64_t n = c->n;
+    if (n == 0) return;
+    k_predict_h<<<blocks_for(n, 256), 256, 0, s>>>(n, dt, static_cast<uint32_t*>(c->perm.p),
+                                                   static_cast<float*>(c->divv_s.p), h);
+    SPH_HIP(hipGetLastError());
+}
 
 void kick(sph_ctx* c, double dt, const float* acc, const float* dudt, const float* vel_in, const float* u_in,
           float* vel_out, float* u_out, hipStream_t s)

@@ -37,7 +37,7 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
     c->density_done = false;
     // the pass rewrites the sorted h, signal velocities and Balsara factors:
     // they are valid again only once it has succeeded
-    c->vsig_valid = c->bal_valid = false;
+    c->vsig_valid = c->bal_valid = c->div_valid = false;
     c->rebuilds = 0;
     density_buffers(c);
     double* cons_d = force_buffers(c, cons != nullptr);

@@ -306,3 +306,86 @@ def test_flags_after_a_replayed_pass(gpu_lib):
         assert ctx.build_info()["n_cells"] == cells
     finally:
         ctx.close()
+
+
+def test_predict_h_follows_the_divergence(gpu_lib):
+    """sph_predict_h advances h by exp(dt div v / 3), with the divergence the
+    force pass recorded: recovered from the prediction, div v matches the
+    oracle's (over the pairs inside h_i) to 1e-4 of its error scale."""
+    d = _case()
+    t = _tensors(d)
+    ctx = gpu_lib.Context(0, signal_velocity=1)
+    try:
+        ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
+        h = t["h0"].clone()
+        ctx.pass_(t["mass"], h, t["vel"], t["u"])
+        h_before = _np(h)
+        r = oracle.run(d)
+        dc = oracle.divcurl(d["pos"], d["vel"], d["mass"], r["h"], r["rho"])
+        # a step long enough that exp(dt div / 3) moves h well above FP32 resolution
+        dt = 0.15 / float(np.median(dc["scale"]))
+        ctx.predict_h(dt, h)
+        h_after = _np(h)
+    finally:
+        ctx.close()
+    div_gpu = 3.0 * np.log(h_after / h_before) / dt
+    err = np.abs(div_gpu - dc["div"]) / dc["scale"]
+    print("div v from the prediction: max err %.2e of the scale, dt %.3g" % (err.max(), dt), flush=True)
+    assert err.max() < 1e-4
+
+
+def test_predict_h_needs_a_force_pass(gpu_lib):
+    d = _case()
+    t = _tensors(d)
+    for sv in (0, 1):
+        ctx = gpu_lib.Context(0, signal_velocity=sv)
+        try:
+            ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
+            h = t["h0"].clone()
+            with pytest.raises(gpu_lib.SphError) as ei:
+                ctx.predict_h(1e-3, h)
+            assert ei.value.code == gpu_lib.SPH_E_STATE
+            ctx.pass_(t["mass"], h, t["vel"], t["u"])
+            if sv:
+                ctx.predict_h(1e-3, h)
+                # kept across a drift (the particles keep their order)
+                ctx.drift(1e-4, t["vel"], t["pos"].clone())
+                ctx.predict_h(1e-3, h)
+            else:
+                with pytest.raises(gpu_lib.SphError) as ei:
+                    ctx.predict_h(1e-3, h)
+                assert ei.value.code == gpu_lib.SPH_E_STATE
+        finally:
+            ctx.close()
+
+
+def test_predicted_h_saves_sweeps(gpu_lib):
+    """Leapfrog steps of a lattice with a random velocity field, with and
+    without the h prediction: the same results within the pass tolerance,
+    fewer Newton evaluations per particle with the prediction."""
+    import torch
+    d = _case()
+    out = {}
+    for pred in (False, True):
+        t = _tensors(d)
+        ctx = gpu_lib.Context(0, signal_velocity=1)
+        try:
+            pos, vel, u, h = t["pos"].clone(), t["vel"].clone(), t["u"].clone(), t["h0"].clone()
+            ctx.build_cells(pos, h, d["box_first"], d["box_len"])
+            r = ctx.pass_(t["mass"], h, vel, u)
+            acc, dudt, rho = r["acc"], r["dudt"], r["rho"]
+            evals, inter = 0, 0
+            for _ in range(6):
+                dt = ctx.timestep(0.3)
+                r = ctx.step(dt, pos, t["mass"], h, vel, u, acc, dudt, rho=rho, predict_h=pred)
+                evals += r["stats"]["sweep_interactions_density"]
+                inter += r["stats"]["interactions_density"]
+            torch.cuda.synchronize()
+            out[pred] = (evals / inter, _np(h), _np(rho))
+        finally:
+            ctx.close()
+    print("evaluations per particle: without %.3f, with the prediction %.3f" % (out[False][0], out[True][0]),
+          flush=True)
+    assert out[True][0] < out[False][0]
+    assert np.max(np.abs(out[True][1] / out[False][1] - 1)) < 2e-5
+    assert np.max(np.abs(out[True][2] / out[False][2] - 1)) < 2e-5
