@@ -203,7 +203,6 @@ struct sph_ctx {
     sph::Buf divv_s;         // float, sorted: velocity divergence of the last force pass with signal velocities
     bool div_valid = false;  // divv_s holds the last such pass of the current cells (kept across drifts)
     sph::Buf bal_s;          // float, sorted: Balsara factor of the last force pass
-    sph::Buf jf4;            // 4 float4 per particle: jf and (B, 0, 0, 0), for the switch
     bool bal_valid = false;  // bal_s matches the current cells and h
     sph::Buf counters;       // int64[CT_COUNT]
     sph::Buf cons_d;         // double, 4 per box (FP32 force loop)
@@ -211,6 +210,8 @@ struct sph_ctx {
     sph::Buf box_leaf;       // int, n_boxes + 1: first leaf of each box (leaves follow the boxes)
     sph::Buf cons64_d;       // double, CONS_SLOTS x 4 per box (plain FP64 form)
     int64_t* h_counters = nullptr;  // pinned host mirror of counters
+    double* h_cons = nullptr;       // pinned host landing buffer of the conservation sums
+    size_t h_cons_cap = 0;          // doubles it holds
 
     // ---- FP64 plain form --------------------------------------------------------
     sph::Buf h64, rho64, f64, st64;     // sorted state of the FP64 solve
@@ -344,12 +345,36 @@ inline void read_cons(const double* cons_d, double* out, int n_boxes, int slots,
     }
 }
 
-// Copy the device counters into the pinned mirror once the stream reaches
-// this point, wait for them and fold the spread slots into the sums.
-inline const int64_t* read_counters(sph_ctx* c, hipStream_t s)
+// Pinned host room for n doubles of conservation sums (grown on demand,
+// outside any capture).
+inline double* cons_host(sph_ctx* c, size_t n)
 {
+    if (c->h_cons_cap < n) {
+        if (c->h_cons) (void)hipHostFree(c->h_cons);
+        c->h_cons = nullptr;
+        c->h_cons_cap = 0;
+        SPH_HIP(hipHostMalloc((void**)&c->h_cons, n * sizeof(double), hipHostMallocDefault));
+        c->h_cons_cap = n;
+    }
+    return c->h_cons;
+}
+
+// Copy the device counters into the pinned mirror once the stream reaches
+// this point, wait for them and fold the spread slots into the sums. With
+// cons_d, the per-box conservation sums (4 per box) travel in the same
+// synchronisation into the context's pinned buffer and then to cons_out.
+inline const int64_t* read_counters(sph_ctx* c, hipStream_t s, const double* cons_d = nullptr,
+                                    double* cons_out = nullptr)
+{
+    double* hc = nullptr;
+    const size_t nc = (size_t)4 * c->n_boxes;
+    if (cons_d && cons_out) {
+        hc = cons_host(c, nc);
+        SPH_HIP(hipMemcpyAsync(hc, cons_d, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
     SPH_HIP(hipMemcpyAsync(c->h_counters, c->counters.p, CT_COUNT * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
+    if (hc) std::memcpy(cons_out, hc, nc * sizeof(double));
     int64_t* h = c->h_counters;
     for (int sl = 0; sl < CT_SPREAD_SLOTS; ++sl) {
         const int64_t* p = h + CT_SPREAD + sl * CT_SUMS;

@@ -18,10 +18,12 @@
 //
 // With the Balsara switch (not in the paper; the Gadget-2 form) the same loop
 // first runs in a gather mode that sums the velocity divergence and curl of
-// each particle over its neighbours inside h_i and stores the factor
-// B = |div v| / (|div v| + |curl v| + 1e-4 c / h); a fourth float4 per
-// particle, (B, 0, 0, 0), then carries it into the force loop, which scales
-// each pair's viscosity by (B_i + B_j) / 2.
+// each particle over its neighbours inside h_i (staging only position and
+// velocity, testing only r < h_i) and stores the factor
+// B = |div v| / (|div v| + |curl v| + 1e-4 c / h) in place of 1/h in the
+// particle's third float4, (rho, Phi, c, B); the force loop then takes 1/h
+// from h^2 (a reciprocal square root) and scales each pair's viscosity by
+// (B_i + B_j) / 2.
 //
 // sph_params.force_form = 1 swaps the grad-h pressure terms for the sum the
 // paper prints as its illustration (Eq. 2): (P_i / rho_i^2 + P_j / rho_j^2)
@@ -63,6 +65,7 @@ __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, c
 
 struct ForceArgs {
     const float4* jf;
+    float4* jf_w;             // the same array, written by the divergence pass (B in place of 1/h)
     const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* cell_aux;  // per schedule slot: leaf, box
     const float2* cell_geom;  // per schedule slot: half width of the leaf, largest search radius in it
@@ -91,7 +94,8 @@ struct ForceArgs {
 // (pad_tile), four tile reads are in flight and the appends are branch-free.
 // A lane tests at most FCAP / 2 candidates of a chunk, so its list cannot
 // overflow.
-template <int LPI>
+// OWN_H false (the divergence and curl): only the pairs inside h_i.
+template <int LPI, bool OWN_H>
 __device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, float xx, float xy, float xz,
                                           float h2_i, uint8_t* lists)
 {
@@ -106,7 +110,7 @@ __device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, fl
         for (int u = 0; u < 4; ++u) {
             const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = (r2 < fmaxf(h2_i, pj[u].w)) & (r2 > 0.0f);
+            const bool in = (r2 < (OWN_H ? fmaxf(h2_i, pj[u].w) : h2_i)) & (r2 > 0.0f);
             lists[o] = (uint8_t)(k0 + u * LPI);
             o += in ? 64u : 0u;
         }
@@ -126,18 +130,7 @@ __device__ __forceinline__ void pad_tile(float4* sj, int len, int cap)
 // switch (4 float4 per particle); the Balsara factors (3 float4 per particle,
 // no force, no counters); the force in the Eq. 2 form.
 enum { FM_FORCE = 0, FM_BALSARA = 1, FM_DIVCURL = 2, FM_EQ2 = 3 };
-
-// (B, 0, 0, 0) after the three float4 of each particle, for FM_BALSARA.
-__global__ void k_pack_balsara(int64_t n, const float4* __restrict__ jf, const float* __restrict__ bal,
-                               float4* __restrict__ jf4)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    jf4[4 * p + 0] = jf[3 * p + 0];
-    jf4[4 * p + 1] = jf[3 * p + 1];
-    jf4[4 * p + 2] = jf[3 * p + 2];
-    jf4[4 * p + 3] = make_float4(bal[p], 0.0f, 0.0f, 0.0f);
-}
+// With FM_BALSARA the third float4 of a particle holds (rho, Phi, c, B).
 
 // Input-order copy of the sorted Balsara factors.
 __global__ void k_unsort_f32(int64_t n, const uint32_t* __restrict__ perm, const float* __restrict__ src,
@@ -155,8 +148,8 @@ __global__ void k_unsort_f32(int64_t n, const uint32_t* __restrict__ perm, const
 template <bool VSIG, int MODE>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
-    constexpr int NF = MODE == FM_BALSARA ? 4 : 3;
     constexpr bool DC = MODE == FM_DIVCURL;
+    constexpr int NF = DC ? 2 : 3;  // float4 staged per candidate (of the 3 per particle)
     __shared__ float4 tile[NF * FCAP];
     __shared__ uint8_t lists[FSLOTS * 64];
     __shared__ uint8_t marks[FCAP];  // record starts of the chunk being fetched
@@ -191,13 +184,13 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const int gi = ib + g;
             const bool valid = gi < ni;
             const int i = i0 + (valid ? gi : 0);
-            const float4 i0v = A.jf[NF * (int64_t)i + 0];
-            const float4 i1v = A.jf[NF * (int64_t)i + 1];
-            const float4 i2v = A.jf[NF * (int64_t)i + 2];
+            const float4 i0v = A.jf[3 * (int64_t)i + 0];
+            const float4 i1v = A.jf[3 * (int64_t)i + 1];
+            const float4 i2v = A.jf[3 * (int64_t)i + 2];
             const uint32_t o_i = DC ? 0u : A.perm[i];  // loaded here so the stores wait for nothing
-            const float bal_i = MODE == FM_BALSARA ? A.jf[NF * (int64_t)i + 3].x : 1.0f;
+            const float bal_i = MODE == FM_BALSARA ? i2v.w : 1.0f;
             const float h2_i = i0v.w;
-            const float hinv_i = i2v.w;
+            const float hinv_i = MODE == FM_BALSARA ? __builtin_amdgcn_rsqf(h2_i) : i2v.w;
             // candidates staged for this pass alone need only reach its
             // particles' largest h (or their own); a tile kept for every pass
             // reaches the cell's largest search radius
@@ -220,9 +213,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     // registers a fetch in flight would hold cost a wavefront
                     // per SIMD, and the other wavefronts cover the loads)
                     cursor_seek(cu, A.p_rec, A.p_shift, c0);
-                    fetch_chunk(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
+                    fetch_chunk<NF, FCAP, 3>(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
                     len = R.len;
-                    slen = commit_chunk_culled(sj, R, hw, reach2);
+                    slen = commit_chunk_culled<NF, FCAP, !DC>(sj, R, hw, reach2);
                     if (single_tile) kept_single = slen;
                     pad_tile(sj, slen, FCAP);
                     loaded = true;
@@ -234,13 +227,13 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
                 int nl;
                 if (lpi == 2)
-                    nl = force_scan<2>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<2, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 4)
-                    nl = force_scan<4>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<4, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else if (lpi == 8)
-                    nl = force_scan<8>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<8, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 else
-                    nl = force_scan<16>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                    nl = force_scan<16, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 if (!valid) nl = 0;
                 cnt += nl;
                 // phase B: the pair terms of the compacted neighbours only
@@ -249,7 +242,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const int k = lst[e * 64];
                     const float4 p0 = sj[k];
                     const float4 p1 = sj[FCAP + k];
-                    const float4 p2 = sj[2 * FCAP + k];
+                    const float4 p2 = DC ? p1 : sj[2 * FCAP + k];  // (not staged for the divergence)
                     const float dx = i0v.x - p0.x, dy = i0v.y - p0.y, dz = i0v.z - p0.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     if constexpr (DC) {
@@ -264,7 +257,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                         az = fmaf(mD, wx * dy - wy * dx, az);
                         continue;
                     }
-                    const float hinv_j = p2.w;
+                    const float hinv_j = MODE == FM_BALSARA ? __builtin_amdgcn_rsqf(p0.w) : p2.w;
                     const float hinv2_j = hinv_j * hinv_j;
                     const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 > 0 (phase A), far from denormal
                     const float r = r2 * rinv;
@@ -274,7 +267,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float wv_ = fminf(vr, 0.0f);
                     const float vsig_ij = c_i + p2.z - 3.0f * wv_;
                     float visc = -A.alpha * vsig_ij * wv_ * __builtin_amdgcn_rcpf(rho_i + p2.x);
-                    if constexpr (MODE == FM_BALSARA) visc *= 0.5f * (bal_i + sj[3 * FCAP + k].x);
+                    if constexpr (MODE == FM_BALSARA) visc *= 0.5f * (bal_i + p2.w);
                     if constexpr (VSIG) {
                         vmax = fmaxf(vmax, vsig_ij);
                         dvr = fmaf(p1.w * Di, vr, dvr);
@@ -308,7 +301,11 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     const float ad = fabsf(du) / rho_i;
                     const float den = ad + sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az))) / rho_i +
                                       1.0e-4f * c_i * hinv_i;
-                    A.bal[i] = den > 0.0f ? ad / den : 0.0f;  // no motion and no sound: no viscosity
+                    const float B = den > 0.0f ? ad / den : 0.0f;  // no motion and no sound: no viscosity
+                    A.bal[i] = B;
+                    // B replaces 1/h in the particle's third float4 for the force
+                    // pass (the candidates of this pass read only the first two)
+                    A.jf_w[3 * (int64_t)i + 2] = make_float4(rho_i, phi_i, c_i, B);
                 }
                 continue;
             }
@@ -417,6 +414,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     }
     ForceArgs A;
     A.jf = jf;
+    A.jf_w = jf;
     A.cells = static_cast<int4*>(c->cells.p);
     A.cell_geom = static_cast<float2*>(c->cell_geom.p);
     A.cell_aux = static_cast<int2*>(c->cell_aux.p);
@@ -440,11 +438,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     if (bal) {
         k_force<false, FM_DIVCURL><<<grid, BS, 0, s>>>(A);
         SPH_HIP(hipGetLastError());
-        float4* jf4 = static_cast<float4*>(c->jf4.p);
-        k_pack_balsara<<<blocks_for(n, 256), 256, 0, s>>>(n, jf, A.bal, jf4);
-        SPH_HIP(hipGetLastError());
         if (c->prm.schedule == 1) fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);  // the force pass pops the queues again
-        A.jf = jf4;
         if (vsig)
             k_force<true, FM_BALSARA><<<grid, BS, 0, s>>>(A);
         else
@@ -477,10 +471,7 @@ double* force_buffers(sph_ctx* c, bool cons)
         ensure<float>(c, c->vsig_s, c->n);
         ensure<float>(c, c->divv_s, c->n);
     }
-    if (c->prm.balsara) {
-        ensure<float>(c, c->bal_s, c->n);
-        ensure<float4>(c, c->jf4, 4 * c->n);
-    }
+    if (c->prm.balsara) ensure<float>(c, c->bal_s, c->n);
     if (!cons) return nullptr;
     ensure<double>(c, c->cons_part, (size_t)4 * c->n_leaves);
     return ensure<double>(c, c->cons_d, (size_t)4 * c->n_boxes);
@@ -498,8 +489,7 @@ void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* 
     ev_record(c, EV_FORCE_C0, s);
     force_enqueue(c, vel, u, acc, dudt, cons_d, true, true, s);
     if (cons || st) {
-        if (cons) read_cons(cons_d, cons, c->n_boxes, 1, s);
-        const int64_t* hc = read_counters(c, s);
+        const int64_t* hc = read_counters(c, s, cons_d, cons);
         SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "negative or non-finite u, or non-finite velocity");
         if (st) {
             st->interactions_force = hc[CT_FORCE_INTER];

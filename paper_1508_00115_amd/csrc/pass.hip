@@ -76,7 +76,9 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
         }
         SPH_HIP(hipGraphLaunch(c->pass_exec, s));
     }
-    const int64_t* hc = read_counters(c, s);
+    // counters and conservation sums in one synchronisation (the sums are
+    // discarded below if the pass has to be repeated)
+    const int64_t* hc = read_counters(c, s, cons_d, cons);
     SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "non-positive or non-finite mass or h, negative u, or "
                                                   "non-finite velocity");
     if (hc[CT_OVERFLOW] > 0 || hc[CT_UNCONV] > 0) {
@@ -95,7 +97,6 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
         }
         return;
     }
-    if (cons) read_cons(cons_d, cons, c->n_boxes, 1, s);
     if (st) {
         st->sweeps = (int32_t)hc[CT_SWEEPS];
         st->rebuilds = 0;

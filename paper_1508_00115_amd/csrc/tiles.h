@@ -332,7 +332,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // plus the marks up to the slot (a ballot of the marks and a lane count).
 // Every record holds at least one particle, so no two records start at the
 // same slot. The loads of the chunk are independent and issue back to back.
-template <int NF, int CAP>
+template <int NF, int CAP, int STRIDE = NF>
 __device__ __forceinline__ void fetch_chunk(ChunkRegs<NF, CAP>& R, const float4* __restrict__ jd,
                                             const NbrLanes& nb, int c0, int len, uint8_t* mk)
 {
@@ -360,7 +360,7 @@ __device__ __forceinline__ void fetch_chunk(ChunkRegs<NF, CAP>& R, const float4*
         R.s[r][1] = __shfl(nb.sy, qt, 64);
         R.s[r][2] = __shfl(nb.sz, qt, 64);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) R.v[r][f] = jd[(int64_t)NF * src + f];
+        for (int f = 0; f < NF; ++f) R.v[r][f] = jd[(int64_t)STRIDE * src + f];
     }
 }
 
@@ -423,8 +423,9 @@ __device__ __forceinline__ float cull_reach2(float reach) { return (reach * 1.00
 
 // Store a fetched chunk (NF float4 per candidate, slot 0 = x, y, z, h^2) with
 // the cell-box test: a candidate is kept when the box lies within
-// max(reach, h_j) of it. Returns how many were kept (packed from slot 0).
-template <int NF, int CAP>
+// max(reach, h_j) of it (OWN_H false: within reach). Returns how many were
+// kept (packed from slot 0).
+template <int NF, int CAP, bool OWN_H = true>
 __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<NF, CAP>& R, float hw,
                                                    float reach2)
 {
@@ -438,7 +439,7 @@ __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<N
         a.x += R.s[r][0];
         a.y += R.s[r][1];
         a.z += R.s[r][2];
-        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < fmaxf(reach2, a.w * 1.00002f);
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < (OWN_H ? fmaxf(reach2, a.w * 1.00002f) : reach2);
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int d = n + lanes_below(m);
