@@ -195,6 +195,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             // particles' largest h (or their own); a tile kept for every pass
             // reaches the cell's largest search radius
             const float reach2 = single_tile ? reach2_cell : cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f)));
+            // ... from the box around this pass's particles, or the cell's box
+            const CullBox box = single_tile ? cell_box(hw) : pass_box(i0v.x, i0v.y, i0v.z, valid);
             const float hinv2_i = hinv_i * hinv_i;
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     cursor_seek(cu, A.p_rec, A.p_shift, c0);
                     fetch_chunk<NF, FCAP, 3>(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
                     len = R.len;
-                    slen = commit_chunk_culled<NF, FCAP, !DC>(sj, R, hw, reach2);
+                    slen = commit_chunk_culled<NF, FCAP, !DC>(sj, R, box, reach2);
                     if (single_tile) kept_single = slen;
                     pad_tile(sj, slen, FCAP);
                     loaded = true;

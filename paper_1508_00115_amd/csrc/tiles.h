@@ -409,6 +409,56 @@ __device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<
 // of them: the 3x3x3 block of cells is a cube, the region within reach of the
 // cell a rounded box about a quarter smaller. (The density loop stages
 // without it: there the compaction cost more than the tests it saved.)
+// An axis-aligned box in the cell frame for the cull of staged candidates:
+// the cell's own box (centre 0, half width hw in every axis, widened by the
+// drift bound) or the bounding box of the particles of one pass.
+struct CullBox {
+    float cx, cy, cz, hx, hy, hz;
+};
+
+__device__ __forceinline__ CullBox cell_box(float hw)
+{
+    CullBox b;
+    b.cx = b.cy = b.cz = 0.0f;
+    b.hx = b.hy = b.hz = hw;
+    return b;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v);
+
+// Bounding box of the positions of the lanes with `in` set (every lane must
+// take part). The half widths are rounded up by a relative 1e-6 of the
+// coordinates, so that the FP32 centre and widths still contain every
+// position; the cull's reach has its own margin.
+__device__ __forceinline__ CullBox pass_box(float x, float y, float z, bool in)
+{
+    const float BIG = 3.0e38f;
+    const float lx = wave_min(in ? x : BIG), hx = wave_max(in ? x : -BIG);
+    const float ly = wave_min(in ? y : BIG), hy = wave_max(in ? y : -BIG);
+    const float lz = wave_min(in ? z : BIG), hz = wave_max(in ? z : -BIG);
+    CullBox b;
+    b.cx = 0.5f * (lx + hx);
+    b.cy = 0.5f * (ly + hy);
+    b.cz = 0.5f * (lz + hz);
+    b.hx = 0.5f * (hx - lx) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lx), fabsf(hx));
+    b.hy = 0.5f * (hy - ly) * 1.000001f + 1.0e-6f * fmaxf(fabsf(ly), fabsf(hy));
+    b.hz = 0.5f * (hz - lz) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lz), fabsf(hz));
+    return b;
+}
+
+__device__ __forceinline__ float box_dist2(float x, float y, float z, const CullBox& b)
+{
+    const float gx = fmaxf(fabsf(x - b.cx) - b.hx, 0.0f), gy = fmaxf(fabsf(y - b.cy) - b.hy, 0.0f),
+                gz = fmaxf(fabsf(z - b.cz) - b.hz, 0.0f);
+    return fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+}
+
 __device__ __forceinline__ float box_dist2(float x, float y, float z, float hw)
 {
     const float gx = fmaxf(fabsf(x) - hw, 0.0f), gy = fmaxf(fabsf(y) - hw, 0.0f), gz = fmaxf(fabsf(z) - hw, 0.0f);
@@ -426,7 +476,7 @@ __device__ __forceinline__ float cull_reach2(float reach) { return (reach * 1.00
 // max(reach, h_j) of it (OWN_H false: within reach). Returns how many were
 // kept (packed from slot 0).
 template <int NF, int CAP, bool OWN_H = true>
-__device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<NF, CAP>& R, float hw,
+__device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<NF, CAP>& R, const CullBox& box,
                                                    float reach2)
 {
     const int lane = threadIdx.x & 63;
@@ -439,7 +489,7 @@ __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<N
         a.x += R.s[r][0];
         a.y += R.s[r][1];
         a.z += R.s[r][2];
-        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < (OWN_H ? fmaxf(reach2, a.w * 1.00002f) : reach2);
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, box) < (OWN_H ? fmaxf(reach2, a.w * 1.00002f) : reach2);
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int d = n + lanes_below(m);
