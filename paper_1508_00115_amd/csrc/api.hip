@@ -115,7 +115,7 @@ void sph_destroy(sph_ctx* c)
     sph::Buf* all[] = {&c->box_first, &c->box_len, &c->box_G, &c->box_top_base, &c->box_hmax, &c->pos_w,
                        &c->hguess, &c->keys, &c->keys_alt, &c->perm, &c->perm_alt, &c->pos_s, &c->xrel,
                        &c->Hs, &c->leaf_of, &c->unassigned, &c->head, &c->scan1, &c->nid, &c->nd_start,
-                       &c->nd_count, &c->nd_hmax, &c->nd_wide, &c->nd_child0, &c->nd_child1, &c->nd_leaf, &c->nd_box,
+                       &c->nd_count, &c->nd_hmax, &c->nd_wide, &c->nd_child0, &c->nd_child1, &c->nd_parent, &c->nd_leaf, &c->nd_box,
                        &c->nd_level, &c->nd_coord, &c->nflag, &c->nscan, &c->top, &c->lf_start, &c->lf_count,
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->u_s, &c->status,

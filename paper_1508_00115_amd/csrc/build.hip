@@ -14,8 +14,8 @@
 // tree as the end of section 3.1 describes -- with the periodic image of each.
 //
 // All of it runs on the GPU: integer keys, a radix sort, one pass of small
-// kernels per tree level, and a stack-based walk per leaf. The host only reads
-// back counts to size buffers.
+// kernels per tree level, and a stack-based walk per (leaf, surrounding top
+// cell). The host only reads back counts to size buffers.
 #include "common.h"
 
 #include <algorithm>
@@ -24,7 +24,6 @@
 namespace {
 
 constexpr int BS = 256;
-constexpr int MAX_STACK = 96;
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v)
 {
@@ -178,7 +177,7 @@ __global__ void k_sorted_H(int64_t n, const uint32_t* __restrict__ perm, const f
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     Hs[p] = margin * hg[perm[p]];
-    leaf_tmp[p] = -1;
+    if (leaf_tmp) leaf_tmp[p] = -1;
 }
 
 __global__ void k_fill_int(int64_t n, int* __restrict__ a, int v)
@@ -271,13 +270,30 @@ __global__ void k_lvl_nodes(int64_t n, const uint64_t* __restrict__ keys, const 
 // wide few then sit in small cells with a long reach (pairs are found by box
 // distance with each cell's own largest radius), instead of a few outliers
 // keeping every particle of a dense region in one huge cell.
-__global__ void k_lvl_decide(int64_t M, int64_t node_base, int level, int max_level, int leaf_target,
-                             const int* __restrict__ nd_count, const int* __restrict__ nd_wide,
-                             uint32_t* __restrict__ nflag, int* __restrict__ nd_child0,
-                             int* __restrict__ nd_child1)
+// The per-level kernels below run over a bound on the level's node count
+// that the host knows (the launch), and take the count itself (*dM) from the
+// device: slots k in [*dM, bound) hold no node.
+__global__ void k_lvl_clear(int64_t node_base, int64_t bound, int* __restrict__ nd_count,
+                            unsigned* __restrict__ nd_hmax, int* __restrict__ nd_wide)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= bound) return;
+    nd_count[node_base + k] = 0;
+    nd_hmax[node_base + k] = 0u;
+    nd_wide[node_base + k] = 0;
+}
+
+__global__ void k_lvl_decide(int64_t bound, const uint32_t* __restrict__ dM, int64_t node_base, int level,
+                             int max_level, int leaf_target, const int* __restrict__ nd_count,
+                             const int* __restrict__ nd_wide, uint32_t* __restrict__ nflag,
+                             int* __restrict__ nd_child0, int* __restrict__ nd_child1)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
+    if (k >= bound) return;
+    if (k >= (int64_t)*dM) {  // no node: not a leaf either (the scan of nflag counts the leaves)
+        nflag[k] = 0u;
+        return;
+    }
     const int64_t id = node_base + k;
     const int cnt = nd_count[id];
     const bool split = level < max_level && cnt > leaf_target && 8 * nd_wide[id] <= cnt;
@@ -286,12 +302,12 @@ __global__ void k_lvl_decide(int64_t M, int64_t node_base, int level, int max_le
     nd_child1[id] = -1;
 }
 
-__global__ void k_lvl_leaves(int64_t M, int64_t node_base, int64_t leaf_base,
+__global__ void k_lvl_leaves(int64_t bound, const uint32_t* __restrict__ dM, int64_t node_base, int64_t leaf_base,
                              const uint32_t* __restrict__ nflag, const uint32_t* __restrict__ nscan,
                              int* __restrict__ nd_leaf, int* __restrict__ lo2node)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
+    if (k >= bound || k >= (int64_t)*dM) return;
     const int64_t id = node_base + k;
     if (nflag[k]) {
         const int64_t lo = leaf_base + nscan[k];
@@ -312,27 +328,31 @@ __global__ void k_lvl_assign(int64_t n, const int* __restrict__ nid, const int* 
 }
 
 // Children of the split nodes of the previous level: the level-l nodes holding
-// the first and last particle of each split parent.
+// the first and last particle of each split parent (level-l nodes are
+// numbered in particle order, so a parent's children are the ids between),
+// and each child's parent.
 __global__ void k_lvl_children(int64_t Mprev, int64_t base_prev, const int* __restrict__ nd_leaf,
                                const int* __restrict__ nd_start, const int* __restrict__ nd_count,
                                const int* __restrict__ nid, int* __restrict__ nd_child0,
-                               int* __restrict__ nd_child1)
+                               int* __restrict__ nd_child1, int* __restrict__ nd_parent)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Mprev) return;
     const int64_t id = base_prev + k;
     if (nd_leaf[id] >= 0) return;
     const int s = nd_start[id];
-    nd_child0[id] = nid[s];
-    nd_child1[id] = nid[s + nd_count[id] - 1];
+    const int c0 = nid[s], c1 = nid[s + nd_count[id] - 1];
+    nd_child0[id] = c0;
+    nd_child1[id] = c1;
+    for (int c = c0; c <= c1; ++c) nd_parent[c] = (int)id;
 }
 
-__global__ void k_top_table(int64_t M, const int* __restrict__ nd_box, const int* __restrict__ nd_coord,
-                            const int* __restrict__ box_G, const int64_t* __restrict__ box_top_base,
-                            int* __restrict__ top)
+__global__ void k_top_table(int64_t bound, const uint32_t* __restrict__ dM, const int* __restrict__ nd_box,
+                            const int* __restrict__ nd_coord, const int* __restrict__ box_G,
+                            const int64_t* __restrict__ box_top_base, int* __restrict__ top)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= M) return;
+    if (id >= bound || id >= (int64_t)*dM) return;
     const int b = nd_box[id];
     const int G = box_G[b];
     const int64_t t = ((int64_t)nd_coord[3 * id] * G + nd_coord[3 * id + 1]) * G + nd_coord[3 * id + 2];
@@ -392,161 +412,239 @@ __device__ __forceinline__ void node_geom(int id, const int* nd_coord, const int
     for (int a = 0; a < 3; ++a) c[a] = ((double)nd_coord[3 * id + a] + 0.5) * w;
 }
 
-// Walk the tree from the 27 top cells around leaf a and list every leaf whose
-// cell box lies within max(Hmax_a, Hmax_leaf) of a's cell box. fill == false
-// counts (all records into p_cnt, the density's into p_cntd), fill == true
-// writes the list at p_start[a]. The list is split in two: first the leaves
-// within Hmax_a of a's box (p_cntd[a] of them), then those that only reach a
-// with their own radius. The density of a's particles (a gather over j
-// inside h_i <= Hmax_a) needs only the first part; the force (pairs inside
-// max(h_i, h_j)) takes both. The top cells are visited in three classes of
-// (dx + dy + dz) mod 3, nine cells each, every class spread over the whole
-// 3x3x3 block: the hot kernels stage the list in consecutive chunks, and a
-// chunk that samples the whole neighbourhood gives every particle a similar
-// share of its neighbours (even lane lists).
-__device__ __forceinline__ uint32_t partners_of(int64_t a, int fill, const int* __restrict__ lf_node,
-                           const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
-                           const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
-                           const int* __restrict__ nd_leaf, const int* __restrict__ nd_child0,
-                           const int* __restrict__ nd_child1, const int* __restrict__ top,
-                           const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
-                           const double* __restrict__ box_len, const uint32_t* __restrict__ p_start,
-                           int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
-                           int2* __restrict__ p_rec, const int* __restrict__ lf_start,
-                           const int* __restrict__ lf_count, const uint32_t* __restrict__ p_cntd,
-                           uint32_t& cnt_dens, int64_t* __restrict__ ctr)
+// The 27 top cells around a leaf's own, in the order its partner list visits
+// them: three classes of (dx + dy + dz) mod 3, nine cells each, every class
+// spread over the whole 3x3x3 block. The hot kernels stage a list in
+// consecutive chunks, and a chunk that samples the whole neighbourhood gives
+// every particle a similar share of its neighbours (even lane lists).
+__constant__ signed char NB27[27][3] = {
+    {-1, -1, -1}, {-1, 0, 1}, {-1, 1, 0}, {0, -1, 1}, {0, 0, 0}, {0, 1, -1}, {1, -1, 0}, {1, 0, -1}, {1, 1, 1},
+    {-1, -1, 0}, {-1, 0, -1}, {-1, 1, 1}, {0, -1, -1}, {0, 0, 1}, {0, 1, 0}, {1, -1, 1}, {1, 0, 0}, {1, 1, -1},
+    {-1, -1, 1}, {-1, 0, 0}, {-1, 1, -1}, {0, -1, 0}, {0, 0, -1}, {0, 1, 1}, {1, -1, -1}, {1, 0, 1}, {1, 1, 0}};
+
+struct TreeView {
+    const int* nd_coord;
+    const int* nd_level;
+    const unsigned* nd_hmax;
+    const int* nd_leaf;
+    const int* nd_child0;
+    const int* nd_child1;
+    const int* nd_parent;
+    int n_nodes;
+};
+
+struct RecordOut {
+    int* p_leaf;
+    float4* p_shift;
+    int* p_code;
+    int2* p_rec;
+    const int* lf_start;
+    const int* lf_count;
+};
+
+// Depth-first walk below top cell T (seen through the periodic image shift S)
+// for the leaves of partner lists of leaf a (centre cA, width wA, largest
+// search radius HA): every leaf whose box lies within max(HA, its own largest
+// radius) of a's box. nd counts those within HA, nf the others. FILL writes
+// them from od and of on, and nj adds up their particles. The walk needs no
+// stack: a split node's children have consecutive ids, so after a node the
+// walk goes to its next sibling, or climbs to the first ancestor below T that
+// has one. Children come in increasing id order. A tree that would take more
+// steps than it has nodes is reported (CT_BAD_INPUT) and the walk ends.
+template <bool FILL>
+__device__ __forceinline__ void walk_top(int T, const double S[3], int code, const double cA[3], double wA,
+                                         double wtop, float HA, const TreeView& tv, const RecordOut& ro,
+                                         uint32_t od, uint32_t of, uint32_t& nd, uint32_t& nf, int& nj,
+                                         int64_t* __restrict__ ctr)
 {
-    const int A = lf_node[a];
-    const int b = nd_box[A];
-    const int G = box_G[b];
-    const double L = box_len[b];
-    const double wtop = L / G;
-    double cA[3], wA;
-    node_geom(A, nd_coord, nd_level, wtop, cA, wA);
-    const float HA = __uint_as_float(nd_hmax[A]);
-    const int lA = nd_level[A];
-    const int tA[3] = {nd_coord[3 * A] >> lA, nd_coord[3 * A + 1] >> lA, nd_coord[3 * A + 2] >> lA};
     const double eps = 1e-9 * wtop;
-    uint32_t cnt = 0, cd = 0;  // records so far: all, and those within Hmax_a
-    const uint32_t base = fill ? p_start[a] : 0u;
-    const uint32_t base_f = fill ? base + p_cntd[a] : 0u;  // first record only the force needs
-    int stack[MAX_STACK];
-    for (int cls = 0; cls < 3; ++cls)
-    for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dz = -1; dz <= 1; ++dz) {
-                if ((dx + dy + dz + 3) % 3 != cls) continue;
-                int t[3] = {tA[0] + dx, tA[1] + dy, tA[2] + dz};
-                int s[3];
+    int X = T;
+    for (int steps = 0;; ++steps) {
+        if (steps > tv.n_nodes) {
+            atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
+            return;
+        }
+        double cX[3], wX;
+        node_geom(X, tv.nd_coord, tv.nd_level, wtop, cX, wX);
+        double d2 = 0.0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    s[k] = 0;
-                    if (t[k] < 0) { t[k] += G; s[k] = -1; }
-                    else if (t[k] >= G) { t[k] -= G; s[k] = 1; }
-                }
-                const int T = top[box_top_base[b] + ((int64_t)t[0] * G + t[1]) * G + t[2]];
-                if (T < 0) continue;
-                const double S[3] = {s[0] * L, s[1] * L, s[2] * L};
-                int sp = 0;
-                stack[sp++] = T;
-                while (sp > 0) {
-                    const int X = stack[--sp];
-                    double cX[3], wX;
-                    node_geom(X, nd_coord, nd_level, wtop, cX, wX);
-                    double d2 = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        double g = fabs(cX[k] + S[k] - cA[k]) - 0.5 * (wA + wX) - eps;
-                        g = g > 0.0 ? g : 0.0;
-                        d2 += g * g;
-                    }
-                    const double R = (double)fmaxf(HA, __uint_as_float(nd_hmax[X]));
-                    if (d2 >= R * R) continue;
-                    const int lf = nd_leaf[X];
-                    if (lf >= 0) {
-                        const bool dens = d2 < (double)HA * (double)HA;
-                        if (fill) {
-                            const uint32_t o = dens ? base + cd : base_f + (cnt - cd);
-                            p_leaf[o] = lf;
-                            p_rec[o] = make_int2(lf_start[lf], lf_count[lf]);
-                            p_shift[o] = make_float4((float)(cX[0] + S[0] - cA[0]), (float)(cX[1] + S[1] - cA[1]),
-                                                     (float)(cX[2] + S[2] - cA[2]), 0.0f);
-                            p_code[o] = image_code(s[0], s[1], s[2]);
-                        }
-                        ++cnt;
-                        cd += dens ? 1u : 0u;
-                    } else {
-                        const int c0 = nd_child0[X], c1 = nd_child1[X];
-                        if (sp + (c1 - c0 + 1) > MAX_STACK) {
-                            atomicAdd((unsigned long long*)&ctr[CT_BAD_INPUT], 1ull);
-                            continue;
-                        }
-                        for (int c = c1; c >= c0; --c) stack[sp++] = c;
-                    }
-                }
+        for (int k = 0; k < 3; ++k) {
+            double g = fabs(cX[k] + S[k] - cA[k]) - 0.5 * (wA + wX) - eps;
+            g = g > 0.0 ? g : 0.0;
+            d2 += g * g;
+        }
+        const double R = (double)fmaxf(HA, __uint_as_float(tv.nd_hmax[X]));
+        if (d2 < R * R) {
+            const int lf = tv.nd_leaf[X];
+            if (lf < 0) {  // split: its first child next
+                X = tv.nd_child0[X];
+                continue;
             }
-    cnt_dens = cd;
-    return cnt;
+            const bool dens = d2 < (double)HA * (double)HA;
+            if (FILL) {
+                const uint32_t o = dens ? od + nd : of + nf;
+                const int cnt = ro.lf_count[lf];
+                ro.p_leaf[o] = lf;
+                ro.p_rec[o] = make_int2(ro.lf_start[lf], cnt);
+                ro.p_shift[o] = make_float4((float)(cX[0] + S[0] - cA[0]), (float)(cX[1] + S[1] - cA[1]),
+                                            (float)(cX[2] + S[2] - cA[2]), 0.0f);
+                ro.p_code[o] = code;
+                nj += cnt;
+            }
+            nd += dens ? 1u : 0u;
+            nf += dens ? 0u : 1u;
+        }
+        while (X != T && X == tv.nd_child1[tv.nd_parent[X]]) X = tv.nd_parent[X];
+        if (X == T) return;
+        ++X;
+    }
 }
 
-
-__global__ void k_partners(int64_t n_leaves, int fill, const int* __restrict__ lf_node,
-                           const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
-                           const int* __restrict__ nd_box, const unsigned* __restrict__ nd_hmax,
-                           const int* __restrict__ nd_leaf, const int* __restrict__ nd_child0,
-                           const int* __restrict__ nd_child1, const int* __restrict__ top,
-                           const int64_t* __restrict__ box_top_base, const int* __restrict__ box_G,
-                           const double* __restrict__ box_len, uint32_t* __restrict__ p_cnt,
-                           uint32_t* __restrict__ p_cntd, const uint32_t* __restrict__ p_start,
-                           int* __restrict__ p_leaf, float4* __restrict__ p_shift, int* __restrict__ p_code,
-                           int2* __restrict__ p_rec, const int* __restrict__ lf_start,
-                           const int* __restrict__ lf_count, int64_t* __restrict__ ctr)
+// Sums over the 32 lanes of a half-wavefront.
+__device__ __forceinline__ uint32_t half_sum(uint32_t v)
 {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t cnt = 0, cnt_dens = 0;
-    if (a < n_leaves)
-        cnt = partners_of(a, fill, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf, nd_child0, nd_child1,
-                          top, box_top_base, box_G, box_len, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
-                          lf_count, p_cntd, cnt_dens, ctr);
+    for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive prefix sum over the 32 lanes of a half-wavefront.
+__device__ __forceinline__ uint32_t half_excl_scan(uint32_t v)
+{
+    const int q = threadIdx.x & 31;
+    uint32_t s = v;
+    for (int o = 1; o < 32; o <<= 1) {
+        const uint32_t t = __shfl_up(s, o, 32);
+        if (q >= o) s += t;
+    }
+    return s - v;
+}
+
+constexpr int PBS = 256;
+
+// Counters k0 + k of the workgroup's values v[k]: the total for k < n_sum,
+// the largest value for the others. One atomic per counter and workgroup,
+// into its spread slot (one per wavefront would be 10^5 atomics on a few
+// cache lines for the largest sets). Every thread of the group must call it.
+template <int NV>
+__device__ __forceinline__ void block_counters(const int64_t (&v)[NV], int64_t (&red)[4][PBS / 64],
+                                               int64_t* __restrict__ ctr, int k0, int n_sum)
+{
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        int64_t x = v[k];
+        for (int o = 32; o >= 1; o >>= 1) {
+            const int64_t y = __shfl_xor(x, o, 64);
+            x = k < n_sum ? x + y : max(x, y);
+        }
+        if ((threadIdx.x & 63) == 0) red[k][w] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        int64_t x = red[k][0];
+        for (int q = 1; q < PBS / 64; ++q) x = k < n_sum ? x + red[k][q] : max(x, red[k][q]);
+        unsigned long long* slot = (unsigned long long*)&ctr_slot(ctr)[k0 + k];
+        if (k < n_sum) {
+            if (x != 0) atomicAdd(slot, (unsigned long long)x);
+        } else {
+            atomicMax(slot, (unsigned long long)x);
+        }
+    }
+}
+
+// The cell-pair tasks (section 3.1: the neighbouring cells of each leaf, found
+// with a tree), one half-wavefront per leaf and one lane per surrounding top
+// cell. fill == 0 counts each leaf's records (all into p_cnt, the density's
+// into p_cntd). fill == 1 writes the list at p_start[a], in two parts: first
+// the leaves within Hmax_a of a's box (p_cntd[a] of them), then those that
+// reach a only with their own radius. The density of a's particles (a gather
+// over j inside h_i <= Hmax_a) needs only the first part; the force (pairs
+// inside max(h_i, h_j)) takes both. Within each part the records follow the
+// NB27 order of their top cells, depth-first below each, so each lane writes
+// from the sum of the counts of the lanes before it (it walks its subtree
+// twice: to count, then to write). The fill also writes the leaf's schedule
+// key (sk != null), its cost particles x candidates as 12 bits of its float
+// (exponent and four bits of mantissa) in decreasing order, prefixed with
+// the XCD whose Morton range holds the leaf when xcd_local; and the build's
+// shape counters (CT_B_*).
+__global__ void __launch_bounds__(PBS) k_partners(int64_t nl, int fill, const int* __restrict__ lf_node,
+                                                  TreeView tv, const int* __restrict__ nd_box,
+                                                  const int* __restrict__ top,
+                                                  const int64_t* __restrict__ box_top_base,
+                                                  const int* __restrict__ box_G, const double* __restrict__ box_len,
+                                                  uint32_t* __restrict__ p_cnt, uint32_t* __restrict__ p_cntd,
+                                                  const uint32_t* __restrict__ p_start, RecordOut ro,
+                                                  uint64_t* __restrict__ sk, uint32_t* __restrict__ sv,
+                                                  int xcd_local, int64_t* __restrict__ ctr)
+{
+    const int q = threadIdx.x & 31;
+    const int64_t a = ((int64_t)blockIdx.x * PBS + threadIdx.x) >> 5;
+    const bool leaf_ok = a < nl;
+    uint32_t nd = 0, nf = 0;
+    int T = -1, code = 0;
+    double S[3] = {0.0, 0.0, 0.0}, cA[3] = {0.0, 0.0, 0.0}, wA = 0.0, wtop = 1.0;
+    float HA = 0.0f;
+    if (leaf_ok && q < 27) {
+        const int A = lf_node[a];
+        const int b = nd_box[A];
+        const int G = box_G[b];
+        const double L = box_len[b];
+        wtop = L / G;
+        node_geom(A, tv.nd_coord, tv.nd_level, wtop, cA, wA);
+        HA = __uint_as_float(tv.nd_hmax[A]);
+        const int lA = tv.nd_level[A];
+        int t[3], s[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            t[k] = (tv.nd_coord[3 * A + k] >> lA) + NB27[q][k];
+            s[k] = 0;
+            if (t[k] < 0) { t[k] += G; s[k] = -1; }
+            else if (t[k] >= G) { t[k] -= G; s[k] = 1; }
+            S[k] = s[k] * L;
+        }
+        T = top[box_top_base[b] + ((int64_t)t[0] * G + t[1]) * G + t[2]];
+        code = image_code(s[0], s[1], s[2]);
+    }
+    int nj = 0;
+    if (T >= 0) walk_top<false>(T, S, code, cA, wA, wtop, HA, tv, ro, 0u, 0u, nd, nf, nj, ctr);
+    __shared__ int64_t red[4][PBS / 64];
     if (!fill) {
-        if (a < n_leaves) {
-            p_cnt[a] = cnt;
-            p_cntd[a] = cnt_dens;
+        const uint32_t td = half_sum(nd), tf = half_sum(nf);
+        if (leaf_ok && q == 0) {
+            p_cnt[a] = td + tf;
+            p_cntd[a] = td;
         }
         // the records of all leaves in 64 bits: the list offsets are a 32-bit scan
-        int64_t v = cnt;
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long*)&ctr[CT_B_PAIRS64], (unsigned long long)v);
+        const int64_t v = (leaf_ok && q == 0) ? (int64_t)(td + tf) : 0;
+        const int64_t r[1] = {v};
+        block_counters<1>(r, red, ctr, CT_B_PAIRS64, 1);
+        return;
     }
-}
-
-// Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
-// Cost of each leaf's cell tasks (particles x candidates) as a sort key that
-// orders by decreasing cost (positive floats order like their bit patterns).
-// xcd_local: the key is prefixed with the XCD whose Morton range holds the
-// leaf (leaves are in Morton order), so the sort keeps each XCD's range
-// together and orders it by cost. Also the build's shape counters (CT_B_*).
-__global__ void k_cell_cost(int64_t nl, const int* __restrict__ lf_count, const uint32_t* __restrict__ p_start,
-                            const int* __restrict__ p_leaf, int xcd_local, uint64_t* __restrict__ keys,
-                            uint32_t* __restrict__ vals, int64_t* __restrict__ ctr)
-{
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int ni = 0, np = 0, nj = 0;
-    if (a < nl) {
-        ni = lf_count[a];
+    const uint32_t sd = half_excl_scan(nd), sf = half_excl_scan(nf);
+    if (T >= 0) {
+        const uint32_t base = p_start[a];
+        uint32_t cd = 0, cf = 0;
+        walk_top<true>(T, S, code, cA, wA, wtop, HA, tv, ro, base + sd, base + p_cntd[a] + sf, cd, cf, nj, ctr);
+    }
+    nj = (int)half_sum((uint32_t)nj);
+    int ni = 0, np = 0;
+    if (leaf_ok) {
+        ni = ro.lf_count[a];
         np = (int)(p_start[a + 1] - p_start[a]);
-        for (uint32_t p = p_start[a]; p < p_start[a + 1]; ++p) nj += lf_count[p_leaf[p]];
-        const float cost = (float)ni * (float)nj;
-        uint64_t x = 0;
-        if (xcd_local)
-            while (x < 7 && a >= sph::xcd_start(nl, (int)x + 1)) ++x;
-        keys[a] = (x << 32) | (0xffffffffull - __float_as_uint(cost));
-        vals[a] = (uint32_t)a;
+        if (sk && q == 0) {
+            const float cost = (float)ni * (float)nj;
+            uint64_t x = 0;
+            if (xcd_local)
+                while (x < 7 && a >= sph::xcd_start(nl, (int)x + 1)) ++x;
+            sk[a] = (x << 12) | (uint64_t)(0xfffu - (__float_as_uint(cost) >> 19));
+            sv[a] = (uint32_t)a;
+        }
     }
-    ctr_wave_add(ctr, CT_B_CAND_PAIRS, (int64_t)ni * nj);
-    ctr_wave_max(ctr, CT_B_MAX_NI, ni);
-    ctr_wave_max(ctr, CT_B_MAX_NP, np);
-    ctr_wave_max(ctr, CT_B_MAX_NJ, nj);
+    const bool lead = leaf_ok && q == 0;
+    // CT_B_CAND_PAIRS, then the maxima CT_B_MAX_NI, _NP, _NJ
+    const int64_t r[4] = {lead ? (int64_t)ni * nj : 0, lead ? ni : 0, lead ? np : 0, lead ? nj : 0};
+    block_counters<4>(r, red, ctr, CT_B_CAND_PAIRS, 1);
 }
 
 // Schedule slots. by_cost != null and deal: the leaf of cost rank r goes to
@@ -577,6 +675,7 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, i
     cell_geom[slot] = make_float2((float)(0.5 * w), lf_hmax[a]);
 }
 
+// Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
 __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ pos_w,
                               const int* __restrict__ leaf_of, const int* __restrict__ lf_node,
                               const int* __restrict__ nd_coord, const int* __restrict__ nd_level,
@@ -626,14 +725,6 @@ int ceil_log2(uint64_t v)
     int b = 0;
     while ((1ull << b) < v) ++b;
     return b;
-}
-
-uint32_t read_u32(const uint32_t* d, hipStream_t s)
-{
-    uint32_t v = 0;
-    SPH_HIP(hipMemcpyAsync(&v, d, 4, hipMemcpyDeviceToHost, s));
-    SPH_HIP(hipStreamSynchronize(s));
-    return v;
 }
 
 }  // namespace
@@ -700,8 +791,12 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_keys<<<blocks_for(n, BS), BS, 0, s>>>(n, static_cast<double*>(c->pos_w.p), box_first, nb, box_len,
                                             box_G, kl, keys, perm);
     SPH_HIP(hipGetLastError());
+    // Sorted by box and top cell first; the Morton bits below the top grid
+    // matter only where a top cell splits, and uniform sets have none (the
+    // particles of a top-cell leaf keep their input order). Where one does,
+    // the whole key is sorted after level 0, below.
     const int key_bits = c->bits_box + c->bits_top + 3 * c->levels;
-    radix_sort(c, keys, perm, keys_alt, perm_alt, n, key_bits, s);
+    radix_sort(c, keys, perm, keys_alt, perm_alt, n, key_bits, s, 3 * c->levels);
 
     float* Hs = ensure<float>(c, c->Hs, n);
     int* leaf_tmp = ensure<int>(c, c->lf_tmp, n);
@@ -710,26 +805,30 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     SPH_HIP(hipGetLastError());
 
     // ---- tree, level by level ---------------------------------------------------------------
+    // One read-back per level: its node count M and leaf count K (the two
+    // halves of one counter word). The level's kernels run over a bound the
+    // host already has: the top cells at level 0, eight children per split
+    // node of the level above after that.
     uint32_t* head = ensure<uint32_t>(c, c->head, n + 1);
     uint32_t* excl = ensure<uint32_t>(c, c->scan1, n + 1);
     int* nid = ensure<int>(c, c->nid, n);
-    uint32_t* d_tot = reinterpret_cast<uint32_t*>(&ctr[CT_TOTAL]);
+    uint32_t* d_M = reinterpret_cast<uint32_t*>(&ctr[CT_TOTAL]);
+    uint32_t* d_K = d_M + 1;
     int* top = ensure<int>(c, c->top, (size_t)c->n_top);
     k_fill_int<<<blocks_for(c->n_top, BS), BS, 0, s>>>(c->n_top, top, -1);
     SPH_HIP(hipGetLastError());
 
     int64_t node_base = 0, leaf_base = 0, prev_base = 0, prev_M = 0;
+    int64_t bound = std::min<int64_t>(n, c->n_top);
     // level-order leaf id -> node; parked in lf_start's buffer until the leaves
     // are renumbered in Morton order
     int* lo2node = ensure<int>(c, c->lf_start, n + 1);
-    for (int level = 0; level <= c->levels; ++level) {
+    for (int level = 0; level <= c->levels && bound > 0; ++level) {
         const int shift = 3 * (c->levels - level);
         k_lvl_head<<<blocks_for(n, BS), BS, 0, s>>>(n, keys, leaf_tmp, shift, head);
         SPH_HIP(hipGetLastError());
-        scan_exclusive(c, head, excl, n, d_tot, s);
-        const int64_t M = read_u32(d_tot, s);
-        if (M == 0) break;
-        const int64_t need = node_base + M;
+        scan_exclusive(c, head, excl, n, d_M, s);
+        const int64_t need = node_base + bound;
         // node ids are int and index 3 ints of nd_coord each
         SPH_REQUIRE(need <= (int64_t)(INT32_MAX / 3), SPH_E_ARG,
                     "the cell tree needs more than " + std::to_string(INT32_MAX / 3) + " nodes");
@@ -741,6 +840,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
             grow_keep<int>(c, c->nd_wide, cap, node_base, s);
             grow_keep<int>(c, c->nd_child0, cap, node_base, s);
             grow_keep<int>(c, c->nd_child1, cap, node_base, s);
+            grow_keep<int>(c, c->nd_parent, cap, node_base, s);
             grow_keep<int>(c, c->nd_leaf, cap, node_base, s);
             grow_keep<int>(c, c->nd_box, cap, node_base, s);
             grow_keep<int>(c, c->nd_level, cap, node_base, s);
@@ -753,51 +853,67 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         int* nd_wide = static_cast<int*>(c->nd_wide.p);
         int* nd_child0 = static_cast<int*>(c->nd_child0.p);
         int* nd_child1 = static_cast<int*>(c->nd_child1.p);
+        int* nd_parent = static_cast<int*>(c->nd_parent.p);
         int* nd_leaf = static_cast<int*>(c->nd_leaf.p);
         int* nd_box = static_cast<int*>(c->nd_box.p);
         int* nd_level = static_cast<int*>(c->nd_level.p);
         int* nd_coord = static_cast<int*>(c->nd_coord.p);
-        SPH_HIP(hipMemsetAsync(nd_count + node_base, 0, (size_t)M * 4, s));
-        SPH_HIP(hipMemsetAsync(nd_hmax + node_base, 0, (size_t)M * 4, s));
-        SPH_HIP(hipMemsetAsync(nd_wide + node_base, 0, (size_t)M * 4, s));
+        const unsigned gb = (unsigned)blocks_for(bound, BS);
+        k_lvl_clear<<<gb, BS, 0, s>>>(node_base, bound, nd_count, nd_hmax, nd_wide);
+        SPH_HIP(hipGetLastError());
         k_lvl_nodes<<<blocks_for(n, BS), BS, 0, s>>>(n, keys, leaf_tmp, head, excl, Hs, level, kl, node_base,
                                                      nid, nd_start, nd_count, nd_hmax, nd_wide, nd_box, nd_level,
                                                      nd_coord, box_G, box_len, (float)c->prm.cell_ratio);
         SPH_HIP(hipGetLastError());
         if (level == 0) {
-            k_top_table<<<blocks_for(M, BS), BS, 0, s>>>(M, nd_box, nd_coord, box_G, box_top_base, top);
+            k_top_table<<<gb, BS, 0, s>>>(bound, d_M, nd_box, nd_coord, box_G, box_top_base, top);
             SPH_HIP(hipGetLastError());
         } else {
             k_lvl_children<<<blocks_for(prev_M, BS), BS, 0, s>>>(prev_M, prev_base, nd_leaf, nd_start,
-                                                                 nd_count, nid, nd_child0, nd_child1);
+                                                                 nd_count, nid, nd_child0, nd_child1,
+                                                                 nd_parent);
             SPH_HIP(hipGetLastError());
         }
-        uint32_t* nflag = ensure<uint32_t>(c, c->nflag, M + 1);
-        uint32_t* nscan = ensure<uint32_t>(c, c->nscan, M + 1);
-        k_lvl_decide<<<blocks_for(M, BS), BS, 0, s>>>(M, node_base, level, c->levels, c->prm.leaf_target,
-                                                      nd_count, nd_wide, nflag, nd_child0, nd_child1);
+        uint32_t* nflag = ensure<uint32_t>(c, c->nflag, bound + 1);
+        uint32_t* nscan = ensure<uint32_t>(c, c->nscan, bound + 1);
+        k_lvl_decide<<<gb, BS, 0, s>>>(bound, d_M, node_base, level, c->levels, c->prm.leaf_target, nd_count,
+                                       nd_wide, nflag, nd_child0, nd_child1);
         SPH_HIP(hipGetLastError());
-        scan_exclusive(c, nflag, nscan, M, d_tot, s);
-        const int64_t K = read_u32(d_tot, s);
-        k_lvl_leaves<<<blocks_for(M, BS), BS, 0, s>>>(M, node_base, leaf_base, nflag, nscan, nd_leaf,
-                                                      lo2node);
+        scan_exclusive(c, nflag, nscan, bound, d_K, s);
+        k_lvl_leaves<<<gb, BS, 0, s>>>(bound, d_M, node_base, leaf_base, nflag, nscan, nd_leaf, lo2node);
         SPH_HIP(hipGetLastError());
         k_lvl_assign<<<blocks_for(n, BS), BS, 0, s>>>(n, nid, nd_leaf, leaf_tmp);
         SPH_HIP(hipGetLastError());
+        uint32_t mk[2] = {0u, 0u};
+        SPH_HIP(hipMemcpyAsync(mk, d_M, sizeof(mk), hipMemcpyDeviceToHost, s));
+        SPH_HIP(hipStreamSynchronize(s));
+        const int64_t M = mk[0], K = mk[1];
+        // every particle not yet in a leaf heads or joins a node of this level,
+        // so the bound (its parents' children) holds them; a larger count is a bug
+        SPH_REQUIRE(M <= bound && K <= M, SPH_E_HIP, "cell tree level outside its bound");
+        if (level == 0 && K < M) {
+            // A top cell splits: order the particles by the whole key. The
+            // sort is stable and keeps every top cell's range, so the level-0
+            // nodes, their sums and each particle's node and leaf stay as
+            // they are; only the sorted search radii follow the new order.
+            radix_sort(c, keys, perm, keys_alt, perm_alt, n, key_bits, s);
+            k_sorted_H<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<float*>(c->hguess.p), margin, Hs,
+                                                        nullptr);
+            SPH_HIP(hipGetLastError());
+        }
         prev_base = node_base;
         prev_M = M;
         node_base += M;
         leaf_base += K;
-        if (K == M) break;  // every node of this level is a leaf
+        bound = std::min<int64_t>(8 * (M - K), n);  // children of this level's split nodes
     }
     c->n_nodes = node_base;
 
     // ---- leaves in Morton (particle) order ---------------------------------------------------
     k_leaf_head<<<blocks_for(n, BS), BS, 0, s>>>(n, leaf_tmp, head);
     SPH_HIP(hipGetLastError());
-    scan_exclusive(c, head, excl, n, d_tot, s);
-    const int64_t nl = read_u32(d_tot, s);
-    SPH_REQUIRE(nl == leaf_base, SPH_E_HIP, "leaf numbering mismatch");
+    scan_exclusive(c, head, excl, n, nullptr, s);
+    const int64_t nl = leaf_base;  // the leaves of all levels, one per run of leaf_tmp
     c->n_leaves = nl;
     int* leaf_of = ensure<int>(c, c->leaf_of, n);
     // lo2node lives in lf_start's buffer; move it aside before lf_start is written
@@ -832,20 +948,18 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     const int* nd_leaf = static_cast<int*>(c->nd_leaf.p);
     const int* nd_child0 = static_cast<int*>(c->nd_child0.p);
     const int* nd_child1 = static_cast<int*>(c->nd_child1.p);
-    k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 0, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
-                                                 nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, p_cntd, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                 nullptr, nullptr, ctr);
+    const TreeView tv{nd_coord, nd_level, nd_hmax, nd_leaf, nd_child0, nd_child1,
+                      static_cast<int*>(c->nd_parent.p), (int)c->n_nodes};
+    const unsigned p_blocks = (unsigned)blocks_for(nl * 32, PBS);
+    k_partners<<<p_blocks, PBS, 0, s>>>(nl, 0, lf_node, tv, nd_box, top, box_top_base, box_G, box_len, p_cnt,
+                                        p_cntd, nullptr, RecordOut{}, nullptr, nullptr, 0, ctr);
     SPH_HIP(hipGetLastError());
     scan_exclusive(c, p_cnt, p_start, nl, p_start + nl, s);
     uint32_t np = 0;
-    int64_t bad2 = 0;
-    int64_t np64 = 0;
     SPH_HIP(hipMemcpyAsync(&np, p_start + nl, 4, hipMemcpyDeviceToHost, s));
-    SPH_HIP(hipMemcpyAsync(&bad2, &ctr[CT_BAD_INPUT], 8, hipMemcpyDeviceToHost, s));
-    SPH_HIP(hipMemcpyAsync(&np64, &ctr[CT_B_PAIRS64], 8, hipMemcpyDeviceToHost, s));
-    SPH_HIP(hipStreamSynchronize(s));
-    SPH_REQUIRE(bad2 == 0, SPH_E_HIP, "tree walk stack overflow");
+    const int64_t* hc0 = read_counters(c, s);  // synchronises: np is in
+    const int64_t bad2 = hc0[CT_BAD_INPUT], np64 = hc0[CT_B_PAIRS64];
+    SPH_REQUIRE(bad2 == 0, SPH_E_HIP, "inconsistent cell tree: a walk took more steps than the tree has nodes");
     SPH_REQUIRE(np64 <= (int64_t)UINT32_MAX && (int64_t)np == np64, SPH_E_ARG,
                 std::to_string(np64) + " (cell, neighbour cell) records: more than 2^32 - 1 cannot be indexed");
     c->n_pairs = np;
@@ -853,25 +967,21 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     float4* p_shift = ensure<float4>(c, c->p_shift, np);
     int* p_code = ensure<int>(c, c->p_code, np);
     int2* p_rec = ensure<int2>(c, c->p_rec, np);
-    k_partners<<<blocks_for(nl, 64), 64, 0, s>>>(nl, 1, lf_node, nd_coord, nd_level, nd_box, nd_hmax, nd_leaf,
-                                                 nd_child0, nd_child1, top, box_top_base, box_G, box_len,
-                                                 p_cnt, p_cntd, p_start, p_leaf, p_shift, p_code, p_rec, lf_start,
-                                                 lf_count, ctr);
+    const int order = c->prm.cell_order;
+    const bool by_cost = order != 1;
+    uint64_t* sk = ensure<uint64_t>(c, c->sched_key, nl);
+    uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
+    k_partners<<<p_blocks, PBS, 0, s>>>(nl, 1, lf_node, tv, nd_box, top, box_top_base, box_G, box_len, p_cnt,
+                                        p_cntd, p_start, RecordOut{p_leaf, p_shift, p_code, p_rec, lf_start, lf_count},
+                                        by_cost ? sk : nullptr, sv, order == 2 ? 1 : 0, ctr);
     SPH_HIP(hipGetLastError());
 
     // ---- work schedule: leaves by decreasing cost dealt out to the XCDs, Morton ranges, or Morton
     //      ranges each ordered by decreasing cost --------------------------------------------------
     {
-        uint64_t* sk = ensure<uint64_t>(c, c->sched_key, nl);
         uint64_t* ska = ensure<uint64_t>(c, c->sched_key_alt, nl);
-        uint32_t* sv = ensure<uint32_t>(c, c->sched_val, nl);
         uint32_t* sva = ensure<uint32_t>(c, c->sched_val_alt, nl);
-        const int order = c->prm.cell_order;
-        const bool by_cost = order != 1;
-        k_cell_cost<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_count, p_start, p_leaf, order == 2 ? 1 : 0, sk, sv,
-                                                      ctr);
-        SPH_HIP(hipGetLastError());
-        if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, order == 2 ? 35 : 32, s);
+        if (by_cost) radix_sort(c, sk, sv, ska, sva, nl, order == 2 ? 15 : 12, s);
         int4* cells = ensure<int4>(c, c->cells, nl);
         int2* cell_aux = ensure<int2>(c, c->cell_aux, nl);
         float2* cell_geom = ensure<float2>(c, c->cell_geom, nl);

@@ -68,12 +68,12 @@ enum {
     CT_B_MAX_NI = 11,      // build: largest leaf (max)
     CT_B_MAX_NP = 12,      // build: longest neighbour-cell list (max)
     CT_B_MAX_NJ = 13,      // build: most candidates of a leaf (max)
+    CT_B_PAIRS64 = 14,     // build: (cell, neighbour cell) records, counted in 64 bits
     CT_SUMS = 16,        // entries [0, CT_SUMS) have spread slots
     // single entries
-    CT_TOTAL = 16,       // scratch for device-computed totals read by the host
+    CT_TOTAL = 16,       // scratch for device-computed totals read by the host (two uint32)
     CT_SCAN_CELLS = 17,  // cells queued for the re-scanning density kernel
     CT_SCAN_POP = 18,    // next queued cell to take
-    CT_B_PAIRS64 = 19,   // build: (cell, neighbour cell) records, counted in 64 bits
     CT_DT_MIN = 20,      // sph_timestep: smallest h / v_sig (float bits in the low word)
     CT_QUEUE = 32,       // 8 work-queue heads (one per XCD), one 64-byte line each: CT_QUEUE + 8 q
     CT_SPREAD = 96,      // CT_SPREAD_SLOTS copies of the sums, CT_SUMS entries each
@@ -165,7 +165,8 @@ struct sph_ctx {
     sph::Buf head, scan1;    // uint32 per particle
     sph::Buf nid;            // int per particle: node at the current level
     // nodes (all levels, level-major)
-    sph::Buf nd_start, nd_count, nd_hmax, nd_wide, nd_child0, nd_child1, nd_leaf, nd_box, nd_level, nd_coord;
+    sph::Buf nd_start, nd_count, nd_hmax, nd_wide, nd_child0, nd_child1, nd_parent, nd_leaf, nd_box, nd_level,
+        nd_coord;
     int64_t node_cap = 0;
     sph::Buf nflag, nscan;   // per-node temporaries of one level
     sph::Buf top;            // int: node of each (box, top cell), -1 if empty
@@ -392,10 +393,11 @@ inline const int64_t* read_counters(sph_ctx* c, hipStream_t s, const double* con
 // sum of all inputs is written there (device pointer).
 void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                     hipStream_t s);
-// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
-// Results end in keys/vals (the alt buffers are scratch).
+// Stable LSD radix sort of (key, value) pairs on bits [lo_bit, bits) of the
+// keys (8-bit digits from lo_bit up). Results end in keys/vals (the alt
+// buffers are scratch).
 void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
-                uint32_t* vals_alt, int64_t n, int bits, hipStream_t s);
+                uint32_t* vals_alt, int64_t n, int bits, hipStream_t s, int lo_bit = 0);
 
 void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len,
                  int64_t n, const double* pos, const float* h_guess, hipStream_t s);

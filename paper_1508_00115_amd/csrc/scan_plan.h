@@ -52,4 +52,10 @@ inline ScanPlan scan_plan(int64_t n)
 // block per tile of level k (which is the number of sums level k + 1 holds).
 inline int64_t scan_apply_grid(const ScanPlan& P, std::size_t k) { return scan_tiles(P.lv[k].count); }
 
+// A plan of one level (at most SCAN_TILE tiles) takes two launches: the
+// reduce, then the apply over the input, in which block b adds up the raw
+// tile sums 0 .. b - 1 itself (they fit one block's pass) instead of reading
+// sum b of a scanned level.
+inline bool scan_one_level(const ScanPlan& P) { return P.lv.size() == 1; }
+
 }  // namespace sph

@@ -61,13 +61,27 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_reduce(const uint32_t* __restr
 }
 
 // Scans each tile and adds the scanned tile offset. sums may be null when there
-// is a single tile. Writes the grand total from the last tile.
+// is a single tile. With raw_sums > 0, sums holds the raw sums of the
+// raw_sums (<= SCAN_TILE) tiles, and block b adds up sums 0 .. b - 1 itself.
+// Writes the grand total from the last tile.
 __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
                                                         const uint32_t* __restrict__ sums,
-                                                        uint32_t* __restrict__ total)
+                                                        uint32_t* __restrict__ total, int64_t raw_sums)
 {
     __shared__ uint32_t lds4[4];
     if ((int64_t)blockIdx.x * SCAN_TILE >= n) return;  // whole block: no tile, no sum to read
+    uint32_t tile_off = 0;
+    if (raw_sums > 0) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            const int64_t t = (int64_t)threadIdx.x * SCAN_ITEMS + k;
+            if (t < (int64_t)blockIdx.x && t < raw_sums) s += sums[t];
+        }
+        block_excl_scan(s, lds4, tile_off);  // the block total: sums before this tile
+    } else if (sums) {
+        tile_off = sums[blockIdx.x];
+    }
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
@@ -78,7 +92,7 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t* in, uint
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan(s, lds4, tot) + (sums ? sums[blockIdx.x] : 0u);
+    uint32_t run = block_excl_scan(s, lds4, tot) + tile_off;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         int64_t i = base + k;
@@ -193,7 +207,7 @@ void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ui
     }
     const ScanPlan P = scan_plan(n);
     if (P.lv.empty()) {
-        k_scan_apply<<<1, SCAN_BS, 0, s>>>(in, out, n, nullptr, total);
+        k_scan_apply<<<1, SCAN_BS, 0, s>>>(in, out, n, nullptr, total, 0);
         SPH_HIP(hipGetLastError());
         return;
     }
@@ -202,6 +216,11 @@ void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ui
     // reduce down: level 0 holds the tile sums of `in`, level k those of level k - 1
     k_scan_reduce<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, n, level(0));
     SPH_HIP(hipGetLastError());
+    if (scan_one_level(P)) {
+        k_scan_apply<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, out, n, level(0), total, P.lv[0].count);
+        SPH_HIP(hipGetLastError());
+        return;
+    }
     for (size_t k = 1; k < P.lv.size(); ++k) {
         k_scan_reduce<<<(unsigned)P.lv[k].count, SCAN_BS, 0, s>>>(level(k - 1), P.lv[k - 1].count, level(k));
         SPH_HIP(hipGetLastError());
@@ -209,21 +228,21 @@ void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ui
     // the last level fits one tile; then apply each level's scanned sums to
     // the level below, one block per tile of it
     const size_t top = P.lv.size() - 1;
-    k_scan_apply<<<1, SCAN_BS, 0, s>>>(level(top), level(top), P.lv[top].count, nullptr, nullptr);
+    k_scan_apply<<<1, SCAN_BS, 0, s>>>(level(top), level(top), P.lv[top].count, nullptr, nullptr, 0);
     SPH_HIP(hipGetLastError());
     for (size_t k = top; k-- > 0;) {
         k_scan_apply<<<(unsigned)scan_apply_grid(P, k), SCAN_BS, 0, s>>>(level(k), level(k), P.lv[k].count,
-                                                                         level(k + 1), nullptr);
+                                                                         level(k + 1), nullptr, 0);
         SPH_HIP(hipGetLastError());
     }
-    k_scan_apply<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, out, n, level(0), total);
+    k_scan_apply<<<(unsigned)P.tiles, SCAN_BS, 0, s>>>(in, out, n, level(0), total, 0);
     SPH_HIP(hipGetLastError());
 }
 
 void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                int64_t n, int bits, hipStream_t s)
+                int64_t n, int bits, hipStream_t s, int lo_bit)
 {
-    if (n <= 1 || bits <= 0) return;
+    if (n <= 1 || bits <= lo_bit) return;
     const int n_tiles = (int)((n + RS_TILE - 1) / RS_TILE);
     const int64_t hn = (int64_t)n_tiles * 256;
     uint32_t* hist = ensure<uint32_t>(c, c->sort_hist, (size_t)hn);
@@ -231,9 +250,9 @@ void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
     uint32_t* va = vals;
     uint64_t* kb = keys_alt;
     uint32_t* vb = vals_alt;
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits - lo_bit + 7) / 8;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = lo_bit + 8 * p;
         k_rs_hist<<<n_tiles, RS_BS, 0, s>>>(ka, n, shift, hist, n_tiles);
         SPH_HIP(hipGetLastError());
         scan_exclusive(c, hist, hist, hn, nullptr, s);

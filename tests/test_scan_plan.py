@@ -6,7 +6,8 @@ against that header, walks every launch the plan makes, block by block, and
 checks that each block reads and writes only inside its input, its output and
 its level of the scratch buffer; it also carries the plan out on the host
 with bounds-checked arrays and compares the result with a plain exclusive
-prefix sum. Lengths cover one tile, one level, the step to a second level
+prefix sum. Lengths cover one tile, one level (two launches: each apply block adds up
+the raw tile sums before it), the step to a second level
 (more than 2048 * 2048 elements, where the apply launches once used one block
 per element instead of one per tile and read past the scratch buffer) and the
 largest particle count the library accepts."""
@@ -54,6 +55,11 @@ static void geometry(long long n)
         below = L.count;
     }
     CHECK(P.lv.back().count <= SCAN_TILE, "last level must fit one block");
+    if (scan_one_level(P)) {
+        // block b of the apply reads raw sums 0 .. b - 1, one pass of a block (SCAN_TILE words)
+        CHECK(P.tiles <= SCAN_TILE && P.lv[0].count == P.tiles, "one-level plan beyond one block's pass");
+        return;
+    }
     for (size_t k = 0; k + 1 < P.lv.size(); ++k) {
         const int64_t grid = scan_apply_grid(P, k);
         // exactly one block per tile: a surplus block would read a sum past level k + 1
@@ -102,6 +108,20 @@ static void numeric(long long n, unsigned seed)
     uint32_t total = 0;
     if (P.lv.empty()) {
         apply(in.data(), out.data(), n, nullptr, 1, &total);
+    } else if (scan_one_level(P)) {
+        // two launches: block b of the apply adds the raw tile sums before it
+        reduce(in.data(), n, P.lv[0], P.tiles);
+        for (int64_t b = 0; b < P.tiles; ++b) {
+            if (b * SCAN_TILE >= n) continue;
+            uint32_t run = 0;
+            for (int64_t t = 0; t < b; ++t) run += scratch.at(P.lv[0].offset + t);
+            for (int64_t i = b * SCAN_TILE; i < (b + 1) * SCAN_TILE; ++i) {
+                const uint32_t v = i < n ? in[i] : 0u;
+                if (i < n) out[i] = run;
+                run += v;
+            }
+            if (b == P.tiles - 1) total = run;
+        }
     } else {
         reduce(in.data(), n, P.lv[0], P.tiles);
         for (size_t k = 1; k < P.lv.size(); ++k)
