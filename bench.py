@@ -196,6 +196,19 @@ class Inputs:
         ctx.build_cells(self.pos, self.h0, self.d["box_first"], self.d["box_len"])
         return ctx
 
+    def build_ms(self, ctx, reps: int = 5) -> float:
+        """Median host wall time of a cell build on a context that has built
+        once (its buffers exist), up to the end of its GPU work."""
+        import torch
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.build_cells(self.pos, self.h0, self.d["box_first"], self.d["box_len"])
+            torch.cuda.synchronize()
+            t.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(t))
+
     def step(self, ctx, cons: bool = True) -> dict:
         self.h.copy_(self.h0)
         return ctx.pass_(self.mass, self.h, self.vel, self.u, rho=self.rho, f=self.f, acc=self.acc,
@@ -225,7 +238,7 @@ def kernel_times(inp: Inputs, sph, params: dict, steps: int, warmup: int) -> dic
     with HIP events on the stream they run on; averages over `steps`."""
     import torch
     ctx_t = inp.context(sph, timing=1, **params)
-    build_ms = ctx_t.timings()["build_ms"]
+    build_ms = inp.build_ms(ctx_t)
     for _ in range(max(warmup, 1)):
         inp.step(ctx_t)
     dk, dr, fk, pc = [], [], [], []
@@ -453,13 +466,18 @@ def main() -> int:
         r0 = ctx_l.pass_(li.mass, h_l, vel_l, u_l)
         acc_l, dudt_l, rho_l = r0["acc"], r0["dudt"], r0["rho"]
 
+        sweeps = []
+
         def leap():
             dt = ctx_l.timestep(0.3)
-            ctx_l.step(dt, pos_l, li.mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
+            r = ctx_l.step(dt, pos_l, li.mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
+            sweeps.append(r["stats"]["sweeps"])
             return dt
 
         leap()
         torch.cuda.synchronize()
+        b0 = ctx_l.timings()["builds"]
+        sweeps.clear()
         t0 = time.perf_counter()
         for _ in range(args.leapfrog_steps):
             dt_last = leap()
@@ -467,9 +485,12 @@ def main() -> int:
         out["leapfrog"] = {
             "workload": "sedov blast 64^3", "ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
             "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
-            "build_ms": ctx_l.timings()["build_ms"],
-            "note": "wall time per step from the host (kick, drift, kick, pass with a cell rebuild "
-                    "when the drift bound requires one, kick, time step), after one untimed step"}
+            "steps_with_a_cell_build": ctx_l.timings()["builds"] - b0,
+            "sweeps_per_pass": float(np.mean(sweeps)),
+            "build_ms": li.build_ms(ctx_l),
+            "note": "wall time per step from the host (kick, drift, h prediction, kick, pass with a "
+                    "cell rebuild when the drift bound requires one, kick, time step), after one "
+                    "untimed step; build_ms: a warm cell build on these particles, GPU work included"}
         ctx_l.close()
         del li
         torch.cuda.empty_cache()

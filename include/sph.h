@@ -138,18 +138,25 @@ typedef struct {
 } sph_params;
 
 /* Durations of the last calls, in milliseconds of GPU time measured with HIP
- * events on the caller's stream (zero unless sph_params.timing was set). */
+ * events on the caller's stream (zero unless sph_params.timing was set), and
+ * the number of cell builds. */
 typedef struct {
     double density_kernel_ms;  /* FP32 density kernels (list and re-scan), summed
                                   over rebuild passes */
     double density_call_ms;    /* whole sph_density: prologues, kernels, copies */
     double force_kernel_ms;    /* FP32 force kernel */
     double force_call_ms;      /* whole sph_force: ghost step, kernel, copies */
-    double build_ms;           /* host wall time of the last sph_build_cells */
+    double build_ms;           /* host wall time of the last sph_build_cells (the
+                                  call returns with its last few kernels, offsets
+                                  and smallest search radius, still queued) */
     int32_t density_launches;  /* density kernel launches of the last sph_density
                                   (two per pass: list kernel, re-scan kernel) */
     double density_rescan_ms;  /* the re-scan kernel's share of density_kernel_ms */
     double pass_call_ms;       /* whole sph_pass */
+    int64_t builds;            /* cell builds since sph_create: sph_build_cells
+                                  calls and the rebuilds the library made after
+                                  a drift or for an h that outgrew its cell
+                                  (counted whatever sph_params.timing) */
 } sph_timings;
 
 typedef struct {

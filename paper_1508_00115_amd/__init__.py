@@ -69,7 +69,8 @@ class sph_timings(ctypes.Structure):
     _fields_ = [("density_kernel_ms", ctypes.c_double), ("density_call_ms", ctypes.c_double),
                 ("force_kernel_ms", ctypes.c_double), ("force_call_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32),
-                ("density_rescan_ms", ctypes.c_double), ("pass_call_ms", ctypes.c_double)]
+                ("density_rescan_ms", ctypes.c_double), ("pass_call_ms", ctypes.c_double),
+                ("builds", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

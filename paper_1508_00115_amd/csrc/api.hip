@@ -96,6 +96,8 @@ sph_status sph_create(const sph_params* params, int hip_device, sph_ctx** out)
             for (auto& e : c->ev) SPH_HIP(hipEventCreate(&e));
         sph::ensure<int64_t>(c, c->counters, CT_COUNT);
         SPH_HIP(hipHostMalloc((void**)&c->h_counters, CT_COUNT * sizeof(int64_t), hipHostMallocDefault));
+        SPH_HIP(hipHostMalloc((void**)&c->h_build, sph::BUILD_OUT_WORDS * sizeof(int64_t), hipHostMallocDefault));
+        SPH_HIP(hipEventCreateWithFlags(&c->ev_build, hipEventDisableTiming));
         sph::scratch_setup(hip_device);  // the static scratch of sph_timestep_noalloc on this device
     });
     if (st != SPH_OK) {
@@ -121,11 +123,13 @@ void sph_destroy(sph_ctx* c)
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->u_s, &c->status,
                        &c->st_s, &c->jf, &c->vsig_s, &c->bal_s, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
                        &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom, &c->cells_d, &c->p_cntd, &c->divv_s,
-                       &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt};
+                       &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt, &c->build_out};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
     if (c->h_counters) hipHostFree(c->h_counters);
+    if (c->h_build) hipHostFree(c->h_build);
+    if (c->ev_build) hipEventDestroy(c->ev_build);
     if (c->h_cons) hipHostFree(c->h_cons);
     if (c->pass_exec) hipGraphExecDestroy(c->pass_exec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
@@ -288,6 +292,9 @@ sph_status sph_get_build_info(const sph_ctx* c, sph_build_info* out)
 {
     if (!c || !out) return SPH_E_ARG;
     if (!c->built) return SPH_E_STATE;
+    sph_ctx* cm = const_cast<sph_ctx*>(c);  // the deferred read-back lands in the context
+    const sph_status st = guarded(cm, [&] { sph::finish_build_read(cm); });
+    if (st != SPH_OK) return st;
     *out = c->binfo;
     return SPH_OK;
 }

@@ -720,6 +720,25 @@ __global__ void __launch_bounds__(BS) k_min_H(int64_t n, const float* __restrict
     }
 }
 
+// The build's shape counters folded over their spread slots, and the
+// smallest search radius, into out (BUILD_OUT_WORDS words): a buffer no other
+// kernel writes, so its copy to the host can wait for the next synchronisation.
+__global__ void k_build_out(const int64_t* __restrict__ ctr, const unsigned* __restrict__ hmin,
+                            int64_t* __restrict__ out)
+{
+    const int k = threadIdx.x;  // CT_B_CAND_PAIRS + k
+    if (k < 4) {
+        int64_t v = ctr[CT_B_CAND_PAIRS + k];
+        for (int sl = 0; sl < CT_SPREAD_SLOTS; ++sl) {
+            const int64_t x = ctr[CT_SPREAD + sl * CT_SUMS + CT_B_CAND_PAIRS + k];
+            v = k == 0 ? v + x : max(v, x);
+        }
+        out[k] = v;
+    } else if (k == 4) {
+        out[4] = (int64_t)*hmin;
+    }
+}
+
 int ceil_log2(uint64_t v)
 {
     int b = 0;
@@ -1008,19 +1027,18 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_min_H<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, BS), 256)), BS, 0, s>>>(n, Hs,
                                                                                                  drift + 2);
     SPH_HIP(hipGetLastError());
-    unsigned hmin_bits = 0;
-    SPH_HIP(hipMemcpyAsync(&hmin_bits, drift + 2, 4, hipMemcpyDeviceToHost, s));
-    {
-        const int64_t* hc = read_counters(c, s);  // synchronises: hmin_bits is in
-        std::memcpy(&c->h_min, &hmin_bits, 4);
-        c->binfo.n_cells = nl;
-        c->binfo.n_pairs = c->n_pairs;
-        c->binfo.candidate_pairs = hc[CT_B_CAND_PAIRS];
-        c->binfo.max_cell_particles = hc[CT_B_MAX_NI];
-        c->binfo.max_neighbour_cells = hc[CT_B_MAX_NP];
-        c->binfo.max_candidates = hc[CT_B_MAX_NJ];
-    }
+    // the shape counters and the smallest radius come back behind an event;
+    // the next synchronisation (or finish_build_read) picks them up
+    int64_t* bo = ensure<int64_t>(c, c->build_out, BUILD_OUT_WORDS);
+    k_build_out<<<1, 64, 0, s>>>(ctr, drift + 2, bo);
+    SPH_HIP(hipGetLastError());
+    SPH_HIP(hipMemcpyAsync(c->h_build, bo, BUILD_OUT_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipEventRecord(c->ev_build, s));
+    c->build_read_pending = true;
+    c->binfo.n_cells = nl;
+    c->binfo.n_pairs = c->n_pairs;
     c->built = true;
+    ++c->tm.builds;
     c->drift_pending = false;
     c->vsig_valid = false;  // signal velocities belong to the cells of the last force pass
     c->bal_valid = false;
@@ -1028,6 +1046,20 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     ++c->layout_serial;  // cell arrays and grid sizes changed
     c->density_done = false;
     c->density64_done = false;
+}
+
+void finish_build_read(sph_ctx* c)
+{
+    if (!c->build_read_pending) return;
+    SPH_HIP(hipEventSynchronize(c->ev_build));
+    c->build_read_pending = false;
+    const int64_t* hb = c->h_build;
+    c->binfo.candidate_pairs = hb[0];
+    c->binfo.max_cell_particles = hb[1];
+    c->binfo.max_neighbour_cells = hb[2];
+    c->binfo.max_candidates = hb[3];
+    const uint32_t bits = (uint32_t)hb[4];
+    std::memcpy(&c->h_min, &bits, 4);
 }
 
 void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len, int64_t n,

@@ -158,13 +158,14 @@ struct sph_ctx {
     // largest |v dt| component of the current drift, [2] float bits of the
     // smallest Hs. Cleared by every build.
     sph::Buf drift;
-    float h_min = 0.0f;           // smallest Hs of the last build (host copy)
+    float h_min = 0.0f;           // smallest Hs of the last build (host copy; see finish_build_read)
     bool drift_pending = false;   // a drift since the last check of delta
     sph::Buf leaf_of;        // int, sorted particle -> leaf
     sph::Buf unassigned;     // int flags per particle during the level loop
     sph::Buf head, scan1;    // uint32 per particle
     sph::Buf nid;            // int per particle: node at the current level
     // nodes (all levels, level-major)
+    sph::Buf build_out;
     sph::Buf nd_start, nd_count, nd_hmax, nd_wide, nd_child0, nd_child1, nd_parent, nd_leaf, nd_box, nd_level,
         nd_coord;
     int64_t node_cap = 0;
@@ -211,6 +212,12 @@ struct sph_ctx {
     sph::Buf box_leaf;       // int, n_boxes + 1: first leaf of each box (leaves follow the boxes)
     sph::Buf cons64_d;       // double, CONS_SLOTS x 4 per box (plain FP64 form)
     int64_t* h_counters = nullptr;  // pinned host mirror of counters
+    // the build's shape counters and smallest search radius come back without
+    // a wait of their own: folded on the device into build_out, copied into
+    // this pinned buffer behind ev_build, read by finish_build_read
+    int64_t* h_build = nullptr;
+    hipEvent_t ev_build = nullptr;
+    bool build_read_pending = false;
     double* h_cons = nullptr;       // pinned host landing buffer of the conservation sums
     size_t h_cons_cap = 0;          // doubles it holds
 
@@ -231,6 +238,7 @@ struct sph_ctx {
     hipStream_t cap_stream = nullptr;    // private stream the pass is captured on
     hipGraphExec_t pass_exec = nullptr;  // instantiated pass for pass_key
     std::vector<uint64_t> pass_key;      // pointers and sizes the captured pass was built for
+    std::vector<uint64_t> pass_key_eager;  // those of the last pass launched directly
 };
 
 // Event pairs of the timing mode.
@@ -398,6 +406,11 @@ void scan_exclusive(sph_ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ui
 // buffers are scratch).
 void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                 uint32_t* vals_alt, int64_t n, int bits, hipStream_t s, int lo_bit = 0);
+
+// Waits for the build's deferred read-back (if any) and sets h_min and the
+// build info from it.
+void finish_build_read(sph_ctx* c);
+constexpr int BUILD_OUT_WORDS = 5;  // candidate pairs, largest leaf, list, candidates; smallest H (bits)
 
 void build_cells(sph_ctx* c, int32_t n_boxes, const int64_t* box_first, const double* box_len,
                  int64_t n, const double* pos, const float* h_guess, hipStream_t s);

@@ -180,6 +180,7 @@ void check_drift(sph_ctx* c, const float* h_caller, hipStream_t s)
     SPH_HIP(hipStreamSynchronize(s));
     c->drift_pending = false;
     SPH_REQUIRE(w[3] == 0u, SPH_E_ARG, "a drift produced a non-finite position");
+    finish_build_read(c);  // h_min
     float delta;
     std::memcpy(&delta, &w[0], 4);
     // the kernels search Hs - 2 delta: keep that above Hs / h_margin, the

@@ -10,9 +10,11 @@
 // step is folded into the density kernels: a particle's force-loop streams
 // are written as soon as its h is final, so there is no ghost kernel between
 // the loops. The kernel sequence never changes between calls with the same
-// buffers, so it is captured on a private stream once and the graph is
-// launched on the caller's stream; the capture is redone when any pointer or
-// size changes.
+// buffers, so it is captured on a private stream and the graph is launched
+// on the caller's stream; the capture is redone when any pointer or size
+// changes. A capture pays only when it is replayed: the first pass on new
+// cells or buffers launches the kernels directly, the second captures them.
+// (A time step that rebuilds its cells every step never captures.)
 #include "common.h"
 
 namespace sph {
@@ -53,7 +55,12 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
             (uint64_t)(uintptr_t)f,     (uint64_t)(uintptr_t)nw,   (uint64_t)(uintptr_t)vel,
             (uint64_t)(uintptr_t)u,     (uint64_t)(uintptr_t)acc,  (uint64_t)(uintptr_t)dudt,
             (uint64_t)(uintptr_t)cons_d};
-        if (!c->pass_exec || c->pass_key != key) {
+        if ((!c->pass_exec || c->pass_key != key) && c->pass_key_eager != key) {
+            // first pass with these cells and buffers: launched directly
+            density_enqueue(c, mass, h, rho, f, nw, true, false, s, vel, u);
+            force_enqueue(c, vel, u, acc, dudt, cons_d, false, false, s, false);
+            c->pass_key_eager = key;
+        } else if (!c->pass_exec || c->pass_key != key) {
             drop_graph(c);
             if (!c->cap_stream) SPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
@@ -73,8 +80,10 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
             SPH_HIP(e);
             c->pass_exec = ex;
             c->pass_key = key;
+            SPH_HIP(hipGraphLaunch(c->pass_exec, s));
+        } else {
+            SPH_HIP(hipGraphLaunch(c->pass_exec, s));
         }
-        SPH_HIP(hipGraphLaunch(c->pass_exec, s));
     }
     // counters and conservation sums in one synchronisation (the sums are
     // discarded below if the pass has to be repeated)

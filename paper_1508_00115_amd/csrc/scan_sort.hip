@@ -5,6 +5,8 @@
 #include "common.h"
 #include "scan_plan.h"
 
+#include <algorithm>
+
 namespace {
 
 using sph::SCAN_BS;
@@ -104,19 +106,20 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_apply(const uint32_t* in, uint
 
 // ---- radix sort ------------------------------------------------------------------
 
+// A tile is `rows` rows of RS_BS keys (one workgroup); rows goes from 1 to
+// RS_ROWS_MAX so that a small sort still has a few tiles per CU and a large
+// one fewer, longer tiles (smaller histograms to scan).
 constexpr int RS_BS = 256;
-constexpr int RS_ROWS = 8;
-constexpr int RS_TILE = RS_BS * RS_ROWS;
+constexpr int RS_ROWS_MAX = 8;
 
 __global__ void __launch_bounds__(RS_BS) k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
-                                                   uint32_t* __restrict__ hist, int n_tiles)
+                                                   uint32_t* __restrict__ hist, int n_tiles, int rows)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll
-    for (int r = 0; r < RS_ROWS; ++r) {
+    const int64_t base = (int64_t)blockIdx.x * RS_BS * rows;
+    for (int r = 0; r < rows; ++r) {
         int64_t i = base + r * RS_BS + threadIdx.x;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     }
@@ -131,7 +134,7 @@ __global__ void __launch_bounds__(RS_BS) k_rs_hist(const uint64_t* __restrict__ 
 __global__ void __launch_bounds__(RS_BS) k_rs_scatter(const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals, int64_t n,
                                                       int shift, const uint32_t* __restrict__ offs,
-                                                      int n_tiles, uint64_t* __restrict__ keys_out,
+                                                      int n_tiles, int rows, uint64_t* __restrict__ keys_out,
                                                       uint32_t* __restrict__ vals_out)
 {
     __shared__ uint32_t run[256];
@@ -143,8 +146,8 @@ __global__ void __launch_bounds__(RS_BS) k_rs_scatter(const uint64_t* __restrict
     run[t] = 0;
     goff[t] = offs[(int64_t)t * n_tiles + blockIdx.x];
     const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ROWS; ++r) {
+    const int64_t base = (int64_t)blockIdx.x * RS_BS * rows;
+    for (int r = 0; r < rows; ++r) {
         const int64_t i = base + r * RS_BS + t;
         const bool valid = i < n;
         uint64_t k = valid ? keys[i] : ~0ull;
@@ -243,7 +246,10 @@ void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
                 int64_t n, int bits, hipStream_t s, int lo_bit)
 {
     if (n <= 1 || bits <= lo_bit) return;
-    const int n_tiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    // about 1024 tiles (four per CU) while a tile holds at most RS_ROWS_MAX rows
+    const int rows = (int)std::min<int64_t>(RS_ROWS_MAX, std::max<int64_t>(1, n / (1024 * RS_BS)));
+    const int64_t tile = (int64_t)RS_BS * rows;
+    const int n_tiles = (int)((n + tile - 1) / tile);
     const int64_t hn = (int64_t)n_tiles * 256;
     uint32_t* hist = ensure<uint32_t>(c, c->sort_hist, (size_t)hn);
     uint64_t* ka = keys;
@@ -253,10 +259,10 @@ void radix_sort(sph_ctx* c, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
     const int passes = (bits - lo_bit + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = lo_bit + 8 * p;
-        k_rs_hist<<<n_tiles, RS_BS, 0, s>>>(ka, n, shift, hist, n_tiles);
+        k_rs_hist<<<n_tiles, RS_BS, 0, s>>>(ka, n, shift, hist, n_tiles, rows);
         SPH_HIP(hipGetLastError());
         scan_exclusive(c, hist, hist, hn, nullptr, s);
-        k_rs_scatter<<<n_tiles, RS_BS, 0, s>>>(ka, va, n, shift, hist, n_tiles, kb, vb);
+        k_rs_scatter<<<n_tiles, RS_BS, 0, s>>>(ka, va, n, shift, hist, n_tiles, rows, kb, vb);
         SPH_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);
