@@ -179,7 +179,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         int kept_single = 0;  // (single tile) candidates kept by the cell-box test
         const float2 geom = A.cell_geom[slot];
         const float hw = cull_half_width(geom.x + delta), reach2_cell = cull_reach2(geom.y);
-        double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};  // this cell's share of the box sums (lane 0)
+        // this cell's share of the box sums: lane 0's totals, kept in scalar
+        // registers across the passes (every lane is active where they change)
+        double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
             const bool valid = gi < ni;
@@ -194,7 +196,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             // candidates staged for this pass alone need only reach its
             // particles' largest h (or their own); a tile kept for every pass
             // reaches the cell's largest search radius
-            const float reach2 = single_tile ? reach2_cell : cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f)));
+            const float reach2 =
+                single_tile ? reach2_cell : uniform_f(cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f))));
             // ... from the box around this pass's particles, or the cell's box
             const CullBox box = single_tile ? cell_box(hw) : pass_box(i0v.x, i0v.y, i0v.z, valid);
             const float hinv2_i = hinv_i * hinv_i;
@@ -335,7 +338,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     for (int o = 32; o >= lpi; o >>= 1) cm[k] += __shfl_xor(cm[k], o, 64);
-                    cm_cell[k] += cm[k];
+                    cm_cell[k] = lane0_d(cm_cell[k] + cm[k]);
                 }
             }
         }

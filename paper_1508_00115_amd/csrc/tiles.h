@@ -424,10 +424,26 @@ __device__ __forceinline__ CullBox cell_box(float hw)
     return b;
 }
 
+// A value every active lane holds alike, moved to a scalar register: it then
+// costs no vector register while it stays live across a loop.
+__device__ __forceinline__ float uniform_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Lane 0's double (the first active lane's), in scalar registers.
+__device__ __forceinline__ double lane0_d(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffull));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
+    return uniform_f(v);
 }
 
 __device__ __forceinline__ float wave_max(float v);
@@ -443,12 +459,12 @@ __device__ __forceinline__ CullBox pass_box(float x, float y, float z, bool in)
     const float ly = wave_min(in ? y : BIG), hy = wave_max(in ? y : -BIG);
     const float lz = wave_min(in ? z : BIG), hz = wave_max(in ? z : -BIG);
     CullBox b;
-    b.cx = 0.5f * (lx + hx);
-    b.cy = 0.5f * (ly + hy);
-    b.cz = 0.5f * (lz + hz);
-    b.hx = 0.5f * (hx - lx) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lx), fabsf(hx));
-    b.hy = 0.5f * (hy - ly) * 1.000001f + 1.0e-6f * fmaxf(fabsf(ly), fabsf(hy));
-    b.hz = 0.5f * (hz - lz) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lz), fabsf(hz));
+    b.cx = uniform_f(0.5f * (lx + hx));
+    b.cy = uniform_f(0.5f * (ly + hy));
+    b.cz = uniform_f(0.5f * (lz + hz));
+    b.hx = uniform_f(0.5f * (hx - lx) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lx), fabsf(hx)));
+    b.hy = uniform_f(0.5f * (hy - ly) * 1.000001f + 1.0e-6f * fmaxf(fabsf(ly), fabsf(hy)));
+    b.hz = uniform_f(0.5f * (hz - lz) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lz), fabsf(hz)));
     return b;
 }
 
@@ -545,7 +561,7 @@ __device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const Chun
 __device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
+    return uniform_f(v);
 }
 
 // Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
