@@ -466,31 +466,45 @@ def main() -> int:
         r0 = ctx_l.pass_(li.mass, h_l, vel_l, u_l)
         acc_l, dudt_l, rho_l = r0["acc"], r0["dudt"], r0["rho"]
 
-        sweeps = []
+        sweeps, evals = [], []
 
-        def leap():
+        def leap(predict=True):
             dt = ctx_l.timestep(0.3)
-            r = ctx_l.step(dt, pos_l, li.mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l)
-            sweeps.append(r["stats"]["sweeps"])
+            r = ctx_l.step(dt, pos_l, li.mass, h_l, vel_l, u_l, acc_l, dudt_l, rho=rho_l, predict_h=predict)
+            st = r["stats"]
+            sweeps.append(st["sweeps"])
+            evals.append(st["sweep_interactions_density"] / max(st["interactions_density"], 1))
             return dt
 
         leap()
         torch.cuda.synchronize()
         b0 = ctx_l.timings()["builds"]
         sweeps.clear()
+        evals.clear()
         t0 = time.perf_counter()
         for _ in range(args.leapfrog_steps):
             dt_last = leap()
         torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps
+        builds = ctx_l.timings()["builds"] - b0
+        ev_pred, sw = float(np.mean(evals)), float(np.mean(sweeps))
+        # the steps that follow, without the prediction (untimed)
+        evals.clear()
+        for _ in range(min(10, args.leapfrog_steps)):
+            leap(predict=False)
         out["leapfrog"] = {
-            "workload": "sedov blast 64^3", "ms_per_step": (time.perf_counter() - t0) * 1e3 / args.leapfrog_steps,
+            "workload": "sedov blast 64^3", "ms_per_step": ms,
             "steps": args.leapfrog_steps, "courant": 0.3, "last_dt": dt_last,
-            "steps_with_a_cell_build": ctx_l.timings()["builds"] - b0,
-            "sweeps_per_pass": float(np.mean(sweeps)),
+            "steps_with_a_cell_build": builds,
+            "sweeps_per_pass": sw,
+            "evaluations_per_particle": ev_pred,
+            "evaluations_per_particle_without_prediction": float(np.mean(evals)),
             "build_ms": li.build_ms(ctx_l),
             "note": "wall time per step from the host (kick, drift, h prediction, kick, pass with a "
                     "cell rebuild when the drift bound requires one, kick, time step), after one "
-                    "untimed step; build_ms: a warm cell build on these particles, GPU work included"}
+                    "untimed step; sweeps: most Newton evaluations of any particle; evaluations: "
+                    "their mean (the next steps run without the prediction for comparison); "
+                    "build_ms: a warm cell build on these particles, GPU work included"}
         ctx_l.close()
         del li
         torch.cuda.empty_cache()

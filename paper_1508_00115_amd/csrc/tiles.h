@@ -443,7 +443,7 @@ __device__ __forceinline__ double lane0_d(double v)
 __device__ __forceinline__ float wave_min(float v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return uniform_f(v);
+    return v;
 }
 
 __device__ __forceinline__ float wave_max(float v);
@@ -561,7 +561,7 @@ __device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const Chun
 __device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return uniform_f(v);
+    return v;
 }
 
 // Stage candidates [c0, c0 + len) (len <= CAP) into the tile: every lane finds
