@@ -286,6 +286,21 @@ def roofline(stats: dict, km: dict, tag: str, params: dict) -> dict:
                               FLOP_FORCE * stats["interactions_force"]) / ((dens_ms + force_ms) * 1e-3) / 1e12}
 
 
+def culling(inp: Inputs, sph, params: dict) -> dict:
+    """One pass on a context counting the density loop's list-building tests
+    and the candidates they list (sph_params.timing = 2, a separate kernel
+    instance): tests per listed neighbour measure the culling, the work the
+    paper's sorted sweeps save (listed: candidates inside the search radius,
+    the particle itself included)."""
+    ctx = inp.context(sph, timing=2, **params)
+    inp.step(ctx)  # as in the timed passes: after any rebuild the first pass needed
+    st = inp.step(ctx)
+    ctx.close()
+    return {"phase_a_tests": st["tests_density"], "listed": st["listed_density"],
+            "tests_per_listed": st["tests_density"] / max(1, st["listed_density"]),
+            "force_candidates_per_interaction": st["candidates_force"] / max(1, st["interactions_force"])}
+
+
 def extra_set(name: str, sph, args, stream, dev) -> dict:
     """The captured pass on another workload, with its kernel times."""
     import torch
@@ -303,6 +318,7 @@ def extra_set(name: str, sph, args, stream, dev) -> dict:
            "roofline": roofline(sp, km, tag, params), "sweeps": sp["sweeps"],
            "candidates_per_interaction_density": sp["candidates_density"] / max(1, sp["interactions_density"]),
            "candidates_per_interaction_force": sp["candidates_force"] / max(1, sp["interactions_force"]),
+           "culling": culling(inp, sph, params),
            "cell_params": params or "library defaults", "cell_params_from": src}
     del inp
     torch.cuda.empty_cache()
@@ -435,6 +451,7 @@ def main() -> int:
                     "candidates_per_interaction": sp["candidates_density"] / max(1, sp["interactions_density"]),
                     "rescanned": sp["rescanned_density"],
                     "cells": sp["n_cells"], "cell_pairs": sp["n_pairs"]},
+        "culling": culling(inp, sph, params),
         "force": {"candidates": sp["candidates_force"],
                   "candidates_per_interaction": sp["candidates_force"] / max(1, sp["interactions_force"])},
         "fp64_plain": {"value": value64, "ms_per_step": ms_step64, "steps": args.fp64_steps,

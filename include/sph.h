@@ -94,7 +94,11 @@ typedef struct {
     int64_t workspace_limit; /* device bytes the context may allocate; 0 = no limit */
     int32_t timing;       /* nonzero: record HIP events around the hot kernels
                              (read with sph_get_timings; adds one stream
-                             synchronisation to sph_force) */
+                             synchronisation to sph_force); 2: also count the
+                             density loop's list-building tests and listed
+                             candidates (sph_stats.tests_density,
+                             listed_density), in a kernel instance that takes
+                             a few percent longer */
     int32_t schedule;     /* how cells reach wavefronts: 0 = hardware dispatch,
                              one cell per wavefront, XCD-contiguous blocks;
                              1 = persistent wavefronts popping per-XCD queues */
@@ -178,6 +182,16 @@ typedef struct {
     int64_t rescanned_density;  /* particles whose solve re-tested every candidate
                                    at each evaluation (unequal masses or a
                                    neighbour list too long for its slots) */
+    int64_t tests_density;      /* FP32 loops: (i, j) candidate pairs tested against
+                                   i's search radius outside the Newton lists (the
+                                   list-building scans, and the rare re-walks of a
+                                   particle whose list did not fit): the part of
+                                   candidates_density that culling decides.
+                                   Counted with sph_params.timing = 2 (0
+                                   otherwise, and in the FP64 form) */
+    int64_t listed_density;     /* FP32 loops, sph_params.timing = 2: of those,
+                                   the pairs inside the search radius, kept for
+                                   the Newton iteration */
 } sph_stats;
 
 /* Create a context on HIP device `hip_device`. `params` (host) may be NULL

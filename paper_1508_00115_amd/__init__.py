@@ -50,7 +50,8 @@ class sph_stats(ctypes.Structure):
                 ("interactions_force", ctypes.c_int64), ("candidates_density", ctypes.c_int64),
                 ("candidates_force", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("sweep_interactions_density", ctypes.c_int64),
-                ("rescanned_density", ctypes.c_int64)]
+                ("rescanned_density", ctypes.c_int64), ("tests_density", ctypes.c_int64),
+                ("listed_density", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

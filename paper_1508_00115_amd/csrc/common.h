@@ -69,11 +69,13 @@ enum {
     CT_B_MAX_NP = 12,      // build: longest neighbour-cell list (max)
     CT_B_MAX_NJ = 13,      // build: most candidates of a leaf (max)
     CT_B_PAIRS64 = 14,     // build: (cell, neighbour cell) records, counted in 64 bits
-    CT_SUMS = 16,        // entries [0, CT_SUMS) have spread slots
+    CT_DENS_TESTS = 15,  // density: candidate pairs tested against the search radius (phase A)
+    CT_DENS_LISTED = 16, // density: candidates listed (inside the search radius) by phase A
+    CT_SUMS = 17,        // entries [0, CT_SUMS) have spread slots
     // single entries
-    CT_TOTAL = 16,       // scratch for device-computed totals read by the host (two uint32)
     CT_SCAN_CELLS = 17,  // cells queued for the re-scanning density kernel
     CT_SCAN_POP = 18,    // next queued cell to take
+    CT_TOTAL = 19,       // scratch for device-computed totals read by the host (two uint32)
     CT_DT_MIN = 20,      // sph_timestep: smallest h / v_sig (float bits in the low word)
     CT_QUEUE = 32,       // 8 work-queue heads (one per XCD), one 64-byte line each: CT_QUEUE + 8 q
     CT_SPREAD = 96,      // CT_SPREAD_SLOTS copies of the sums, CT_SUMS entries each

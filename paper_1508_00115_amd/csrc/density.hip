@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace {
 
@@ -82,6 +83,8 @@ struct DensArgs {
     float4* jf;
     float gamma;
     const float* drift;      // [0]: bound on the drift since the build (search Hs - 2 drift)
+    int detail;              // count the list-building tests and the listed candidates
+                             // (sph_params.timing = 2; the list kernel's DETAIL instance)
 };
 
 // Sorted copies of position (cell frame), mass, h and state. fresh: every
@@ -254,9 +257,15 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, uint32_t 
 
 __device__ __forceinline__ void flush_counters(const DensArgs& A, int64_t cand_acc, int64_t list_acc,
                                                int64_t inter_acc, int64_t sweep_acc, int64_t n_over,
-                                               int64_t n_unconv, int max_ev, int64_t n_scan)
+                                               int64_t n_unconv, int max_ev, int64_t n_scan,
+                                               int64_t listed_acc)
 {
-    ctr_add_uniform(A.ctr, CT_DENS_CAND, cand_acc);  // already a wavefront total
+    // cand_acc and listed_acc are wavefront totals already
+    ctr_add_uniform(A.ctr, CT_DENS_CAND, cand_acc);
+    if (A.detail) {
+        ctr_add_uniform(A.ctr, CT_DENS_TESTS, cand_acc);
+        ctr_add_uniform(A.ctr, CT_DENS_LISTED, listed_acc);
+    }
     ctr_wave_add(A.ctr, CT_DENS_CAND, list_acc);
     ctr_wave_add(A.ctr, CT_DENS_INTER, inter_acc);
     ctr_wave_add(A.ctr, CT_DENS_SWEEP_INTER, sweep_acc);
@@ -384,7 +393,9 @@ __device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float
 // that takes leave three wavefronts per SIMD, which then cover the memory
 // latency the prefetch does not. Hardware dispatch (one cell per wavefront)
 // has no next cell: at most 128 VGPRs, four wavefronts per SIMD.
-template <int TCAP, bool PERSIST>
+// DETAIL: also count the candidates listed (sph_params.timing = 2); a
+// separate instance, since the counter costs the hot loop registers.
+template <int TCAP, bool PERSIST, bool DETAIL>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
     __shared__ float4 tile[TCAP];
@@ -400,6 +411,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
     // per-lane counts (far below 2^31 for any particle count that fits a GPU)
     int inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0, n_scan = 0, list_acc = 0;
     int max_ev = 0;
+    int64_t listed_acc = 0;  // wave-uniform
 
     // the next schedule slot of this wavefront (wave-uniform), if any
     auto next_slot = [&](int& sl) -> bool {
@@ -599,6 +611,13 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                 fcnt = cnt;
                 hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
             }
+            if constexpr (DETAIL) {
+                // the candidates listed in this pass (balancing moved entries
+                // between a particle's lanes but kept their number): one wave sum
+                int v = nl;
+                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                listed_acc += __builtin_amdgcn_readfirstlane(v);
+            }
             if (valid && sub == 0 && st0 == ST_ACTIVE && fits)
                 write_result(A, i, o_i, s, fS0, m0 * fS0, m0 * fS1, fcnt, inter_acc, n_over, n_unconv, max_ev);
         }
@@ -609,7 +628,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         slot = nslot;
         have = have_next;
     }
-    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan);
+    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, n_scan, listed_acc);
 }
 
 // ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
@@ -668,13 +687,27 @@ __device__ __forceinline__ ListSums list_sums(const float* lr, const float* lm, 
 
 // Stage the chunk of candidates starting at c0 into the tile (unless a
 // single-tile cell already holds them all); returns its length.
+// Candidates [c0, c0 + len) into the tile; returns len. A cell whose
+// candidates fit one tile stages them once for all its groups of particles
+// (kept = every candidate). Otherwise only those within reach2 of the
+// group's box are kept, packed from slot 0 (kept of them): a particle of the
+// group pairs with no other.
 __device__ __forceinline__ int rescan_stage(const DensArgs& A, NbrCursor& cu, float4* tile, int c0, int nj,
-                                            bool single_tile, bool& loaded)
+                                            bool single_tile, bool& loaded, const CullBox& box, float reach2,
+                                            int& kept)
 {
-    if (single_tile && loaded) return nj;
+    if (single_tile && loaded) {
+        kept = nj;
+        return nj;
+    }
     cursor_seek(cu, A.p_rec, A.p_shift, c0);
     const int len = cursor_chunk(cu, c0, SCAP);
-    stage_fast<1, SCAP>(tile, A.jd, cu.nb, c0 - cu.off0, len);
+    if (single_tile) {
+        stage_fast<1, SCAP>(tile, A.jd, cu.nb, c0 - cu.off0, len);
+        kept = len;
+    } else {
+        kept = stage_fast_culled<1, SCAP>(tile, A.jd, cu.nb, c0 - cu.off0, len, box, reach2);
+    }
     loaded = true;
     return len;
 }
@@ -684,8 +717,8 @@ __device__ __forceinline__ int rescan_stage(const DensArgs& A, NbrCursor& cu, fl
 template <class I>
 __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, float4* tile, int nj, bool single_tile,
                                              bool& loaded, bool active, int i, float4 xi, int sub,
-                                             int64_t& cand_acc, I& inter_acc, I& sweep_acc, I& n_over,
-                                             I& n_unconv, int& max_ev)
+                                             const CullBox& box, float reach2, int64_t& cand_acc, I& inter_acc,
+                                             I& sweep_acc, I& n_over, I& n_unconv, int& max_ev)
 {
     HSolve s = hsolve_init(A.hs[i], A.Hs[i] - 2.0f * A.drift[0], !active, ST_ACTIVE);
     float S0 = 0.f, S1 = 0.f, M0 = 0.f, M1 = 0.f;
@@ -696,10 +729,12 @@ __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, f
         S0 = S1 = M0 = M1 = 0.f;
         cnt = 0;
         const int groups_now = wave_count(!s.done && sub == 0);
-        int len;
+        int len, kept_tot = 0;
         for (int c0 = 0; c0 < nj; c0 += len) {
-            len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded);
-            for (int k = sub; k < len; k += RLPI) {
+            int kept;
+            len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded, box, reach2, kept);
+            kept_tot += kept;
+            for (int k = sub; k < kept; k += RLPI) {
                 const float4 pj = tile[k];
                 const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -716,7 +751,7 @@ __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, f
             }
             if (!single_tile) wave_sync_lds();
         }
-        cand_acc += (int64_t)groups_now * nj;
+        cand_acc += (int64_t)groups_now * kept_tot;
         S0 = group_sum(S0, RLPI);
         S1 = group_sum(S1, RLPI);
         M0 = group_sum(M0, RLPI);
@@ -745,6 +780,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
     const float two_delta = 2.0f * A.drift[0];
     int64_t cand_acc = 0;  // wave-uniform
     int list_acc = 0, inter_acc = 0, sweep_acc = 0, n_over = 0, n_unconv = 0;
+    int64_t listed_acc = 0;  // wave-uniform
     int max_ev = 0;
     const int n_queued = (int)A.ctr[CT_SCAN_CELLS];  // final: written by the list kernel
     if ((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6) >= n_queued) return;
@@ -778,11 +814,17 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
 
                 // ---- phase A: every candidate once, hits inside H listed ----------
                 const float H2 = valid ? s.Hi * s.Hi : -1.0f;
+                // the staged candidates any particle of this group can pair with:
+                // within its largest search radius of the box around the group
+                const CullBox gbox = pass_box(xi.x, xi.y, xi.z, valid);
+                const float greach2 = uniform_f(cull_reach2(wave_max(valid ? s.Hi : 0.0f)));
                 unsigned o = o_lane;
-                int len;
+                int len, kept_tot = 0;
                 for (int c0 = 0; c0 < nj; c0 += len) {
-                    len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded);
-                    for (int kk = sub; kk < len; kk += RLPI) {
+                    int kept;
+                    len = rescan_stage(A, cu, tile, c0, nj, single_tile, loaded, gbox, greach2, kept);
+                    kept_tot += kept;
+                    for (int kk = sub; kk < kept; kk += RLPI) {
                         const float4 pj = tile[kk];
                         const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -793,9 +835,14 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                     }
                     if (!single_tile) wave_sync_lds();
                 }
-                cand_acc += (int64_t)wave_count(valid && sub == 0) * nj;
+                cand_acc += (int64_t)wave_count(valid && sub == 0) * kept_tot;
                 const int nl = (int)((o - o_lane) >> 8);
                 const bool fits = group_sum_i(nl > RSLOTS ? 1 : 0, RLPI) == 0;
+                if (A.detail) {
+                    int v = valid && fits ? nl : 0;
+                    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                    listed_acc += __builtin_amdgcn_readfirstlane(v);
+                }
 
                 // ---- phase B: Newton's method over the lists ---------------------
                 const bool listed = valid && fits;
@@ -828,12 +875,12 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                 // ---- lists too short: re-test every candidate per evaluation -------
                 const bool rewalk = valid && !fits;
                 if (__any(rewalk))
-                    rewalk_solve(A, cu, tile, nj, single_tile, loaded, rewalk, i, xi, sub, cand_acc, inter_acc,
-                                 sweep_acc, n_over, n_unconv, max_ev);
+                    rewalk_solve(A, cu, tile, nj, single_tile, loaded, rewalk, i, xi, sub, gbox, greach2, cand_acc,
+                                 inter_acc, sweep_acc, n_over, n_unconv, max_ev);
             }
         }
     }
-    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0);
+    flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0, listed_acc);
 }
 
 }  // namespace
@@ -909,17 +956,25 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.jf = jf;
     A.gamma = (float)c->prm.gamma;
     A.drift = static_cast<float*>(c->drift.p);
+    A.detail = c->prm.timing == 2 ? 1 : 0;
     const int grid = make_sched(c, c->n_leaves, WAVES, 12, A.W);
     // re-scan grid: enough wavefronts for a full queue; the surplus exits at once
     const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
     if (events) ev_record(c, EV_DENS_K0, s);
     const bool pers = A.W.persistent != 0;
+    auto launch = [&](auto tcap) {
+        constexpr int T = decltype(tcap)::value;
+        if (A.detail)
+            pers ? k_density<T, true, true><<<grid, BS, 0, s>>>(A) : k_density<T, false, true><<<grid, BS, 0, s>>>(A);
+        else
+            pers ? k_density<T, true, false><<<grid, BS, 0, s>>>(A) : k_density<T, false, false><<<grid, BS, 0, s>>>(A);
+    };
     if (c->prm.tile_cap == 512)
-        pers ? k_density<512, true><<<grid, BS, 0, s>>>(A) : k_density<512, false><<<grid, BS, 0, s>>>(A);
+        launch(std::integral_constant<int, 512>{});
     else if (c->prm.tile_cap == 256)
-        pers ? k_density<256, true><<<grid, BS, 0, s>>>(A) : k_density<256, false><<<grid, BS, 0, s>>>(A);
+        launch(std::integral_constant<int, 256>{});
     else
-        pers ? k_density<128, true><<<grid, BS, 0, s>>>(A) : k_density<128, false><<<grid, BS, 0, s>>>(A);
+        launch(std::integral_constant<int, 128>{});
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_DENS_KM, s);
     k_density_scan<<<scan_grid, BS, 0, s>>>(A);
@@ -946,7 +1001,7 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
     SPH_REQUIRE(c->built, SPH_E_STATE, "sph_density before sph_build_cells");
     SPH_REQUIRE(mass && h && rho && f, SPH_E_ARG, "null mass/h/rho/f");
     check_drift(c, h, s);
-    int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0;
+    int64_t tot_inter = 0, tot_cand = 0, tot_sweep_inter = 0, tot_scan = 0, tot_tests = 0, tot_listed = 0;
     int32_t sweeps = 0;
     c->rebuilds = 0;
     c->density_done = false;
@@ -968,6 +1023,8 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
         tot_scan += hc[CT_NEED_SCAN];
         tot_inter += hc[CT_DENS_INTER];
         tot_cand += hc[CT_DENS_CAND];
+        tot_tests += hc[CT_DENS_TESTS];
+        tot_listed += hc[CT_DENS_LISTED];
         tot_sweep_inter += hc[CT_DENS_SWEEP_INTER];
         sweeps = std::max<int32_t>(sweeps, (int32_t)hc[CT_SWEEPS]);
         if (hc[CT_OVERFLOW] == 0) {
@@ -981,6 +1038,8 @@ void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, 
                 st->candidates_force = 0;
                 st->sweep_interactions_density = tot_sweep_inter;
                 st->rescanned_density = tot_scan;
+                st->tests_density = tot_tests;
+                st->listed_density = tot_listed;
                 st->n_cells = c->n_leaves;
                 st->n_pairs = c->n_pairs;
             }

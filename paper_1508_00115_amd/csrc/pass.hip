@@ -116,6 +116,8 @@ void pass_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, flo
         st->candidates_force = hc[CT_FORCE_CAND];
         st->sweep_interactions_density = hc[CT_DENS_SWEEP_INTER];
         st->rescanned_density = hc[CT_NEED_SCAN];
+        st->tests_density = hc[CT_DENS_TESTS];
+        st->listed_density = hc[CT_DENS_LISTED];
         st->n_cells = c->n_leaves;
         st->n_pairs = c->n_pairs;
     }

@@ -618,3 +618,61 @@ __device__ __forceinline__ void stage_fast(float4* sj, const float4* __restrict_
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// stage_fast keeping only the candidates within reach of `box` (distance to
+// it below sqrt(reach2)), packed from slot 0 in candidate order; returns how
+// many it kept.
+template <int NF, int CAP>
+__device__ __forceinline__ int stage_fast_culled(float4* sj, const float4* __restrict__ jd, const NbrLanes& nb,
+                                                 int c0, int len, const CullBox& box, float reach2)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = CAP / 64;
+    int src[PER];
+    float s3[PER][3];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        const int kg = c0 + (t < len ? t : 0);
+        int q = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = q + step;
+            const int v = __shfl(nb.off, cand < nb.np ? cand : nb.np - 1, 64);
+            if (cand < nb.np && v <= kg) q = cand;
+        }
+        src[r] = __shfl(nb.bs, q, 64) + (kg - __shfl(nb.off, q, 64));
+        s3[r][0] = __shfl(nb.sx, q, 64);
+        s3[r][1] = __shfl(nb.sy, q, 64);
+        s3[r][2] = __shfl(nb.sz, q, 64);
+    }
+    float4 v[PER][NF];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        if (lane + 64 * r < len) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[r][f] = jd[(int64_t)NF * src[r] + f];
+        }
+    }
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        float4 a = v[r][0];
+        a.x += s3[r][0];
+        a.y += s3[r][1];
+        a.z += s3[r][2];
+        const bool keep = lane + 64 * r < len && box_dist2(a.x, a.y, a.z, box) < reach2;
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int d = n + lanes_below(m);
+            sj[d] = a;
+#pragma unroll
+            for (int f = 1; f < NF; ++f) sj[f * CAP + d] = v[r][f];
+        }
+        n += __popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return n;
+}
+

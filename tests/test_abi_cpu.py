@@ -48,7 +48,7 @@ def test_struct_layouts_match_header(lib):
     for which, mirror in enumerate((sph.sph_params, sph.sph_stats, sph.sph_timings, sph.sph_build_info)):
         assert lib.sph_struct_size(which) == ctypes.sizeof(mirror), mirror.__name__
     assert lib.sph_struct_size(4) == -1
-    assert ctypes.sizeof(sph.sph_stats) == 80
+    assert ctypes.sizeof(sph.sph_stats) == 96
 
 
 def test_create_rejects_null_out_and_bad_params(lib):

@@ -75,6 +75,38 @@ def _same(a, b, label, d=None):
         assert a["stats"][k] == b["stats"][k], (label, k, a["stats"][k], b["stats"][k])
 
 
+def test_detail_counters(gpu_lib):
+    """sph_params.timing = 2 counts the density loop's list-building tests and
+    the candidates they list. Every particle lists each particle inside its
+    search radius H_i = h_margin h_guess_i (itself included) once, so the
+    listed count is sum_i #{j : r_ij < H_i} (scipy's cKDTree, periodic), up to
+    pairs within FP32 rounding of H_i; the tests count at least those. Without
+    it nothing is counted, and the outputs are the same bits either way."""
+    from scipy.spatial import cKDTree
+    d = workloads.small()
+    t = _inputs(d)
+    out = {}
+    for timing in (0, 2):
+        ctx = gpu_lib.Context(0, timing=timing, h_margin=1.26)
+        try:
+            ctx.build_cells(t["pos"], t["h0"], d["box_first"], d["box_len"])
+            out[timing], _ = _pass(ctx, t, d)
+        finally:
+            ctx.close()
+    _same(out[0], out[2], "timing 2")
+    st0, st = out[0]["stats"], out[2]["stats"]
+    assert st0["tests_density"] == 0 and st0["listed_density"] == 0
+    H = (np.float32(1.26) * d["h0"].astype(np.float32)).astype(np.float64)  # the FP32 radius of the build
+    pos = np.mod(d["pos"], 1.0)
+    tree = cKDTree(pos, boxsize=1.0)
+    lo = int(tree.query_ball_point(pos, H * (1.0 - 1e-5), return_length=True).sum())
+    hi = int(tree.query_ball_point(pos, H * (1.0 + 1e-5), return_length=True).sum())
+    print("listed %d (expected %d..%d), tests %d" % (st["listed_density"], lo, hi, st["tests_density"]), flush=True)
+    assert st["rescanned_density"] == 0
+    assert lo <= st["listed_density"] <= hi
+    assert st["tests_density"] >= st["listed_density"]
+
+
 @pytest.mark.parametrize("name", ["small", "sedov32", "batched8", "mixed_mass"])
 def test_pass_equals_density_then_force(gpu_lib, name):
     import torch
