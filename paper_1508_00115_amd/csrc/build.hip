@@ -391,6 +391,45 @@ __global__ void k_box_leaf(int n_boxes, int64_t n, int64_t nl, const int64_t* __
     box_leaf[b] = p < n ? leaf_of[p] : (int)nl;
 }
 
+// Particles of each leaf of 2 to 64 particles in decreasing order of search
+// radius (ties by input index), one wavefront per leaf, a bitonic network
+// over the 64 lanes. The hot kernels take a leaf's particles a pass at a
+// time and cull the staged candidates to the pass's largest radius, which
+// this order makes as small as it can be for every pass but the first.
+// Only the order inside each leaf changes: leaves, nodes and lists stay.
+__global__ void __launch_bounds__(256) k_leaf_sort_h(int64_t nl, const int* __restrict__ lf_start,
+                                                     const int* __restrict__ lf_count, uint32_t* __restrict__ perm,
+                                                     float* __restrict__ Hs)
+{
+    const int64_t leaf = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (leaf >= nl) return;  // whole wavefronts
+    const int n = lf_count[leaf];
+    if (n < 2 || n > 64) return;
+    const int p0 = lf_start[leaf];
+    // key: H descending, then index ascending; empty lanes last
+    float k = lane < n ? Hs[p0 + lane] : -INFINITY;
+    uint32_t v = lane < n ? perm[p0 + lane] : 0xffffffffu;
+    for (int size = 2; size <= 64; size <<= 1) {
+        for (int stride = size >> 1; stride >= 1; stride >>= 1) {
+            const float ko = __shfl_xor(k, stride, 64);
+            const uint32_t vo = (uint32_t)__shfl_xor((int)v, stride, 64);
+            const bool before = (ko > k) || (ko == k && vo < v);  // the partner sorts first
+            const bool lower = (lane & stride) == 0;              // this lane keeps the first of the pair
+            const bool desc_block = (lane & size) == 0;           // blocks alternate in bitonic order
+            const bool take = (lower == desc_block) ? before : !before;
+            if (take) {
+                k = ko;
+                v = vo;
+            }
+        }
+    }
+    if (lane < n) {
+        Hs[p0 + lane] = k;
+        perm[p0 + lane] = v;
+    }
+}
+
 __global__ void k_leaf_fix(int64_t nl, const int* __restrict__ lf_node, const int* __restrict__ nd_count,
                            const unsigned* __restrict__ nd_hmax, int* __restrict__ nd_leaf,
                            int* __restrict__ lf_count, float* __restrict__ lf_hmax)
@@ -947,6 +986,8 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_leaf_fix<<<blocks_for(nl, BS), BS, 0, s>>>(nl, lf_node, static_cast<int*>(c->nd_count.p),
                                                  static_cast<unsigned*>(c->nd_hmax.p),
                                                  static_cast<int*>(c->nd_leaf.p), lf_count, lf_hmax);
+    SPH_HIP(hipGetLastError());
+    k_leaf_sort_h<<<(unsigned)blocks_for(nl * 64, 256), 256, 0, s>>>(nl, lf_start, lf_count, perm, Hs);
     SPH_HIP(hipGetLastError());
     {
         int* box_leaf = ensure<int>(c, c->box_leaf, c->n_boxes + 1);
