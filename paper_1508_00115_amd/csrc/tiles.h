@@ -403,15 +403,17 @@ __device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<
 }
 
 
-// The cell-box test of a staged force candidate: its squared distance (cell
-// frame) from the cell's box [-hw, hw]^3. A candidate farther than every
-// search radius of the cell's particles and than its own h pairs with none
-// of them: the 3x3x3 block of cells is a cube, the region within reach of the
-// cell a rounded box about a quarter smaller. (The density loop stages
-// without it: there the compaction cost more than the tests it saved.)
-// An axis-aligned box in the cell frame for the cull of staged candidates:
-// the cell's own box (centre 0, half width hw in every axis, widened by the
-// drift bound) or the bounding box of the particles of one pass.
+// Culling of staged candidates. A candidate farther from a box than every
+// search radius of the particles inside it (and, for the force, than its own
+// h) pairs with none of them: the 3x3x3 block of cells is a cube, the region
+// within reach of a cell a rounded box about a quarter smaller, and that of
+// a pass's particles smaller still. The force tests its candidates against
+// the box of each pass; the density only on non-uniform cells, against the
+// cell's box (on a uniform grid the compaction costs more than the tests it
+// saves); the re-scanning kernel against the box of each group of particles.
+// An axis-aligned box in the cell frame: the cell's own box (centre 0, half
+// width hw in every axis, widened by the drift bound) or the bounding box of
+// the particles of one pass.
 struct CullBox {
     float cx, cy, cz, hx, hy, hz;
 };
