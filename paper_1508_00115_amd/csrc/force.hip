@@ -357,25 +357,33 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
 // Per-box sums of the cells' shares: block b adds the shares of its leaves
 // [box_leaf[b], box_leaf[b + 1]) in a fixed order (strided partial sums, then
 // a tree in LDS), so the result does not depend on scheduling.
-__global__ void __launch_bounds__(256) k_cons_reduce(const int* __restrict__ box_leaf,
-                                                     const double* __restrict__ cons_part, double* __restrict__ cons)
+constexpr int CR_BS = 1024;
+
+__global__ void __launch_bounds__(CR_BS) k_cons_reduce(const int* __restrict__ box_leaf,
+                                                       const double* __restrict__ cons_part, double* __restrict__ cons)
 {
-    __shared__ double red[4][256];
+    __shared__ double red[4][CR_BS];
     const int b = blockIdx.x;
     const int t = threadIdx.x;
     const int l0 = box_leaf[b], l1 = box_leaf[b + 1];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l = l0 + t; l < l1; l += 256) {
+    // two partial sums per thread (leaves t, t + 2 CR_BS, ... and t + CR_BS,
+    // t + 3 CR_BS, ...): two loads in flight, one fixed order
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = l0 + t; l < l1; l += 2 * CR_BS) {
+        const bool second = l + CR_BS < l1;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] += cons_part[4 * (int64_t)l + k];
+        for (int k = 0; k < 4; ++k) {
+            v[k] += cons_part[4 * (int64_t)l + k];
+            w[k] += second ? cons_part[4 * (int64_t)(l + CR_BS) + k] : 0.0;
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+    for (int k = 0; k < 4; ++k) red[k][t] = v[k] + w[k];
     __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) {
+    for (int half = CR_BS / 2; half >= 1; half >>= 1) {
+        if (t < half) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + w];
+            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + half];
         }
         __syncthreads();
     }
@@ -461,7 +469,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_FORCE_K1, s);
     if (cons_d) {
-        k_cons_reduce<<<c->n_boxes, 256, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);
+        k_cons_reduce<<<c->n_boxes, CR_BS, 0, s>>>(static_cast<int*>(c->box_leaf.p), A.cons_part, cons_d);
         SPH_HIP(hipGetLastError());
     }
 }
