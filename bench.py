@@ -57,9 +57,11 @@ PEAK_HBM_GBS = 8000.0
 #   a candidate pair tested and rejected            8   (3 sub, r^2, compare)
 #   a density interaction at one trial h           26   (+1 sqrt)
 #   a force interaction, gather form (per side)    61   (+1 rsqrt, +1 rcp)
+#   a near-field gravity pair (per side)           22   (+1 rsqrt)
 FLOP_REJECT = 8
 FLOP_DENSITY = 26
 FLOP_FORCE = 61
+FLOP_GRAVITY = 22
 
 WORKLOADS = {
     # name: (generator, description, profile tag)
@@ -301,6 +303,26 @@ def culling(inp: Inputs, sph, params: dict) -> dict:
             "force_candidates_per_interaction": st["candidates_force"] / max(1, st["interactions_force"])}
 
 
+def gravity(inp: Inputs, sph, params: dict, steps: int) -> dict:
+    """Near-field gravity (sph_gravity_p2p) on the same cells with the
+    workload's masses, r_cut = 0.95 x the smallest h guess (inside every
+    particle's search radius), G = 1, eps = 1e-3: the kernel's HIP-event time
+    averaged over `steps` calls after one untimed call."""
+    ctx = inp.context(sph, timing=1, **params)
+    rc = 0.95 * float(inp.d["h0"].min())
+    _, pairs, cand = ctx.gravity_p2p(inp.mass, 1.0, 1e-3, rc, acc=inp.acc, candidates=True)
+    kms = []
+    for _ in range(steps):
+        ctx.gravity_p2p(inp.mass, 1.0, 1e-3, rc, acc=inp.acc)
+        kms.append(ctx.timings()["gravity_kernel_ms"])
+    ctx.close()
+    ms = float(np.mean(kms))
+    alg = FLOP_GRAVITY * pairs + FLOP_REJECT * (cand - pairs)
+    return {"r_cut": rc, "pairs": pairs, "candidates": cand, "candidates_per_pair": cand / max(1, pairs),
+            "kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "calls": steps,
+            "algorithmic_flop_per_launch": alg, "frac_fp32_peak": alg / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+
+
 def extra_set(name: str, sph, args, stream, dev) -> dict:
     """The captured pass on another workload, with its kernel times."""
     import torch
@@ -459,6 +481,7 @@ def main() -> int:
                        "note": "sph_density_f64 + sph_force_f64 with the conservation sums, same cells"},
         "speedup_vs_fp64_plain": value / value64,
         "balsara": bal,
+        "gravity_p2p": gravity(inp, sph, params, args.steps),
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
         "autotune_top5": None if tuned is None else [

@@ -161,6 +161,8 @@ typedef struct {
                                   calls and the rebuilds the library made after
                                   a drift or for an h that outgrew its cell
                                   (counted whatever sph_params.timing) */
+    double gravity_kernel_ms;  /* near-field gravity kernel of the last
+                                  sph_gravity_p2p */
 } sph_timings;
 
 typedef struct {
@@ -391,6 +393,40 @@ sph_status sph_predict_h(sph_ctx* ctx, double dt, float* h, void* stream);
  * `stream`.
  */
 sph_status sph_timestep_noalloc(sph_ctx* ctx, double courant, double* dt, void* stream);
+
+/*
+ * Near-field gravity, particle-particle (the paper's section 2, Eq. 3:
+ * Newton's pull summed over the other particles; section 3.2 evaluates the
+ * pairs of neighbouring cells directly and the far field by multipoles, this
+ * call computes the direct part over the current cells):
+ *   g_i = -G sum_{j != i} m_j r_ij (|r_ij|^2 + eps^2)^(-3/2) S(|r_ij| / r_cut),
+ * r_ij the minimum image of x_i - x_j in i's box, eps a Plummer softening and
+ * S(x) = (1 - x^2)^2 for x < 1, 0 beyond (zero with zero slope at the cutoff,
+ * so g is continuous in the positions; the part 1 - S is the far field's).
+ * Coincident pairs add nothing. FP32 arithmetic; each particle sums its own
+ * pairs (no atomics), so repeated calls give the same bits.
+ *   mass    device, n floats, caller order, each finite and > 0 (not
+ *           necessarily the masses of the density)
+ *   G       finite
+ *   eps     finite, >= 0
+ *   r_cut   > 0 and at most the smallest search radius of the cells
+ *           (sph_params.h_margin x the smallest h of the last build) less
+ *           twice the distance the particles may have moved since the build:
+ *           every pair closer than that is in the cells' neighbour lists (and
+ *           r_cut is below a third of every box, so one image per pair)
+ *   acc     device, n x 3 floats, caller order, out (caller-owned; the
+ *           gravity alone, not added to anything)
+ *   counts  host, nullable, 2 int64 out: [0] ordered pairs (i, j) with
+ *           0 < r_ij < r_cut, [1] (particle, candidate) pairs the kernel
+ *           tested (the particles of the neighbour cells within reach)
+ * Uses the positions of the last sph_build_cells / sph_drift (after drifts
+ * that used up the cells' margin it rebuilds them around the last build's
+ * guesses first, as sph_density would). Errors: SPH_E_ARG (null, a bad value,
+ * an r_cut beyond the limits above, a mass <= 0 or non-finite), SPH_E_STATE
+ * (no cells), SPH_E_NOMEM, SPH_E_HIP. Synchronises `stream`.
+ */
+sph_status sph_gravity_p2p(sph_ctx* ctx, const float* mass, double G, double eps, double r_cut, float* acc,
+                           int64_t* counts, void* stream);
 
 /*
  * Balsara factors B of the last force pass (see sph_params.balsara), in the

@@ -19,7 +19,9 @@ here). Pairs at r = 0 add nothing (no direction).
 
 Two code paths, sharing no arithmetic: ``p2p`` finds the pairs with scipy's
 cKDTree and adds every pair to both of its particles; ``p2p_dense`` takes
-dense minimum-image separation matrices and sums each row on its own.
+dense minimum-image separation matrices and sums each row on its own
+(``p2p_rows``: the same for chosen rows only, for sampled checks of sets too
+large for the tree path).
 """
 
 from __future__ import annotations
@@ -85,3 +87,28 @@ def p2p_dense(pos, mass, G: float, eps: float, r_cut: float, L: float = 1.0) -> 
     x = np.where(inside, r / r_cut, 1.0)
     f = np.where(inside, G * mass[None, :] * (1.0 - x * x) ** 2 / (r * r + eps * eps) ** 1.5, 0.0)
     return -np.einsum("ij,ijk->ik", f, d)
+
+
+def p2p_rows(pos, mass, G: float, eps: float, r_cut: float, rows, L: float = 1.0) -> dict:
+    """Acceleration, gross scale and pair count of the particles ``rows``
+    only, each row summed over every particle of the set (dense, one row
+    block at a time)."""
+    pos = np.mod(np.asarray(pos, dtype=np.float64), L)
+    mass = np.asarray(mass, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    if not (0.0 < r_cut < 0.5 * L):
+        raise ValueError("r_cut must lie in (0, L/2)")
+    acc = np.zeros((len(rows), 3))
+    gross = np.zeros(len(rows))
+    npair = np.zeros(len(rows), dtype=np.int64)
+    for a in range(0, len(rows), 64):
+        rb = rows[a:a + 64]
+        d = pos[rb][:, None, :] - pos[None, :, :]
+        d -= L * np.rint(d / L)
+        r = np.sqrt(np.sum(d * d, axis=2))
+        inside = (r > 0.0) & (r < r_cut)
+        f = np.where(inside, pair_force(np.where(inside, r, 0.0), mass[None, :], G, eps, r_cut), 0.0)
+        acc[a:a + 64] = -np.sum(f[:, :, None] * d, axis=1)
+        gross[a:a + 64] = np.sum(f * r, axis=1)
+        npair[a:a + 64] = np.sum(inside, axis=1)
+    return {"acc": acc, "gross": gross, "npair": npair}

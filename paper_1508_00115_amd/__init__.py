@@ -29,7 +29,7 @@ EXPORTS = ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_f
            "sph_density_f64", "sph_force_f64", "sph_get_timings", "sph_status_string",
            "sph_last_error", "sph_version", "sph_struct_size", "sph_pass", "sph_get_build_info",
            "sph_kick", "sph_drift", "sph_timestep", "sph_get_balsara", "sph_timestep_noalloc",
-           "sph_predict_h")
+           "sph_predict_h", "sph_gravity_p2p")
 
 
 class sph_params(ctypes.Structure):
@@ -71,7 +71,7 @@ class sph_timings(ctypes.Structure):
                 ("force_kernel_ms", ctypes.c_double), ("force_call_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("density_launches", ctypes.c_int32),
                 ("density_rescan_ms", ctypes.c_double), ("pass_call_ms", ctypes.c_double),
-                ("builds", ctypes.c_int64)]
+                ("builds", ctypes.c_int64), ("gravity_kernel_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -135,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sph_predict_h.restype = ctypes.c_int
     lib.sph_get_balsara.argtypes = [P, P, P]
     lib.sph_get_balsara.restype = ctypes.c_int
+    lib.sph_gravity_p2p.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P]
+    lib.sph_gravity_p2p.restype = ctypes.c_int
     lib.sph_struct_size.argtypes = [ctypes.c_int32]
     lib.sph_struct_size.restype = ctypes.c_int32
     _lib = lib
@@ -221,6 +223,10 @@ def sph_timestep_noalloc(ctx, courant, dt_out, stream) -> int:
 
 def sph_get_balsara(ctx, balsara, stream) -> int:
     return load_library().sph_get_balsara(ctx, balsara, stream)
+
+
+def sph_gravity_p2p(ctx, mass, G, eps, r_cut, acc, counts_out, stream) -> int:
+    return load_library().sph_gravity_p2p(ctx, mass, G, eps, r_cut, acc, counts_out, stream)
 
 
 def sph_get_timings(ctx, out) -> int:
@@ -411,6 +417,21 @@ class Context:
         rc = sph_get_balsara(self.ctx, _dev(out, torch.float32, (self.n,), "balsara"), _stream(stream))
         _check(rc, self.ctx)
         return out
+
+    def gravity_p2p(self, mass, G, eps, r_cut, acc=None, stream=None, candidates=False):
+        """sph_gravity_p2p: the near-field gravity of every particle over the
+        pairs closer than r_cut (float32, (n, 3), input order) and the number
+        of ordered pairs (and of the candidate pairs tested, with
+        candidates=True)."""
+        import torch
+        n = self.n
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        counts = (ctypes.c_int64 * 2)()
+        rc = sph_gravity_p2p(self.ctx, _dev(mass, torch.float32, (n,), "mass"), float(G), float(eps), float(r_cut),
+                             _dev(acc, torch.float32, (n, 3), "acc"), counts, _stream(stream))
+        _check(rc, self.ctx)
+        return (acc, counts[0], counts[1]) if candidates else (acc, counts[0])
 
     def step(self, dt, pos, mass, h, vel, u, acc, dudt, rho=None, f=None, stream=None,
              predict_h=True) -> dict:

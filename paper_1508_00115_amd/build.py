@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsph.so")
 SOURCES = ["api.hip", "build.hip", "scan_sort.hip", "density.hip", "force.hip", "pass.hip", "plain64.hip", "integrate.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "gravity.hip"]
 
 
 def hipcc() -> str:

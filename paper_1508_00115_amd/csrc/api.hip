@@ -123,7 +123,7 @@ void sph_destroy(sph_ctx* c)
                        &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->u_s, &c->status,
                        &c->st_s, &c->jf, &c->vsig_s, &c->bal_s, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
                        &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom, &c->cells_d, &c->p_cntd, &c->divv_s,
-                       &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt, &c->build_out};
+                       &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt, &c->build_out, &c->jg};
     for (sph::Buf* b : all) sph::free_buf(c, *b);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
@@ -228,6 +228,16 @@ sph_status sph_timestep_noalloc(sph_ctx* c, double courant, double* dt, void* st
         SPH_REQUIRE(dt, SPH_E_ARG, "null dt");
         set_device(c);
         *dt = sph::timestep_noalloc(c, courant, (hipStream_t)stream);
+    });
+}
+
+sph_status sph_gravity_p2p(sph_ctx* c, const float* mass, double G, double eps, double r_cut, float* acc,
+                           int64_t* counts, void* stream)
+{
+    if (!c) return SPH_E_ARG;
+    return guarded(c, [&] {
+        set_device(c);
+        sph::gravity_p2p(c, mass, G, eps, r_cut, acc, counts, (hipStream_t)stream);
     });
 }
 

@@ -196,6 +196,7 @@ struct sph_ctx {
 
     // ---- density / force state (sorted order) ---------------------------------
     sph::Buf jd;             // float4 (x, y, z, m)
+    sph::Buf jg;             // float4 (x, y, z, m) of the near-field gravity (its own masses)
     sph::Buf hs, rhos, fs;   // float, sorted
     sph::Buf u_s;            // float, sorted u (the pass's fused ghost step)
     sph::Buf status;         // uint8, caller order
@@ -231,7 +232,7 @@ struct sph_ctx {
 
     // ---- tuning and timing ------------------------------------------------------------
     int n_cu = 256;
-    hipEvent_t ev[9] = {};
+    hipEvent_t ev[11] = {};
     sph_timings tm{};
     sph_build_info binfo{};
 
@@ -245,7 +246,8 @@ struct sph_ctx {
 
 // Event pairs of the timing mode.
 enum { EV_DENS_K0 = 0, EV_DENS_K1 = 1, EV_DENS_C0 = 2, EV_DENS_C1 = 3,
-       EV_FORCE_K0 = 4, EV_FORCE_K1 = 5, EV_FORCE_C0 = 6, EV_FORCE_C1 = 7, EV_DENS_KM = 8 };
+       EV_FORCE_K0 = 4, EV_FORCE_K1 = 5, EV_FORCE_C0 = 6, EV_FORCE_C1 = 7, EV_DENS_KM = 8,
+       EV_GRAV_K0 = 9, EV_GRAV_K1 = 10 };
 
 inline void ev_record(sph_ctx* c, int k, hipStream_t s)
 {
@@ -424,6 +426,9 @@ void fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
 
 void density_f32(sph_ctx* c, const float* mass, float* h, float* rho, float* f, float* nw,
                  sph_stats* st, hipStream_t s);
+// Near-field gravity over the pairs of the current cells (sph_gravity_p2p).
+void gravity_p2p(sph_ctx* c, const float* mass, double G, double eps, double r_cut, float* acc,
+                 int64_t* counts, hipStream_t s);
 void force_f32(sph_ctx* c, const float* vel, const float* u, float* acc, float* dudt,
                double* cons, sph_stats* st, hipStream_t s);
 // Allocate what one density pass / force pass needs (never under capture).

@@ -1,0 +1,195 @@
+// Near-field gravity, particle-particle: Newton's pull of section 2, Eq. 3 of
+// the Swift paper, summed directly over the pairs of neighbouring cells, the
+// part that the tree code of section 3.2 evaluates particle by particle:
+//
+//   g_i = -G sum_{j != i} m_j r_ij (r_ij^2 + eps^2)^(-3/2) S(r_ij / r_cut),
+//
+// r_ij the minimum image of x_i - x_j, eps a Plummer softening and
+// S(x) = (1 - x^2)^2 below 1, 0 beyond: the window takes the pull to zero
+// with zero slope at the cutoff, so the sum is continuous in the positions
+// (the remaining 1 - S belongs to a far field of multipoles, not computed
+// here). Coincident pairs add nothing.
+//
+// Work unit: one leaf cell per wavefront, as in the density loop. Its
+// candidates are the particles of the leaves within the cell's own largest
+// search radius (the first part of its neighbour records), which the cutoff
+// may not exceed, so every pair inside r_cut is among them. They are staged
+// through LDS in chunks of GCH, shifted into the cell frame, keeping only
+// those within r_cut of the bounding box of the particles in the pass (the
+// cutoff is usually well inside the search radius the lists were built for);
+// the lanes of each particle split the kept candidates and add up their
+// pairs, then meet in a group sum. It is a gather: each particle sums its own
+// pairs, so there are no atomics and the result has the same bits on every
+// run.
+#include <cmath>
+
+#include "common.h"
+#include "tiles.h"
+
+namespace {
+
+constexpr int GBS = 64;   // one wavefront per block
+constexpr int GCH = 256;  // candidates per staged chunk
+
+struct GravArgs {
+    const float4* jg;       // sorted (x, y, z) in the leaf frame, m
+    const uint32_t* perm;   // sorted index -> caller index
+    const int4* cells;      // per schedule slot: first particle, count, first record, density records
+    const int2* p_rec;      // per record: first particle and count of the neighbour leaf
+    const float4* p_shift;  // per record: frame shift of the neighbour leaf
+    float* acc;             // caller order, 3 per particle
+    int64_t* ctr;
+    int n_slots;
+    float G, eps2, rc2, inv_rc2;
+};
+
+// Sorted copies of position (leaf frame) and mass; counts non-positive or
+// non-finite masses.
+__global__ void __launch_bounds__(256) k_grav_prologue(int64_t n, const uint32_t* __restrict__ perm,
+                                                       const float4* __restrict__ xrel,
+                                                       const float* __restrict__ mass, float4* __restrict__ jg,
+                                                       int64_t* __restrict__ ctr)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (p < n) {
+        const float m = mass[perm[p]];
+        const float4 x = xrel[p];
+        jg[p] = make_float4(x.x, x.y, x.z, m);
+        bad = !(m > 0.0f) || !isfinite(m);
+    }
+    const int n_bad = __syncthreads_count(bad);
+    if (threadIdx.x == 0 && n_bad) atomicAdd((unsigned long long*)&ctr_slot(ctr)[CT_BAD_INPUT], (unsigned long long)n_bad);
+}
+
+__global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
+{
+    __shared__ float4 tile[GCH];
+    const int lane = threadIdx.x & 63;
+    const int slot = xcd_block_index();  // each XCD takes its own run of slots
+    if (slot >= A.n_slots) return;       // whole wavefront
+    const int4 ci = A.cells[slot];
+    const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np = ci.w;
+    NbrCursor cu;
+    cursor_init(cu, A.p_rec, A.p_shift, pb0, np);
+    const int nj = np <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np);
+    // lanes per particle: the cell's particles spread over the wavefront
+    int lpi = 1;
+    while (lpi < 16 && 2 * lpi * ni <= 64) lpi *= 2;
+    const int per_pass = 64 / lpi;
+    const int g = lane / lpi, sub = lane & (lpi - 1);
+    const float reach2 = cull_reach2(uniform_f(sqrtf(A.rc2)));
+    int pairs = 0;
+    int64_t tested = 0;
+    for (int ib = 0; ib < ni; ib += per_pass) {
+        const int gi = ib + g;
+        const bool valid = gi < ni;
+        const int i = i0 + (valid ? gi : 0);
+        const float4 xi = A.jg[i];
+        // only the candidates within r_cut of the pass's bounding box can pair
+        const CullBox box = pass_box(xi.x, xi.y, xi.z, valid);
+        const int n_valid = min(per_pass, ni - ib);
+        float ax = 0.0f, ay = 0.0f, az = 0.0f;
+        int cnt = 0;
+        int len;
+        for (int c0 = 0; c0 < nj; c0 += len) {
+            cursor_seek(cu, A.p_rec, A.p_shift, c0);
+            len = cursor_chunk(cu, c0, GCH);
+            const int kept = stage_fast_culled<1, GCH>(tile, A.jg, cu.nb, c0 - cu.off0, len, box, reach2);
+            tested += (int64_t)n_valid * kept;
+            if (valid) {
+                for (int k = sub; k < kept; k += lpi) {
+                    const float4 pj = tile[k];
+                    const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const bool in = r2 < A.rc2 && r2 > 0.0f;
+                    const float s = 1.0f - r2 * A.inv_rc2;                  // 1 - x^2
+                    const float inv = __builtin_amdgcn_rsqf(r2 + A.eps2);  // (r^2 + eps^2)^(-1/2)
+                    const float f = in ? pj.w * (s * s) * (inv * inv * inv) : 0.0f;
+                    ax = fmaf(-f, dx, ax);
+                    ay = fmaf(-f, dy, ay);
+                    az = fmaf(-f, dz, az);
+                    cnt += in ? 1 : 0;
+                }
+            }
+            wave_sync_lds();  // every lane is done with the tile before it is staged again
+        }
+        ax = group_sum(ax, lpi);
+        ay = group_sum(ay, lpi);
+        az = group_sum(az, lpi);
+        cnt = group_sum_i(cnt, lpi);
+        if (valid && sub == 0) {
+            const uint32_t o = A.perm[i];
+            A.acc[3 * (int64_t)o + 0] = A.G * ax;
+            A.acc[3 * (int64_t)o + 1] = A.G * ay;
+            A.acc[3 * (int64_t)o + 2] = A.G * az;
+            pairs += cnt;
+        }
+    }
+    // the gravity call has the counters to itself
+    ctr_wave_add(A.ctr, CT_FORCE_INTER, pairs);
+    ctr_add_uniform(A.ctr, CT_FORCE_CAND, tested);
+}
+
+}  // namespace
+
+namespace sph {
+
+void gravity_p2p(sph_ctx* c, const float* mass, double G, double eps, double r_cut, float* acc,
+                 int64_t* counts, hipStream_t s)
+{
+    SPH_REQUIRE(c->built, SPH_E_STATE, "sph_gravity_p2p before sph_build_cells");
+    SPH_REQUIRE(mass && acc, SPH_E_ARG, "null mass or acc");
+    SPH_REQUIRE(std::isfinite(G) && std::isfinite(eps) && eps >= 0.0, SPH_E_ARG,
+                "G must be finite and eps finite and >= 0");
+    SPH_REQUIRE(std::isfinite(r_cut) && r_cut > 0.0, SPH_E_ARG, "r_cut must be finite and > 0");
+    // after drifts that used up the margin of the cells, rebuild them around
+    // the guesses of the last build (as the density would)
+    check_drift(c, nullptr, s);
+    finish_build_read(c);  // the smallest search radius of the build
+    // the lists hold every pair closer than the search radius less twice the
+    // distance the particles may have moved since the build. A search radius
+    // is at most a third of its box (a build condition), so no two periodic
+    // images of one particle both lie inside r_cut.
+    unsigned w[4] = {0u, 0u, 0u, 0u};
+    SPH_HIP(hipMemcpyAsync(w, c->drift.p, sizeof(w), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    float delta;
+    std::memcpy(&delta, &w[0], 4);
+    SPH_REQUIRE(r_cut + 2.0 * (double)delta <= (double)c->h_min, SPH_E_ARG,
+                "r_cut " + std::to_string(r_cut) + " exceeds the smallest search radius of the cells (" +
+                    std::to_string(c->h_min) + ", less twice the drift since the build)");
+    const int64_t n = c->n;
+    int64_t* ctr = static_cast<int64_t*>(c->counters.p);
+    float4* jg = ensure<float4>(c, c->jg, n);
+    fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);
+    k_grav_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
+                                                       static_cast<float4*>(c->xrel.p), mass, jg, ctr);
+    SPH_HIP(hipGetLastError());
+    GravArgs A;
+    A.jg = jg;
+    A.perm = static_cast<uint32_t*>(c->perm.p);
+    A.cells = static_cast<int4*>(c->cells_d.p);
+    A.p_rec = static_cast<int2*>(c->p_rec.p);
+    A.p_shift = static_cast<float4*>(c->p_shift.p);
+    A.acc = acc;
+    A.ctr = ctr;
+    A.n_slots = (int)c->n_leaves;
+    A.G = (float)G;
+    A.eps2 = (float)(eps * eps);
+    A.rc2 = (float)(r_cut * r_cut);
+    A.inv_rc2 = (float)(1.0 / (r_cut * r_cut));
+    ev_record(c, EV_GRAV_K0, s);
+    k_gravity<<<(unsigned)std::max<int64_t>(c->n_leaves, 1), GBS, 0, s>>>(A);
+    SPH_HIP(hipGetLastError());
+    ev_record(c, EV_GRAV_K1, s);
+    const int64_t* hc = read_counters(c, s);
+    SPH_REQUIRE(hc[CT_BAD_INPUT] == 0, SPH_E_ARG, "non-positive or non-finite mass");
+    if (counts) {
+        counts[0] = hc[CT_FORCE_INTER];
+        counts[1] = hc[CT_FORCE_CAND];
+    }
+    c->tm.gravity_kernel_ms = ev_ms(c, EV_GRAV_K0, EV_GRAV_K1);
+}
+
+}  // namespace sph

@@ -16,6 +16,7 @@ what it must satisfy rather than by retyping it:
 import numpy as np
 import pytest
 from scipy.integrate import quad
+from scipy.spatial import cKDTree
 
 from oracle import gravity as og
 
@@ -91,6 +92,27 @@ def test_dense_rows_match_tree_pairs_and_conserve_momentum(seed):
     assert t["npair"] % 2 == 0 and t["npair"] > 0
     # gross scale: at least the magnitude of the sum
     assert np.all(np.linalg.norm(t["acc"], axis=1) <= t["gross"] * (1 + 1e-12))
+
+
+def test_rows_match_tree_pairs():
+    """The row-sampled form against the tree pairs, rows spread over the set
+    (a clump across the periodic corner included)."""
+    rng = np.random.default_rng([1508, 75])
+    n = 400
+    pos = rng.random((n, 3))
+    pos[:50] = np.mod(0.03 * rng.standard_normal((50, 3)), 1.0)
+    mass = rng.uniform(0.5, 2.0, n)
+    G, eps, rc = 0.7, 0.002, 0.12
+    t = og.p2p(pos, mass, G, eps, rc)
+    rows = np.concatenate([np.arange(0, 50, 7), rng.choice(n, 70, replace=False)])
+    w = og.p2p_rows(pos, mass, G, eps, rc, rows)
+    np.testing.assert_allclose(w["acc"], t["acc"][rows], rtol=0, atol=1e-12 * t["gross"].max())
+    np.testing.assert_allclose(w["gross"], t["gross"][rows], rtol=1e-12)
+    # pairs of each row from a periodic ball query (itself excluded; no two
+    # particles coincide and none sits at r_cut)
+    tree = cKDTree(pos, boxsize=1.0)
+    ball = tree.query_ball_point(pos[rows], rc, return_length=True) - 1
+    assert np.array_equal(w["npair"], ball)
 
 
 def test_lattice_feels_no_pull():
