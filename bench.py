@@ -122,6 +122,7 @@ def cpu_baseline(d: dict, min_seconds: float, one_thread_seconds: float) -> dict
 KERNEL_SOURCES = {
     "k_density": ["density.hip", "tiles.h", "common.h"],
     "k_force": ["force.hip", "tiles.h", "common.h"],
+    "k_gravity": ["gravity.hip", "tiles.h", "common.h"],
 }
 
 
