@@ -304,7 +304,7 @@ def culling(inp: Inputs, sph, params: dict) -> dict:
             "force_candidates_per_interaction": st["candidates_force"] / max(1, st["interactions_force"])}
 
 
-def gravity(inp: Inputs, sph, params: dict, steps: int) -> dict:
+def gravity(inp: Inputs, sph, params: dict, steps: int, tag: str) -> dict:
     """Near-field gravity (sph_gravity_p2p) on the same cells with the
     workload's masses, r_cut = 0.95 x the smallest h guess (inside every
     particle's search radius), G = 1, eps = 1e-3: the kernel's HIP-event time
@@ -319,9 +319,12 @@ def gravity(inp: Inputs, sph, params: dict, steps: int) -> dict:
     ctx.close()
     ms = float(np.mean(kms))
     alg = FLOP_GRAVITY * pairs + FLOP_REJECT * (cand - pairs)
+    traffic = _traffic("k_gravity", tag, params)
     return {"r_cut": rc, "pairs": pairs, "candidates": cand, "candidates_per_pair": cand / max(1, pairs),
             "kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "calls": steps,
-            "algorithmic_flop_per_launch": alg, "frac_fp32_peak": alg / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+            "algorithmic_flop_per_launch": alg, "frac_fp32_peak": alg / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "traffic": None if traffic is None else traffic["bytes"],
+            "traffic_gbs": None if traffic is None else traffic["bytes"] / (ms * 1e-3) / 1e9}
 
 
 def extra_set(name: str, sph, args, stream, dev) -> dict:
@@ -482,7 +485,7 @@ def main() -> int:
                        "note": "sph_density_f64 + sph_force_f64 with the conservation sums, same cells"},
         "speedup_vs_fp64_plain": value / value64,
         "balsara": bal,
-        "gravity_p2p": gravity(inp, sph, params, args.steps),
+        "gravity_p2p": gravity(inp, sph, params, args.steps, tag),
         "cell_params": params or "library defaults",
         "cell_params_from": tune_source,
         "autotune_top5": None if tuned is None else [

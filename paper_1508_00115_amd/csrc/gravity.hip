@@ -62,9 +62,72 @@ __global__ void __launch_bounds__(256) k_grav_prologue(int64_t n, const uint32_t
     if (threadIdx.x == 0 && n_bad) atomicAdd((unsigned long long*)&ctr_slot(ctr)[CT_BAD_INPUT], (unsigned long long)n_bad);
 }
 
+// Store a fetched chunk (x, y, z, m in the cell frame) keeping only the
+// candidates within reach of `box`, packed from slot 0; the slots after them
+// up to GCH get a massless candidate far outside r_cut, so the pair loop may
+// run to a multiple of its stride without a bounds test. Returns how many
+// were kept.
+__device__ __forceinline__ int commit_culled(float4* sj, const ChunkRegs<1, GCH>& R, const CullBox& box,
+                                             float reach2)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int PER = GCH / 64;
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        float4 a = R.v[r][0];
+        a.x += R.s[r][0];
+        a.y += R.s[r][1];
+        a.z += R.s[r][2];
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, box) < reach2;
+        const uint64_t m = __ballot(keep);
+        if (keep) sj[n + lanes_below(m)] = a;
+        n += __popcll(m);
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int t = lane + 64 * r;
+        if (t >= n) sj[t] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f);
+    }
+    wave_sync_lds();
+    return n;
+}
+
+// The pairs of one particle with the staged candidates sub, sub + LPI, ...
+// below len (rounded up to a multiple of 4 LPI: the padding adds nothing),
+// four tile reads in flight at once. The pull on i is -m_j S (r^2 + eps^2)^(-3/2)
+// r_ij per pair inside r_cut; a pair outside (or at r = 0) is selected away,
+// so the far padding's overflows never reach the sums.
+template <int LPI>
+__device__ __forceinline__ void pair_chunk(const float4* tc, int len, const float4& xi, float rc2, float inv_rc2,
+                                           float eps2, float& ax, float& ay, float& az, int& cnt)
+{
+    const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
+    for (int k0 = 0; k0 < len_pad; k0 += 4 * LPI, tc += 4 * LPI) {
+        float4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = tc[u * LPI];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float dx = xi.x - pj[u].x, dy = xi.y - pj[u].y, dz = xi.z - pj[u].z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool in = r2 < rc2 && r2 > 0.0f;
+            const float s = fmaf(-r2, inv_rc2, 1.0f);                 // 1 - x^2
+            const float inv = __builtin_amdgcn_rsqf(r2 + eps2);      // (r^2 + eps^2)^(-1/2)
+            const float f = in ? pj[u].w * (s * s) * (inv * inv * inv) : 0.0f;
+            ax = fmaf(-f, dx, ax);
+            ay = fmaf(-f, dy, ay);
+            az = fmaf(-f, dz, az);
+            cnt += in ? 1 : 0;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
 {
     __shared__ float4 tile[GCH];
+    __shared__ uint8_t marks[GCH];  // record starts of the chunk being fetched
     const int lane = threadIdx.x & 63;
     const int slot = xcd_block_index();  // each XCD takes its own run of slots
     if (slot >= A.n_slots) return;       // whole wavefront
@@ -91,27 +154,31 @@ __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
         const int n_valid = min(per_pass, ni - ib);
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
         int cnt = 0;
+        ChunkRegs<1, GCH> R;
+        cursor_seek(cu, A.p_rec, A.p_shift, 0);
+        fetch_chunk(R, A.jg, cu.nb, 0, cursor_chunk(cu, 0, GCH), marks);
         int len;
         for (int c0 = 0; c0 < nj; c0 += len) {
-            cursor_seek(cu, A.p_rec, A.p_shift, c0);
-            len = cursor_chunk(cu, c0, GCH);
-            const int kept = stage_fast_culled<1, GCH>(tile, A.jg, cu.nb, c0 - cu.off0, len, box, reach2);
-            tested += (int64_t)n_valid * kept;
-            if (valid) {
-                for (int k = sub; k < kept; k += lpi) {
-                    const float4 pj = tile[k];
-                    const float dx = xi.x - pj.x, dy = xi.y - pj.y, dz = xi.z - pj.z;
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const bool in = r2 < A.rc2 && r2 > 0.0f;
-                    const float s = 1.0f - r2 * A.inv_rc2;                  // 1 - x^2
-                    const float inv = __builtin_amdgcn_rsqf(r2 + A.eps2);  // (r^2 + eps^2)^(-1/2)
-                    const float f = in ? pj.w * (s * s) * (inv * inv * inv) : 0.0f;
-                    ax = fmaf(-f, dx, ax);
-                    ay = fmaf(-f, dy, ay);
-                    az = fmaf(-f, dz, az);
-                    cnt += in ? 1 : 0;
-                }
+            len = R.len;
+            const int kept = commit_culled(tile, R, box, reach2);
+            // the next chunk's loads are in flight while this one is summed
+            const int nx = c0 + len;
+            if (nx < nj) {
+                cursor_seek(cu, A.p_rec, A.p_shift, nx);
+                fetch_chunk(R, A.jg, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, GCH), marks);
             }
+            tested += (int64_t)n_valid * kept;
+            const float4* tc = tile + sub;
+            if (lpi == 1)
+                pair_chunk<1>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+            else if (lpi == 2)
+                pair_chunk<2>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+            else if (lpi == 4)
+                pair_chunk<4>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+            else if (lpi == 8)
+                pair_chunk<8>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+            else
+                pair_chunk<16>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
             wave_sync_lds();  // every lane is done with the tile before it is staged again
         }
         ax = group_sum(ax, lpi);
