@@ -714,6 +714,46 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, i
     cell_geom[slot] = make_float2((float)(0.5 * w), lf_hmax[a]);
 }
 
+// Bounding box of each leaf's particles at their current offsets (one
+// wavefront per schedule slot), for the density loop's culling of staged
+// candidates: centre and the leaf's largest search radius, then the half
+// widths, rounded up by a relative 1e-6 of the coordinates so that the FP32
+// centre and widths still contain every particle.
+__global__ void __launch_bounds__(256) k_cell_pbox(int64_t nl, const int4* __restrict__ cells,
+                                                   const float4* __restrict__ xrel,
+                                                   const float2* __restrict__ cell_geom, float4* __restrict__ pbox)
+{
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (slot >= nl) return;  // whole wavefront
+    const int lane = threadIdx.x & 63;
+    const int4 ci = cells[slot];
+    const float BIG = 3.0e38f;
+    float lx = BIG, ly = BIG, lz = BIG, hx = -BIG, hy = -BIG, hz = -BIG;
+    for (int k = lane; k < ci.y; k += 64) {
+        const float4 x = xrel[ci.x + k];
+        lx = fminf(lx, x.x);
+        ly = fminf(ly, x.y);
+        lz = fminf(lz, x.z);
+        hx = fmaxf(hx, x.x);
+        hy = fmaxf(hy, x.y);
+        hz = fmaxf(hz, x.z);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, o, 64));
+        ly = fminf(ly, __shfl_xor(ly, o, 64));
+        lz = fminf(lz, __shfl_xor(lz, o, 64));
+        hx = fmaxf(hx, __shfl_xor(hx, o, 64));
+        hy = fmaxf(hy, __shfl_xor(hy, o, 64));
+        hz = fmaxf(hz, __shfl_xor(hz, o, 64));
+    }
+    if (lane == 0) {
+        pbox[2 * slot] = make_float4(0.5f * (lx + hx), 0.5f * (ly + hy), 0.5f * (lz + hz), cell_geom[slot].y);
+        pbox[2 * slot + 1] = make_float4(0.5f * (hx - lx) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lx), fabsf(hx)),
+                                         0.5f * (hy - ly) * 1.000001f + 1.0e-6f * fmaxf(fabsf(ly), fabsf(hy)),
+                                         0.5f * (hz - lz) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lz), fabsf(hz)), 0.0f);
+    }
+}
+
 // Sorted FP64 positions and FP32 offsets from the centre of each particle's leaf.
 __global__ void k_sorted_fill(int64_t n, const uint32_t* __restrict__ perm, const double* __restrict__ pos_w,
                               const int* __restrict__ leaf_of, const int* __restrict__ lf_node,
@@ -946,6 +986,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
         SPH_HIP(hipMemcpyAsync(mk, d_M, sizeof(mk), hipMemcpyDeviceToHost, s));
         SPH_HIP(hipStreamSynchronize(s));
         const int64_t M = mk[0], K = mk[1];
+        if (level == 0) c->cells_refined = K < M;
         // every particle not yet in a leaf heads or joins a node of this level,
         // so the bound (its parents' children) holds them; a larger count is a bug
         SPH_REQUIRE(M <= bound && K <= M, SPH_E_HIP, "cell tree level outside its bound");
@@ -1060,6 +1101,7 @@ static void build_from_wrapped(sph_ctx* c, hipStream_t s)
     k_sorted_fill<<<blocks_for(n, BS), BS, 0, s>>>(n, perm, static_cast<double*>(c->pos_w.p), leaf_of, lf_node,
                                                    nd_coord, nd_level, nd_box, box_G, box_len, pos_s, xrel);
     SPH_HIP(hipGetLastError());
+    cell_boxes(c, s);
     // no drift since this build; the smallest search radius bounds how far
     // the particles may drift before the cells are rebuilt
     unsigned* drift = ensure<unsigned>(c, c->drift, 4);
@@ -1141,6 +1183,19 @@ void refresh_offsets(sph_ctx* c, hipStream_t s)
         static_cast<int*>(c->lf_node.p), static_cast<int*>(c->nd_coord.p), static_cast<int*>(c->nd_level.p),
         static_cast<int*>(c->nd_box.p), static_cast<int*>(c->box_G.p), static_cast<double*>(c->box_len.p),
         static_cast<double*>(c->pos_s.p), static_cast<float4*>(c->xrel.p));
+    SPH_HIP(hipGetLastError());
+    cell_boxes(c, s);
+}
+
+// The particle boxes of every leaf (k_cell_pbox) from the current offsets.
+void cell_boxes(sph_ctx* c, hipStream_t s)
+{
+    const int64_t nl = c->n_leaves;
+    float4* pbox = ensure<float4>(c, c->cell_pbox, 2 * nl);
+    if (nl == 0) return;
+    k_cell_pbox<<<blocks_for(64 * nl, 256), 256, 0, s>>>(nl, static_cast<int4*>(c->cells.p),
+                                                        static_cast<float4*>(c->xrel.p),
+                                                        static_cast<float2*>(c->cell_geom.p), pbox);
     SPH_HIP(hipGetLastError());
 }
 

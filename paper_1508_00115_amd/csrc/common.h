@@ -161,6 +161,7 @@ struct sph_ctx {
     // smallest Hs. Cleared by every build.
     sph::Buf drift;
     float h_min = 0.0f;           // smallest Hs of the last build (host copy; see finish_build_read)
+    bool cells_refined = false;   // a top cell was split in the last build (leaves of several sizes)
     bool drift_pending = false;   // a drift since the last check of delta
     sph::Buf leaf_of;        // int, sorted particle -> leaf
     sph::Buf unassigned;     // int flags per particle during the level loop
@@ -189,6 +190,8 @@ struct sph_ctx {
     sph::Buf cells;          // int4 per slot: first particle, count, first neighbour entry, neighbour entries
     sph::Buf cell_aux;       // int2 per slot: leaf index, box
     sph::Buf cell_geom;      // float2 per slot: half width of the leaf, largest search radius in it
+    sph::Buf cell_pbox;      // float4 x 2 per slot: box of the leaf's particles at their current offsets
+                             // (centre, largest search radius; half widths, 0)
     sph::Buf cells_d;        // int4 per slot as `cells`, with the density's record count (a prefix)
     sph::Buf sched_key, sched_key_alt, sched_val, sched_val_alt;  // cost sort
     sph::Buf scan_tmp;       // scan workspace
@@ -467,6 +470,8 @@ double timestep_noalloc(sph_ctx* c, double courant, hipStream_t s);
 void scratch_setup(int device);
 // Offsets from the leaf centres from the current positions (build.hip).
 void refresh_offsets(sph_ctx* c, hipStream_t s);
+// Bounding boxes of the leaves' particles at their current offsets (cell_pbox).
+void cell_boxes(sph_ctx* c, hipStream_t s);
 // Before a density pass after a drift: reject non-finite positions, and
 // rebuild the cells (around h_caller, or the last guesses when null) once the
 // drift bound eats into the margin of the search radii.

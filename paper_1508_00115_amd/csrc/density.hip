@@ -64,7 +64,8 @@ struct DensArgs {
     const int4* cells;       // per schedule slot: first particle, count, first neighbour entry, and
                              // the entries within the leaf's largest search radius (a prefix of its
                              // list: the density needs no others)
-    const float2* cell_geom; // per schedule slot: half width of the leaf, largest search radius in it
+    const float4* cell_pbox; // per schedule slot, 2: bounding box of the leaf's particles (centre, largest
+                             // search radius; half widths, 0), at their current offsets
     const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     int64_t* ctr;
@@ -395,12 +396,13 @@ __device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float
 // has no next cell: at most 128 VGPRs, four wavefronts per SIMD.
 // DETAIL: also count the candidates listed (sph_params.timing = 2); a
 // separate instance, since the counter costs the hot loop registers.
-template <int TCAP, bool PERSIST, bool DETAIL>
+template <int TCAP, bool PERSIST, bool DETAIL, bool CULL>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
     __shared__ float4 tile[TCAP];
     __shared__ float lists[(DSLOTS + 1) * 64];
     __shared__ uint8_t marks[DCH];  // record starts of the chunk being fetched
+    __shared__ float4 box_lds[2];   // the cell's particle box (cull_pbox), culling cells only
     const int lane = threadIdx.x & 63;
     float4* sj = tile;
     float* lst = lists + lane;
@@ -462,10 +464,19 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         bool pre_issued = false;
         float m0 = 0.0f;      // the mass of the cell's first particle
         unsigned kept_pack = 0;  // (resident) candidates kept of each staged chunk, 8 bits each
-        const bool cull = np_all > 27;  // neighbour cells of other sizes than the cell's own
-        float2 geom = make_float2(0.f, 0.f);  // half width of the cell, its largest search radius
-        if (cull) geom = A.cell_geom[slot];
-        const float hw = cull_half_width(geom.x + 0.5f * two_delta);
+        // neighbour cells of other sizes than the cell's own (only where a
+        // top cell was split: CULL)
+        const bool cull = CULL && np_all > 27;
+        // the bounding box of the cell's particles at their current offsets
+        // and the cell's largest search radius; the box waits in LDS for the
+        // commits (held in registers across the passes it would cost the hot
+        // loops)
+        float geom_y = 0.0f;
+        if (cull) {
+            const float4 b = A.cell_pbox[2 * slot + (lane & 1)];
+            if (lane < 2) box_lds[lane] = b;
+            geom_y = uniform_f(__shfl(b.w, 0, 64));
+        }
 
         for (int ib = 0; ib < ni; ib += per_pass) {
             const int gi = ib + g;
@@ -502,13 +513,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
             {
                 const float H2 = s.done ? -1.0f : s.Hi * s.Hi;
                 const bool stream = !(resident && loaded);
-                // staging keeps only the candidates within reach of the cell's
-                // box (widened by the drift): the largest search radius of this
-                // pass, or of the whole cell when the tile stays for later
-                // passes. A cell of a uniform grid (27 neighbour cells, all as
-                // wide as the reach) loses only the block's corners, which
-                // costs about what it saves, so it keeps every candidate.
-                const float reach2 = !cull ? 0.0f : cull_reach2(resident ? geom.y : wave_max(s.done ? 0.0f : s.Hi));
+                // staging keeps only the candidates within reach of the box of
+                // the cell's particles (cell_pbox, at their current offsets):
+                // the largest search radius of this pass, or of the whole cell
+                // when the tile stays for later passes. A cell of a uniform
+                // grid (27 neighbour cells, all as wide as the reach) loses
+                // only the block's corners, which costs about what it saves,
+                // so it keeps every candidate.
+                const float reach2 = !cull ? 0.0f : cull_reach2(resident ? geom_y : wave_max(s.done ? 0.0f : s.Hi));
                 int kept_tot = 0;
                 ChunkRegs<1, DCH> R;
                 if (stream) {
@@ -533,7 +545,15 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                         // store this chunk's candidates within reach (padded to
                         // DCH), put the next chunk in flight
                         if (cull) {
-                            slen = commit_chunk_culled_padded(sj + (resident ? c0 : 0), R, hw, reach2);
+                            const float4 b0 = box_lds[0], b1 = box_lds[1];
+                            CullBox cbox;
+                            cbox.cx = b0.x;
+                            cbox.cy = b0.y;
+                            cbox.cz = b0.z;
+                            cbox.hx = b1.x;
+                            cbox.hy = b1.y;
+                            cbox.hz = b1.z;
+                            slen = commit_chunk_culled_padded(sj + (resident ? c0 : 0), R, cbox, reach2);
                         } else {
                             commit_chunk_padded(sj + (resident ? c0 : 0), R);
                             slen = len;
@@ -936,7 +956,7 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.nw_out = nw;
     A.status = status;
     A.cells = static_cast<int4*>(c->cells_d.p);
-    A.cell_geom = static_cast<float2*>(c->cell_geom.p);
+    A.cell_pbox = static_cast<float4*>(c->cell_pbox.p);
     A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
     A.ctr = ctr;
@@ -962,19 +982,30 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     const int scan_grid = (int)std::max<int64_t>(std::min<int64_t>(c->n_leaves, (int64_t)c->n_cu * 8), 1);
     if (events) ev_record(c, EV_DENS_K0, s);
     const bool pers = A.W.persistent != 0;
-    auto launch = [&](auto tcap) {
+    auto launch = [&](auto tcap, auto cullc) {
         constexpr int T = decltype(tcap)::value;
+        constexpr bool C = decltype(cullc)::value;
         if (A.detail)
-            pers ? k_density<T, true, true><<<grid, BS, 0, s>>>(A) : k_density<T, false, true><<<grid, BS, 0, s>>>(A);
+            pers ? k_density<T, true, true, C><<<grid, BS, 0, s>>>(A)
+                 : k_density<T, false, true, C><<<grid, BS, 0, s>>>(A);
         else
-            pers ? k_density<T, true, false><<<grid, BS, 0, s>>>(A) : k_density<T, false, false><<<grid, BS, 0, s>>>(A);
+            pers ? k_density<T, true, false, C><<<grid, BS, 0, s>>>(A)
+                 : k_density<T, false, false, C><<<grid, BS, 0, s>>>(A);
     };
-    if (c->prm.tile_cap == 512)
-        launch(std::integral_constant<int, 512>{});
-    else if (c->prm.tile_cap == 256)
-        launch(std::integral_constant<int, 256>{});
+    auto launch_t = [&](auto cullc) {
+        if (c->prm.tile_cap == 512)
+            launch(std::integral_constant<int, 512>{}, cullc);
+        else if (c->prm.tile_cap == 256)
+            launch(std::integral_constant<int, 256>{}, cullc);
+        else
+            launch(std::integral_constant<int, 128>{}, cullc);
+    };
+    // a layout of top cells only (no split) has no cell with more than 27
+    // neighbour cells, so its kernels carry no culling code
+    if (c->cells_refined)
+        launch_t(std::true_type{});
     else
-        launch(std::integral_constant<int, 128>{});
+        launch_t(std::false_type{});
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_DENS_KM, s);
     k_density_scan<<<scan_grid, BS, 0, s>>>(A);

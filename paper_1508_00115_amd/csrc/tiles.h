@@ -409,11 +409,11 @@ __device__ __forceinline__ void commit_chunk_padded(float4* sj, const ChunkRegs<
 // within reach of a cell a rounded box about a quarter smaller, and that of
 // a pass's particles smaller still. The force tests its candidates against
 // the box of each pass; the density only on non-uniform cells, against the
-// cell's box (on a uniform grid the compaction costs more than the tests it
-// saves); the re-scanning kernel against the box of each group of particles.
-// An axis-aligned box in the cell frame: the cell's own box (centre 0, half
-// width hw in every axis, widened by the drift bound) or the bounding box of
-// the particles of one pass.
+// box of the cell's particles (on a uniform grid the compaction costs more
+// than the tests it saves); the re-scanning kernel against the box of each
+// group of particles. An axis-aligned box in the cell frame: the cell's own
+// box (centre 0, half width hw in every axis, widened by the drift bound) or
+// the bounding box of a set of particles.
 struct CullBox {
     float cx, cy, cz, hx, hy, hz;
 };
@@ -530,7 +530,7 @@ __device__ __forceinline__ int commit_chunk_culled(float4* sj, const ChunkRegs<N
 // test. Returns how many were kept. A candidate farther from the box than
 // every search radius of the cell pairs with none of its particles.
 template <int CAP>
-__device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const ChunkRegs<1, CAP>& R, float hw,
+__device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const ChunkRegs<1, CAP>& R, const CullBox& box,
                                                           float reach2)
 {
     const int lane = threadIdx.x & 63;
@@ -543,7 +543,7 @@ __device__ __forceinline__ int commit_chunk_culled_padded(float4* sj, const Chun
         a.x += R.s[r][0];
         a.y += R.s[r][1];
         a.z += R.s[r][2];
-        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, hw) < reach2;
+        const bool keep = t < R.len && box_dist2(a.x, a.y, a.z, box) < reach2;
         const uint64_t m = __ballot(keep);
         if (keep) sj[n + lanes_below(m)] = a;
         n += __popcll(m);
