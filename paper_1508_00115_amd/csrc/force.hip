@@ -68,7 +68,8 @@ struct ForceArgs {
     float4* jf_w;             // the same array, written by the divergence pass (B in place of 1/h)
     const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* cell_aux;  // per schedule slot: leaf, box
-    const float2* cell_geom;  // per schedule slot: half width of the leaf, largest search radius in it
+    const float4* cell_pbox;  // per schedule slot, 2: box of the leaf's particles at their current offsets
+                              // (centre, largest search radius; half widths, 0)
     const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     const uint32_t* perm;
@@ -159,7 +160,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
     int wstate = 0, a_cur = 0, a_end = 0;
     int64_t cand_acc = 0, inter_acc = 0;
     const float K8PI = 8.0f / SPH_PI_F;
-    const float delta = A.drift[0];  // particles may sit this far outside their cell boxes
 
     for (;;) {
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
@@ -177,8 +177,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         const int sub = lane & (lpi - 1);
         bool loaded = false;
         int kept_single = 0;  // (single tile) candidates kept by the cell-box test
-        const float2 geom = A.cell_geom[slot];
-        const float hw = cull_half_width(geom.x + delta), reach2_cell = cull_reach2(geom.y);
         // this cell's share of the box sums: lane 0's totals, kept in scalar
         // registers across the passes (every lane is active where they change)
         double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};
@@ -194,12 +192,25 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float h2_i = i0v.w;
             const float hinv_i = MODE == FM_BALSARA ? __builtin_amdgcn_rsqf(h2_i) : i2v.w;
             // candidates staged for this pass alone need only reach its
-            // particles' largest h (or their own); a tile kept for every pass
-            // reaches the cell's largest search radius
-            const float reach2 =
-                single_tile ? reach2_cell : uniform_f(cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f))));
-            // ... from the box around this pass's particles, or the cell's box
-            const CullBox box = single_tile ? cell_box(hw) : pass_box(i0v.x, i0v.y, i0v.z, valid);
+            // particles' largest h (or their own) from the box around them; a
+            // tile kept for every pass reaches the cell's largest search
+            // radius from the box around all the cell's particles (at their
+            // current offsets)
+            float reach2;
+            CullBox box;
+            if (single_tile) {
+                const float4 bx0 = A.cell_pbox[2 * slot], bx1 = A.cell_pbox[2 * slot + 1];
+                reach2 = uniform_f(cull_reach2(bx0.w));
+                box.cx = uniform_f(bx0.x);
+                box.cy = uniform_f(bx0.y);
+                box.cz = uniform_f(bx0.z);
+                box.hx = uniform_f(bx1.x);
+                box.hy = uniform_f(bx1.y);
+                box.hz = uniform_f(bx1.z);
+            } else {
+                reach2 = uniform_f(cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f))));
+                box = pass_box(i0v.x, i0v.y, i0v.z, valid);
+            }
             const float hinv2_i = hinv_i * hinv_i;
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
@@ -429,7 +440,7 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.jf = jf;
     A.jf_w = jf;
     A.cells = static_cast<int4*>(c->cells.p);
-    A.cell_geom = static_cast<float2*>(c->cell_geom.p);
+    A.cell_pbox = static_cast<float4*>(c->cell_pbox.p);
     A.cell_aux = static_cast<int2*>(c->cell_aux.p);
     A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
