@@ -98,10 +98,12 @@ __device__ __forceinline__ int commit_culled(float4* sj, const ChunkRegs<1, GCH>
 // below len (rounded up to a multiple of 4 LPI: the padding adds nothing),
 // four tile reads in flight at once. The pull on i is -m_j S (r^2 + eps^2)^(-3/2)
 // r_ij per pair inside r_cut; a pair outside (or at r = 0) is selected away,
-// so the far padding's overflows never reach the sums.
+// so the far padding's overflows never reach the sums. rc2 is the lane's:
+// below zero on a lane without a particle. The pairs inside are counted for
+// the whole wavefront (a ballot of the same test, in scalar registers).
 template <int LPI>
 __device__ __forceinline__ void pair_chunk(const float4* tc, int len, const float4& xi, float rc2, float inv_rc2,
-                                           float eps2, float& ax, float& ay, float& az, int& cnt)
+                                           float eps2, float& ax, float& ay, float& az, int& wcnt)
 {
     const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
     for (int k0 = 0; k0 < len_pad; k0 += 4 * LPI, tc += 4 * LPI) {
@@ -119,7 +121,7 @@ __device__ __forceinline__ void pair_chunk(const float4* tc, int len, const floa
             ax = fmaf(-f, dx, ax);
             ay = fmaf(-f, dy, ay);
             az = fmaf(-f, dz, az);
-            cnt += in ? 1 : 0;
+            wcnt += __popcll(__ballot(in));
         }
     }
 }
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
     const int per_pass = 64 / lpi;
     const int g = lane / lpi, sub = lane & (lpi - 1);
     const float reach2 = cull_reach2(uniform_f(sqrtf(A.rc2)));
-    int pairs = 0;
+    int pairs = 0;  // wave-uniform
     int64_t tested = 0;
     for (int ib = 0; ib < ni; ib += per_pass) {
         const int gi = ib + g;
@@ -152,8 +154,8 @@ __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
         // only the candidates within r_cut of the pass's bounding box can pair
         const CullBox box = pass_box(xi.x, xi.y, xi.z, valid);
         const int n_valid = min(per_pass, ni - ib);
+        const float rc2 = valid ? A.rc2 : -1.0f;
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
-        int cnt = 0;
         ChunkRegs<1, GCH> R;
         cursor_seek(cu, A.p_rec, A.p_shift, 0);
         fetch_chunk(R, A.jg, cu.nb, 0, cursor_chunk(cu, 0, GCH), marks);
@@ -170,31 +172,29 @@ __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
             tested += (int64_t)n_valid * kept;
             const float4* tc = tile + sub;
             if (lpi == 1)
-                pair_chunk<1>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+                pair_chunk<1>(tc, kept, xi, rc2, A.inv_rc2, A.eps2, ax, ay, az, pairs);
             else if (lpi == 2)
-                pair_chunk<2>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+                pair_chunk<2>(tc, kept, xi, rc2, A.inv_rc2, A.eps2, ax, ay, az, pairs);
             else if (lpi == 4)
-                pair_chunk<4>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+                pair_chunk<4>(tc, kept, xi, rc2, A.inv_rc2, A.eps2, ax, ay, az, pairs);
             else if (lpi == 8)
-                pair_chunk<8>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+                pair_chunk<8>(tc, kept, xi, rc2, A.inv_rc2, A.eps2, ax, ay, az, pairs);
             else
-                pair_chunk<16>(tc, kept, xi, A.rc2, A.inv_rc2, A.eps2, ax, ay, az, cnt);
+                pair_chunk<16>(tc, kept, xi, rc2, A.inv_rc2, A.eps2, ax, ay, az, pairs);
             wave_sync_lds();  // every lane is done with the tile before it is staged again
         }
         ax = group_sum(ax, lpi);
         ay = group_sum(ay, lpi);
         az = group_sum(az, lpi);
-        cnt = group_sum_i(cnt, lpi);
         if (valid && sub == 0) {
             const uint32_t o = A.perm[i];
             A.acc[3 * (int64_t)o + 0] = A.G * ax;
             A.acc[3 * (int64_t)o + 1] = A.G * ay;
             A.acc[3 * (int64_t)o + 2] = A.G * az;
-            pairs += cnt;
         }
     }
     // the gravity call has the counters to itself
-    ctr_wave_add(A.ctr, CT_FORCE_INTER, pairs);
+    ctr_add_uniform(A.ctr, CT_FORCE_INTER, pairs);
     ctr_add_uniform(A.ctr, CT_FORCE_CAND, tested);
 }
 
