@@ -137,6 +137,27 @@ def test_gravity_matches_oracle(gpu_lib, case):
     assert abs(npair - tot) <= band, (npair, tot, band)
 
 
+def test_gravity_empty_and_lonely_boxes(gpu_lib):
+    """A batch with an empty box and a box of side 2 holding one particle:
+    the lonely particle has no pair and gets exactly 0; the other boxes
+    match the oracle."""
+    a = workloads.lattice_box(12, [1508, 886], jitter=0.25)
+    b = workloads.lattice_box(9, [1508, 887], jitter=0.25)
+    n1, n2 = len(a["pos"]), len(b["pos"])
+    d = {k: np.concatenate([a[k], np.array([[1.3, 0.2, 1.7]]) if k == "pos" else a[k][:1], b[k]])
+         for k in ("pos", "vel", "mass", "u", "h0")}
+    d["box_first"] = np.array([0, n1, n1, n1 + 1, n1 + 1 + n2], dtype=np.int64)
+    d["box_len"] = np.array([1.0, 1.0, 2.0, 1.0])
+    mass = _masses(len(d["pos"]), 7)
+    rc = 0.95 * float(d["h0"].min())
+    acc, npair = _gpu(gpu_lib, d, mass, 1.0, 1e-3, rc)
+    assert np.all(acc[n1] == 0.0)
+    tot = _check_box(acc[:n1], d["pos"][:n1], mass[:n1], 1.0, 1e-3, rc, 1.0, "box 0")
+    tot += _check_box(acc[n1 + 1:], d["pos"][n1 + 1:], mass[n1 + 1:], 1.0, 1e-3, rc, 1.0, "box 3")
+    band = _band(d["pos"][:n1], rc) + _band(d["pos"][n1 + 1:], rc)
+    assert abs(npair - tot) <= band
+
+
 def test_gravity_unsoftened_and_at_the_search_radius(gpu_lib):
     """eps = 0 and r_cut just inside the smallest search radius (every pair
     the cells' lists can hold)."""
