@@ -393,7 +393,7 @@ __global__ void k_box_leaf(int n_boxes, int64_t n, int64_t nl, const int64_t* __
 
 // Particles of each leaf of 2 to 64 particles in decreasing order of search
 // radius (ties by input index), one wavefront per leaf, a bitonic network
-// over the 64 lanes. The hot kernels take a leaf's particles a pass at a
+// over the 64 lanes; a leaf whose radii are all equal is left as it is. The hot kernels take a leaf's particles a pass at a
 // time and cull the staged candidates to the pass's largest radius, which
 // this order makes as small as it can be for every pass but the first.
 // Only the order inside each leaf changes: leaves, nodes and lists stay.
@@ -409,6 +409,14 @@ __global__ void __launch_bounds__(256) k_leaf_sort_h(int64_t nl, const int* __re
     const int p0 = lf_start[leaf];
     // key: H descending, then index ascending; empty lanes last
     float k = lane < n ? Hs[p0 + lane] : -INFINITY;
+    // a leaf whose radii are all equal keeps its order (every pass has the
+    // same reach), without the network
+    float lo = lane < n ? k : INFINITY, hi = k;
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lo == hi) return;  // whole wavefront
     uint32_t v = lane < n ? perm[p0 + lane] : 0xffffffffu;
     for (int size = 2; size <= 64; size <<= 1) {
         for (int stride = size >> 1; stride >= 1; stride >>= 1) {
