@@ -87,14 +87,24 @@ def _boxes8():
     return d
 
 
-@pytest.mark.parametrize("case", ["lattice", "batched8"])
+def _clustered_vel():
+    # Plummer spheres in a uniform background (cells of several sizes, so the
+    # density culls against the particle boxes refreshed after each drift)
+    d = workloads.clustered(n_uniform=6000, n_spheres=4, per_sphere=1500, a_range=(0.02, 0.08))
+    rng = np.random.default_rng([1508, 961])
+    d["vel"] = rng.normal(0.0, 0.3, size=d["pos"].shape).astype(np.float32)
+    return d
+
+
+@pytest.mark.parametrize("case", ["lattice", "batched8", "clustered"])
 def test_drift_keeps_the_cells(gpu_lib, case):
     """After drifts the pass runs on the kept cells (search radius reduced by
     twice the drift bound) and, once the bound eats the margin, on rebuilt
-    ones; both against the oracle at the drifted positions (one box, and
-    eight boxes of different sides and counts, each wrapped on its own)."""
+    ones; both against the oracle at the drifted positions (one box, eight
+    boxes of different sides and counts, each wrapped on its own, and a
+    clustered set whose cells have several sizes)."""
     import torch
-    d = _case() if case == "lattice" else _boxes8()
+    d = {"lattice": _case, "batched8": _boxes8, "clustered": _clustered_vel}[case]()
     t = _tensors(d)
     ctx = gpu_lib.Context(0, signal_velocity=1)
     try:
