@@ -722,8 +722,8 @@ __global__ void k_sched_fill(int64_t nl, const uint32_t* __restrict__ by_cost, i
     cell_geom[slot] = make_float2((float)(0.5 * w), lf_hmax[a]);
 }
 
-// Bounding box of each leaf's particles at their current offsets (one
-// wavefront per schedule slot), for the density loop's culling of staged
+// Bounding box of each leaf's particles at their current offsets (sixteen
+// lanes per schedule slot), for the density loop's culling of staged
 // candidates: centre and the leaf's largest search radius, then the half
 // widths, rounded up by a relative 1e-6 of the coordinates so that the FP32
 // centre and widths still contain every particle.
@@ -731,13 +731,15 @@ __global__ void __launch_bounds__(256) k_cell_pbox(int64_t nl, const int4* __res
                                                    const float4* __restrict__ xrel,
                                                    const float2* __restrict__ cell_geom, float4* __restrict__ pbox)
 {
-    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (slot >= nl) return;  // whole wavefront
-    const int lane = threadIdx.x & 63;
-    const int4 ci = cells[slot];
+    // sixteen lanes per leaf (a leaf holds about that many particles); every
+    // lane takes part in the shuffles, a group past the last leaf with no data
+    const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    const bool live = slot < nl;
+    const int4 ci = live ? cells[slot] : make_int4(0, 0, 0, 0);
     const float BIG = 3.0e38f;
     float lx = BIG, ly = BIG, lz = BIG, hx = -BIG, hy = -BIG, hz = -BIG;
-    for (int k = lane; k < ci.y; k += 64) {
+    for (int k = sub; k < ci.y; k += 16) {
         const float4 x = xrel[ci.x + k];
         lx = fminf(lx, x.x);
         ly = fminf(ly, x.y);
@@ -746,7 +748,7 @@ __global__ void __launch_bounds__(256) k_cell_pbox(int64_t nl, const int4* __res
         hy = fmaxf(hy, x.y);
         hz = fmaxf(hz, x.z);
     }
-    for (int o = 32; o >= 1; o >>= 1) {
+    for (int o = 8; o >= 1; o >>= 1) {  // within the group of 16
         lx = fminf(lx, __shfl_xor(lx, o, 64));
         ly = fminf(ly, __shfl_xor(ly, o, 64));
         lz = fminf(lz, __shfl_xor(lz, o, 64));
@@ -754,7 +756,7 @@ __global__ void __launch_bounds__(256) k_cell_pbox(int64_t nl, const int4* __res
         hy = fmaxf(hy, __shfl_xor(hy, o, 64));
         hz = fmaxf(hz, __shfl_xor(hz, o, 64));
     }
-    if (lane == 0) {
+    if (live && sub == 0) {
         pbox[2 * slot] = make_float4(0.5f * (lx + hx), 0.5f * (ly + hy), 0.5f * (lz + hz), cell_geom[slot].y);
         pbox[2 * slot + 1] = make_float4(0.5f * (hx - lx) * 1.000001f + 1.0e-6f * fmaxf(fabsf(lx), fabsf(hx)),
                                          0.5f * (hy - ly) * 1.000001f + 1.0e-6f * fmaxf(fabsf(ly), fabsf(hy)),
@@ -1201,7 +1203,7 @@ void cell_boxes(sph_ctx* c, hipStream_t s)
     const int64_t nl = c->n_leaves;
     float4* pbox = ensure<float4>(c, c->cell_pbox, 2 * nl);
     if (nl == 0) return;
-    k_cell_pbox<<<blocks_for(64 * nl, 256), 256, 0, s>>>(nl, static_cast<int4*>(c->cells.p),
+    k_cell_pbox<<<blocks_for(16 * nl, 256), 256, 0, s>>>(nl, static_cast<int4*>(c->cells.p),
                                                         static_cast<float4*>(c->xrel.p),
                                                         static_cast<float2*>(c->cell_geom.p), pbox);
     SPH_HIP(hipGetLastError());
