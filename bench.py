@@ -116,7 +116,31 @@ def cpu_baseline(d: dict, min_seconds: float, one_thread_seconds: float) -> dict
     out["value_1thread"] = i1 / t1
     out["sample_1thread"] = "%d of the %d boxes (seeded order), %.1f s on 1 thread" % (boxes, nb, t1)
     oracle.run(workloads.box_slice(d, int(order[0])), threads=cores)  # leave the library at all cores
+    out["gravity_p2p"] = cpu_gravity(d, order)
     return out
+
+
+def cpu_gravity(d: dict, order, min_seconds: float = 3.0) -> dict:
+    """The FP64 gravity oracle (scipy's tree search and numpy, one process)
+    over boxes in the seeded order, with the cutoff, softening and masses
+    the GPU entry uses, until min_seconds have passed."""
+    import time as _time
+
+    from oracle import gravity as og
+    import workloads
+    rc = 0.95 * float(d["h0"].min())
+    t, pairs, boxes = 0.0, 0, 0
+    for b in order:
+        e = workloads.box_slice(d, int(b))
+        t0 = _time.perf_counter()
+        r = og.p2p(e["pos"], e["mass"].astype(np.float64), 1.0, 1e-3, rc, float(e["box_len"][0]))
+        t += _time.perf_counter() - t0
+        pairs += int(r["npair"])
+        boxes += 1
+        if t >= min_seconds:
+            break
+    return {"value": pairs / t, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of the %d boxes (seeded order), %.1f s in one process" % (boxes, len(d["box_len"]), t)}
 
 
 KERNEL_SOURCES = {
