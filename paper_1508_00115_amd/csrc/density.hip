@@ -396,6 +396,10 @@ __device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float
 // has no next cell: at most 128 VGPRs, four wavefronts per SIMD.
 // DETAIL: also count the candidates listed (sph_params.timing = 2); a
 // separate instance, since the counter costs the hot loop registers.
+// CULL: the culling of staged candidates and the per-cell choice of lanes
+// per particle (layouts that split a top cell, or whose lists need more
+// than four lanes); without it, four lanes per particle and no culling,
+// which lets the compiler specialise every loop on the lane count.
 template <int TCAP, bool PERSIST, bool DETAIL, bool CULL>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
@@ -454,7 +458,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         // resident: one block of neighbour records and at most TCAP candidates,
         // staged once at fixed tile slots of DCH
         const bool resident = np_all <= 64 && nj <= TCAP;
-        const int lpi = choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH);
+        // a layout of top cells only runs with four lanes per particle (its
+        // cells hold similar numbers of particles, for which the choice is
+        // four, and the fixed count lets the compiler specialise every loop)
+        const int lpi = CULL ? choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH) : 4;
         const int lg = __builtin_ctz(lpi);
         const int per_pass = 64 >> lg;
         const int g = lane >> lg;
@@ -1001,8 +1008,9 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
             launch(std::integral_constant<int, 128>{}, cullc);
     };
     // a layout of top cells only (no split) has no cell with more than 27
-    // neighbour cells, so its kernels carry no culling code
-    if (c->cells_refined)
+    // neighbour cells, so its kernels carry no culling code, and take four
+    // lanes per particle where four hold the expected lists
+    if (c->cells_refined || A.lpi_min > 4)
         launch_t(std::true_type{});
     else
         launch_t(std::false_type{});
