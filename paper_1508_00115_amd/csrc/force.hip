@@ -83,7 +83,6 @@ struct ForceArgs {
     int64_t* ctr;
     WorkSched W;
     float alpha;
-    float list_work;  // pair-term work per particle, in candidate tests (choose_lpi)
 };
 
 // Phase A of one chunk for the lanes of one particle: the lane with index sub
@@ -170,9 +169,13 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= FCAP;
-        const int lpi = choose_lpi(ni, nj, 4, A.list_work, single_tile, FCAP);
-        const int lg = __builtin_ctz(lpi);
-        const int per_pass = 64 >> lg;
+        // four lanes per particle on every cell: a lane's byte list (one
+        // chunk's hits) cannot overflow, and the fixed count lets the
+        // compiler specialise every loop (measured faster on every set than
+        // a per-cell choice, even where leaves hold few particles)
+        constexpr int lpi = 4;
+        constexpr int lg = 2;
+        constexpr int per_pass = 64 >> lg;
         const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
         bool loaded = false;
@@ -241,15 +244,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 }
                 kept += slen;
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
-                int nl;
-                if (lpi == 2)
-                    nl = force_scan<2, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
-                else if (lpi == 4)
-                    nl = force_scan<4, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
-                else if (lpi == 8)
-                    nl = force_scan<8, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
-                else
-                    nl = force_scan<16, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
+                int nl = force_scan<lpi, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 if (!valid) nl = 0;
                 cnt += nl;
                 // phase B: the pair terms of the compacted neighbours only
@@ -456,7 +451,6 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.ctr = ctr;
     const int grid = make_sched(c, c->n_leaves, WAVES, 16, A.W);
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
-    A.list_work = (float)(4.0 * c->prm.n_ngb);  // ~n_ngb pairs per particle at ~4 tests' cost each
     if (events) ev_record(c, EV_FORCE_K0, s);
     const bool bal = c->prm.balsara != 0 && A.alpha > 0.0f;
     if (bal) {
