@@ -403,7 +403,7 @@ __device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float
 template <int TCAP, bool PERSIST, bool DETAIL, bool CULL>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
-    __shared__ float4 tile[TCAP];
+    __shared__ float4 tile[CULL ? TCAP : DCH];  // (no resident tiles without CULL)
     __shared__ float lists[(DSLOTS + 1) * 64];
     __shared__ uint8_t marks[DCH];  // record starts of the chunk being fetched
     __shared__ float4 box_lds[2];   // the cell's particle box (cull_pbox), culling cells only
@@ -457,7 +457,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         // resident: one block of neighbour records and at most TCAP candidates,
         // staged once at fixed tile slots of DCH
-        const bool resident = np_all <= 64 && nj <= TCAP;
+        // (the instance without culling always streams: with four lanes a
+        // cell of up to 16 particles takes one pass, where a resident tile
+        // saves nothing, and dropping that path frees registers)
+        const bool resident = CULL && np_all <= 64 && nj <= TCAP;
         // a layout of top cells only runs with four lanes per particle (its
         // cells hold similar numbers of particles, for which the choice is
         // four, and the fixed count lets the compiler specialise every loop)
