@@ -68,8 +68,6 @@ struct ForceArgs {
     float4* jf_w;             // the same array, written by the divergence pass (B in place of 1/h)
     const int4* cells;     // per schedule slot: first particle, count, first neighbour entry, entries
     const int2* cell_aux;  // per schedule slot: leaf, box
-    const float4* cell_pbox;  // per schedule slot, 2: box of the leaf's particles at their current offsets
-                              // (centre, largest search radius; half widths, 0)
     const int2* p_rec;       // per (cell, neighbour cell) record: first particle and count of the neighbour
     const float4* p_shift;
     const uint32_t* perm;
@@ -168,7 +166,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         NbrCursor cu;  // neighbour records 64 at a time
         cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
-        const bool single_tile = np_all <= 64 && nj <= FCAP;
         // four lanes per particle on every cell: a lane's byte list (one
         // chunk's hits) cannot overflow, and the fixed count lets the
         // compiler specialise every loop (measured faster on every set than
@@ -178,8 +175,6 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         constexpr int per_pass = 64 >> lg;
         const int g = lane >> lg;
         const int sub = lane & (lpi - 1);
-        bool loaded = false;
-        int kept_single = 0;  // (single tile) candidates kept by the cell-box test
         // this cell's share of the box sums: lane 0's totals, kept in scalar
         // registers across the passes (every lane is active where they change)
         double cm_cell[4] = {0.0, 0.0, 0.0, 0.0};
@@ -194,26 +189,13 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             const float bal_i = MODE == FM_BALSARA ? i2v.w : 1.0f;
             const float h2_i = i0v.w;
             const float hinv_i = MODE == FM_BALSARA ? __builtin_amdgcn_rsqf(h2_i) : i2v.w;
-            // candidates staged for this pass alone need only reach its
-            // particles' largest h (or their own) from the box around them; a
-            // tile kept for every pass reaches the cell's largest search
-            // radius from the box around all the cell's particles (at their
-            // current offsets)
-            float reach2;
-            CullBox box;
-            if (single_tile) {
-                const float4 bx0 = A.cell_pbox[2 * slot], bx1 = A.cell_pbox[2 * slot + 1];
-                reach2 = uniform_f(cull_reach2(bx0.w));
-                box.cx = uniform_f(bx0.x);
-                box.cy = uniform_f(bx0.y);
-                box.cz = uniform_f(bx0.z);
-                box.hx = uniform_f(bx1.x);
-                box.hy = uniform_f(bx1.y);
-                box.hz = uniform_f(bx1.z);
-            } else {
-                reach2 = uniform_f(cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f))));
-                box = pass_box(i0v.x, i0v.y, i0v.z, valid);
-            }
+            // every pass stages its own candidates (with four lanes a cell of
+            // up to 16 particles takes one pass, so a tile kept across passes
+            // would save little, and dropping it frees registers): those within
+            // the pass's largest h, or their own, of the box around its
+            // particles
+            const float reach2 = uniform_f(cull_reach2(sqrtf(wave_max(valid ? h2_i : 0.0f))));
+            const CullBox box = pass_box(i0v.x, i0v.y, i0v.z, valid);
             const float hinv2_i = hinv_i * hinv_i;
             const float Ki = K8PI * hinv2_i * hinv2_i;
             const float rho_i = i2v.x, phi_i = i2v.y, c_i = i2v.z;
@@ -222,26 +204,17 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
             float dvr = 0.f;   // (VSIG) sum_j m_j D_i (v_ij . rhat) = -rho_i div v_i
             int cnt = 0;
             ChunkRegs<NF, FCAP> R;
-            const bool stream_chunks = !(single_tile && loaded);
-            int len, kept = 0;  // candidates of this chunk; kept by the cell-box test (all chunks)
+            int len, kept = 0;  // candidates of this chunk; kept by the box test (all chunks)
             for (int c0 = 0; c0 < nj; c0 += len) {
-                int slen;
-                if (stream_chunks) {
-                    // stage this chunk's candidates within reach of the cell
-                    // (loaded and stored here rather than one chunk ahead: the
-                    // registers a fetch in flight would hold cost a wavefront
-                    // per SIMD, and the other wavefronts cover the loads)
-                    cursor_seek(cu, A.p_rec, A.p_shift, c0);
-                    fetch_chunk<NF, FCAP, 3>(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
-                    len = R.len;
-                    slen = commit_chunk_culled<NF, FCAP, !DC>(sj, R, box, reach2);
-                    if (single_tile) kept_single = slen;
-                    pad_tile(sj, slen, FCAP);
-                    loaded = true;
-                } else {
-                    len = nj;
-                    slen = kept_single;
-                }
+                // stage this chunk's candidates within reach of the pass
+                // (loaded and stored here rather than one chunk ahead: the
+                // registers a fetch in flight would hold cost a wavefront per
+                // SIMD, and the other wavefronts cover the loads)
+                cursor_seek(cu, A.p_rec, A.p_shift, c0);
+                fetch_chunk<NF, FCAP, 3>(R, A.jf, cu.nb, c0 - cu.off0, cursor_chunk(cu, c0, FCAP), marks);
+                len = R.len;
+                const int slen = commit_chunk_culled<NF, FCAP, !DC>(sj, R, box, reach2);
+                pad_tile(sj, slen, FCAP);
                 kept += slen;
                 // phase A: compact the candidates inside max(h_i, h_j) of this chunk
                 int nl = force_scan<lpi, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
@@ -292,10 +265,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                     az = fmaf(-mGr, dz, az);
                     du = fmaf(p1.w * fmaf(phi_i, Di, 0.5f * visc * Dbar), vr, du);
                 }
-                if (!single_tile) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                }
+                // every lane is done with the tile before the next chunk is staged
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
             ax = group_sum(ax, lpi);
             ay = group_sum(ay, lpi);
@@ -435,7 +407,6 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.jf = jf;
     A.jf_w = jf;
     A.cells = static_cast<int4*>(c->cells.p);
-    A.cell_pbox = static_cast<float4*>(c->cell_pbox.p);
     A.cell_aux = static_cast<int2*>(c->cell_aux.p);
     A.p_rec = static_cast<int2*>(c->p_rec.p);
     A.p_shift = static_cast<float4*>(c->p_shift.p);
