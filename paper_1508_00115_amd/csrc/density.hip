@@ -438,7 +438,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         const bool have_next = PERSIST && next_slot(nslot);
         CellRecs nxt;
         if (have_next) nxt.ci = A.cells[nslot];  // in flight while this cell is staged
-        const int i0 = cur.ci.x, ni = cur.ci.y, pb0 = cur.ci.z, np_all = cur.ci.w;
+        // (a leaf of a layout of top cells only has at most the 27 records of
+        // its block, within one block of 64: telling the compiler drops the
+        // multi-block paths)
+        const int i0 = cur.ci.x, ni = cur.ci.y, pb0 = cur.ci.z, np_all = CULL ? cur.ci.w : min(cur.ci.w, 64);
         // the cell's first 64 particles, one per lane (in flight with the first chunk)
         float4 px = make_float4(0.f, 0.f, 0.f, 0.f);
         float ph = 0.f, pH = 0.f;
