@@ -29,6 +29,8 @@
 // paper prints as its illustration (Eq. 2): (P_i / rho_i^2 + P_j / rho_j^2)
 // times the gradient of particle i's kernel, with no grad-h factor (the
 // prologue then stores Phi = P / rho^2).
+#include <type_traits>
+
 #include "common.h"
 #include "tiles.h"
 
@@ -143,7 +145,9 @@ __global__ void k_unsort_f32(int64_t n, const uint32_t* __restrict__ perm, const
 // divergence, rho_i div v_i = -sum_j m_j (v_i - v_j) . grad_i W(r_ij, h_i)
 // (the pairs inside h_i; grad_i W = D_i rhat), from which the next step's
 // smoothing length is predicted (continuity: dh/dt = h div v / 3).
-template <bool VSIG, int MODE>
+// ONEBLK: every cell has at most 64 neighbour records (a layout of top cells
+// only has 27), so the multi-block paths of the record cursor drop out.
+template <bool VSIG, int MODE, bool ONEBLK>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_force(ForceArgs A)
 {
     constexpr bool DC = MODE == FM_DIVCURL;
@@ -162,7 +166,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
         if (a_cur >= a_end && !next_items(A.W, A.ctr, WAVES, wstate, a_cur, a_end)) break;
         const int slot = a_cur++;
         const int4 ci = A.cells[slot];
-        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
+        const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ONEBLK ? min(ci.w, 64) : ci.w;
         NbrCursor cu;  // neighbour records 64 at a time
         cursor_init(cu, A.p_rec, A.p_shift, pb0, np_all);
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
@@ -424,23 +428,35 @@ void force_enqueue(sph_ctx* c, const float* vel, const float* u, float* acc, flo
     A.alpha = c->prm.alpha_visc > 0 ? (float)c->prm.alpha_visc : 0.0f;
     if (events) ev_record(c, EV_FORCE_K0, s);
     const bool bal = c->prm.balsara != 0 && A.alpha > 0.0f;
+    // a layout of top cells only (no split) has at most 27 records per cell
+    const bool one_block = !c->cells_refined;
+    auto go = [&](auto vs, auto md) {
+        constexpr bool V = decltype(vs)::value;
+        constexpr int M = decltype(md)::value;
+        if (one_block)
+            k_force<V, M, true><<<grid, BS, 0, s>>>(A);
+        else
+            k_force<V, M, false><<<grid, BS, 0, s>>>(A);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
     if (bal) {
-        k_force<false, FM_DIVCURL><<<grid, BS, 0, s>>>(A);
+        go(F{}, std::integral_constant<int, FM_DIVCURL>{});
         SPH_HIP(hipGetLastError());
         if (c->prm.schedule == 1) fill_u32(ctr + CT_QUEUE, 0u, 2 * 64, s);  // the force pass pops the queues again
         if (vsig)
-            k_force<true, FM_BALSARA><<<grid, BS, 0, s>>>(A);
+            go(T{}, std::integral_constant<int, FM_BALSARA>{});
         else
-            k_force<false, FM_BALSARA><<<grid, BS, 0, s>>>(A);
+            go(F{}, std::integral_constant<int, FM_BALSARA>{});
     } else if (eq2) {
         if (vsig)
-            k_force<true, FM_EQ2><<<grid, BS, 0, s>>>(A);
+            go(T{}, std::integral_constant<int, FM_EQ2>{});
         else
-            k_force<false, FM_EQ2><<<grid, BS, 0, s>>>(A);
+            go(F{}, std::integral_constant<int, FM_EQ2>{});
     } else if (vsig) {
-        k_force<true, FM_FORCE><<<grid, BS, 0, s>>>(A);
+        go(T{}, std::integral_constant<int, FM_FORCE>{});
     } else {
-        k_force<false, FM_FORCE><<<grid, BS, 0, s>>>(A);
+        go(F{}, std::integral_constant<int, FM_FORCE>{});
     }
     SPH_HIP(hipGetLastError());
     if (events) ev_record(c, EV_FORCE_K1, s);
