@@ -126,6 +126,9 @@ __device__ __forceinline__ void pair_chunk(const float4* tc, int len, const floa
     }
 }
 
+// ONEBLK: every cell has at most 64 records (a layout of top cells only has
+// 27), so the multi-block paths of the record cursor drop out.
+template <bool ONEBLK>
 __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
 {
     __shared__ float4 tile[GCH];
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(GBS) k_gravity(GravArgs A)
     const int slot = xcd_block_index();  // each XCD takes its own run of slots
     if (slot >= A.n_slots) return;       // whole wavefront
     const int4 ci = A.cells[slot];
-    const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np = ci.w;
+    const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np = ONEBLK ? min(ci.w, 64) : ci.w;
     NbrCursor cu;
     cursor_init(cu, A.p_rec, A.p_shift, pb0, np);
     const int nj = np <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np);
@@ -247,7 +250,11 @@ void gravity_p2p(sph_ctx* c, const float* mass, double G, double eps, double r_c
     A.rc2 = (float)(r_cut * r_cut);
     A.inv_rc2 = (float)(1.0 / (r_cut * r_cut));
     ev_record(c, EV_GRAV_K0, s);
-    k_gravity<<<(unsigned)std::max<int64_t>(c->n_leaves, 1), GBS, 0, s>>>(A);
+    const unsigned grid = (unsigned)std::max<int64_t>(c->n_leaves, 1);
+    if (!c->cells_refined)
+        k_gravity<true><<<grid, GBS, 0, s>>>(A);
+    else
+        k_gravity<false><<<grid, GBS, 0, s>>>(A);
     SPH_HIP(hipGetLastError());
     ev_record(c, EV_GRAV_K1, s);
     const int64_t* hc = read_counters(c, s);
