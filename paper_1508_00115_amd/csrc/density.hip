@@ -210,8 +210,11 @@ __device__ __forceinline__ void hsolve_step(HSolve& s, float S0, float S1, float
 
 // Outputs of one particle at its final h (sums M0 = sum m w, M1 = sum m q w'):
 // sorted copies for the force loop, caller-order outputs at o = perm[i]
-// (loaded with the particle, so the stores wait for nothing).
-template <class I>
+// (loaded with the particle, so the stores wait for nothing). SORTED_STATE
+// false leaves the sorted state as it is: the re-scanning kernel's wavefronts
+// that share a cell number its flagged particles from it, and nothing reads it
+// after that kernel (the caller-order state carries over to the next pass).
+template <bool SORTED_STATE = true, class I>
 __device__ __forceinline__ void write_result(const DensArgs& A, int i, uint32_t o, const HSolve& s, float S0,
                                              float M0, float M1, int cnt, I& inter_acc, I& n_over,
                                              I& n_unconv, int& max_ev)
@@ -232,7 +235,7 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, uint32_t 
     A.hs[i] = s.h;
     A.rhos[i] = rho;
     A.fs[i] = f;
-    A.st_s[i] = s.state;
+    if (SORTED_STATE) A.st_s[i] = s.state;
     A.h_out[o] = h_report;
     A.rho_out[o] = rho;
     A.f_out[o] = f;
@@ -665,7 +668,8 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
 }
 
 // ---- the re-scanning kernel: particles flagged ST_SCAN -------------------------------
-// Persistent wavefronts take the queued cells one at a time; a wavefront with
+// Persistent wavefronts take the queued cells one at a time (or, when the
+// queue is short, a share of a cell's groups: see `split`); a wavefront with
 // no queued cell left exits at once, so the launch costs little when nothing
 // was queued. The flagged particles of a cell are compacted and taken four at
 // a time, RLPI = 16 lanes each. Phase A walks the cell's candidates once and
@@ -794,7 +798,8 @@ __device__ __forceinline__ void rewalk_solve(const DensArgs& A, NbrCursor& cu, f
         if (sub == 0) sweep_acc += cnt;
         hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
     }
-    if (active && sub == 0) write_result(A, i, A.perm[i], s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
+    if (active && sub == 0)
+        write_result<false>(A, i, A.perm[i], s, S0, M0, M1, cnt, inter_acc, n_over, n_unconv, max_ev);
 }
 
 __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
@@ -816,14 +821,25 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
     int64_t listed_acc = 0;  // wave-uniform
     int max_ev = 0;
     const int n_queued = (int)A.ctr[CT_SCAN_CELLS];  // final: written by the list kernel
-    if ((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6) >= n_queued) return;
+    // A short queue leaves most wavefronts idle while a few take long cells
+    // (a blast's hot centre: thousands of candidates, groups taken one after
+    // another). Each queued cell then becomes `split` items, and item `part`
+    // takes the cell's groups of flagged particles whose number is part
+    // modulo split. A group's arithmetic does not depend on which wavefront
+    // runs it, so the results keep their bits.
+    const int n_waves = (int)gridDim.x * WAVES;
+    int split = 1;
+    while (split < 16 && (int64_t)n_queued * split * 2 <= n_waves) split *= 2;
+    const int n_items = n_queued * split;
+    if ((int)blockIdx.x * WAVES + (int)(threadIdx.x >> 6) >= n_items) return;
 
     for (;;) {
         int k = 0;
         if (lane == 0) k = (int)atomicAdd((unsigned long long*)&A.ctr[CT_SCAN_POP], 1ull);
         k = __shfl(k, 0, 64);
-        if (k >= n_queued) break;
-        const int slot = A.scan_cells[k];
+        if (k >= n_items) break;
+        const int kc = k / split, part = k - kc * split;
+        const int slot = A.scan_cells[kc];
         const int4 ci = A.cells[slot];
         const int i0 = ci.x, ni = ci.y, pb0 = ci.z, np_all = ci.w;
         NbrCursor cu;  // neighbour records 64 at a time
@@ -831,6 +847,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
         const int nj = np_all <= 64 ? cu.nb.nj : count_candidates(A.p_rec, pb0, np_all);
         const bool single_tile = np_all <= 64 && nj <= SCAP;
         bool loaded = false;
+        int gbase = 0;  // groups in the cell's earlier blocks
         for (int b0 = 0; b0 < ni; b0 += 64) {
             // the flagged particles of these 64, compacted into pidx
             const bool flag = b0 + lane < ni && A.st_s[i0 + b0 + lane] == ST_SCAN;
@@ -839,7 +856,11 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
             wave_sync_lds();  // the previous block's reads of pidx are done
             if (flag) pidx[lanes_below(fm)] = b0 + lane;
             wave_sync_lds();
-            for (int p0 = 0; p0 < nflag; p0 += 64 / RLPI) {
+            constexpr int GP = 64 / RLPI;  // particles per group
+            const int ng = (nflag + GP - 1) / GP;
+            // this item's groups q of the block: gbase + q = part (mod split)
+            for (int q = (part - gbase) & (split - 1); q < ng; q += split) {
+                const int p0 = q * GP;
                 const bool valid = p0 + g < nflag;
                 const int i = i0 + pidx[valid ? p0 + g : p0];
                 const float4 xi = A.jd[i];
@@ -903,7 +924,8 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                     hsolve_step(s, S0, S1, A.inv_target, A.tol, A.max_iter);
                 }
                 if (listed && sub == 0)
-                    write_result(A, i, A.perm[i], s, fS0, fM0, fM1, fcnt, inter_acc, n_over, n_unconv, max_ev);
+                    write_result<false>(A, i, A.perm[i], s, fS0, fM0, fM1, fcnt, inter_acc, n_over, n_unconv,
+                                        max_ev);
 
                 // ---- lists too short: re-test every candidate per evaluation -------
                 const bool rewalk = valid && !fits;
@@ -911,6 +933,7 @@ __global__ void __launch_bounds__(BS) k_density_scan(DensArgs A)
                     rewalk_solve(A, cu, tile, nj, single_tile, loaded, rewalk, i, xi, sub, gbox, greach2, cand_acc,
                                  inter_acc, sweep_acc, n_over, n_unconv, max_ev);
             }
+            gbase += ng;
         }
     }
     flush_counters(A, cand_acc, list_acc, inter_acc, sweep_acc, n_over, n_unconv, max_ev, 0, listed_acc);
