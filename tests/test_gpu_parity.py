@@ -129,6 +129,48 @@ def test_coincident_particles(gpu_lib, fp64):
     assert np.all(r["nngb"][n:] >= 1)
 
 
+@pytest.mark.parametrize("layout", ["top_cells", "big_leaves"])
+def test_short_rescan_queue(gpu_lib, layout):
+    """Mixed masses inside one small sphere: only the cells that reach it go
+    to the re-scanning kernel, a queue far shorter than the kernel's
+    wavefronts, so several wavefronts share each queued cell. Every particle
+    must be solved exactly once and match the oracle. big_leaves: clustered
+    particles with leaves of up to 256, so a queued cell holds several blocks
+    of 64 flagged particles."""
+    import torch
+    if layout == "top_cells":
+        d = workloads.lattice_box(24, [1508, 907], jitter=0.3, u=1.0, vel_sigma=0.2)
+        params, radius = {}, 0.1
+    else:
+        d = workloads.clustered(n_uniform=1 << 13, n_spheres=2, per_sphere=4096, a_range=(0.02, 0.04))
+        params, radius = {"leaf_target": 256}, 2.0 * float(d["h0"].min())
+    n = d["pos"].shape[0]
+    centre = d["pos"][int(np.argmin(d["h0"]))]
+    off = d["pos"] - centre
+    off -= np.rint(off)
+    inside = np.linalg.norm(off, axis=1) < radius
+    f = np.ones(n)
+    f[inside] = np.random.default_rng([1508, 907, 1]).uniform(0.5, 1.5, size=int(inside.sum()))
+    d["mass"] = (d["mass"] * f).astype(np.float32)
+    ctx = gpu_lib.Context(0, **params)
+    try:
+        g = gpu_lib.run_workload(ctx, d)
+        info = ctx.build_info()
+    finally:
+        ctx.close()
+    torch.cuda.synchronize()
+    r = oracle.run(d)
+    e = errors(g, r)
+    st = g["stats_density"]
+    print("short queue", layout, "N", n, "mixed", int(inside.sum()), e, st, info, flush=True)
+    assert_within(e, TOL32, "short queue " + layout)
+    assert int(inside.sum()) <= st["rescanned_density"] < n // 2
+    n_d = int(r["nngb"].sum())
+    assert abs(st["interactions_density"] - n_d) <= 1e-5 * n_d + 2
+    if layout == "big_leaves":
+        assert info["max_cell_particles"] > 64
+
+
 def test_positions_outside_the_box(gpu_lib):
     """Input positions below 0 and at or above L (whole periods away) are
     wrapped into the box: the results equal those of the wrapped input."""
