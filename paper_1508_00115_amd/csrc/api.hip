@@ -120,7 +120,7 @@ void sph_destroy(sph_ctx* c)
                        &c->nd_count, &c->nd_hmax, &c->nd_wide, &c->nd_child0, &c->nd_child1, &c->nd_parent, &c->nd_leaf, &c->nd_box,
                        &c->nd_level, &c->nd_coord, &c->nflag, &c->nscan, &c->top, &c->lf_start, &c->lf_count,
                        &c->lf_node, &c->lf_hmax, &c->lf_tmp, &c->p_start, &c->p_cnt, &c->p_leaf, &c->p_shift,
-                       &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->u_s, &c->status,
+                       &c->p_code, &c->scan_tmp, &c->sort_hist, &c->jd, &c->hs, &c->rhos, &c->fs, &c->status,
                        &c->st_s, &c->jf, &c->vsig_s, &c->bal_s, &c->drift, &c->p_rec, &c->counters, &c->cons_d, &c->cons_part, &c->box_leaf, &c->cons64_d, &c->h64, &c->rho64, &c->f64, &c->st64,
                        &c->m64s, &c->jf64, &c->hf_tmp, &c->scan_cells, &c->cells, &c->cell_aux, &c->cell_geom, &c->cell_pbox, &c->cells_d, &c->p_cntd, &c->divv_s,
                        &c->sched_key, &c->sched_key_alt, &c->sched_val, &c->sched_val_alt, &c->build_out, &c->jg};

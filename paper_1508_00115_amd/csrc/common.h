@@ -201,7 +201,6 @@ struct sph_ctx {
     sph::Buf jd;             // float4 (x, y, z, m)
     sph::Buf jg;             // float4 (x, y, z, m) of the near-field gravity (its own masses)
     sph::Buf hs, rhos, fs;   // float, sorted
-    sph::Buf u_s;            // float, sorted u (the pass's fused ghost step)
     sph::Buf status;         // uint8, caller order
     sph::Buf st_s;           // uint8, sorted copy of status
     sph::Buf scan_cells;     // int: leaves holding particles left to the re-scan

@@ -78,9 +78,10 @@ struct DensArgs {
     int lpi_min;             // fewest lanes per particle (a power of two): spreads a list over enough slots
     float nl_est;            // expected list length of a particle: n_ngb * h_margin^3
     // ghost step fused into the outputs (null jf: not fused): the force
-    // loop's streams from the final h, rho, f and u (the prologue has put
-    // (v, m) into each particle's second float4 and u into u_s)
-    const float* u_s;
+    // loop's three float4 per particle from the final h, rho, f and the
+    // caller-order velocity and u
+    const float* vel_in;
+    const float* u_in;
     float4* jf;
     float gamma;
     const float* drift;      // [0]: bound on the drift since the build (search Hs - 2 drift)
@@ -90,19 +91,16 @@ struct DensArgs {
 
 // Sorted copies of position (cell frame), mass, h and state. fresh: every
 // particle starts active; otherwise the caller-order state of the previous
-// pass is kept (an overflowed particle starts again). With vel and u (the
-// pass's fused ghost step) also the force loop's (v, m) stream and the sorted
-// u, with their checks, so that the density kernels' ghost step reads only
-// sorted data.
+// pass is kept (an overflowed particle starts again). The pass's fused ghost
+// step reads velocity and u itself, by caller index, where it writes the
+// particle's force streams: copying them here would gather them once more.
 __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t* __restrict__ perm,
                                                        const float4* __restrict__ xrel,
                                                        const float* __restrict__ mass,
                                                        const float* __restrict__ h_in,
                                                        const uint8_t* __restrict__ status, int fresh,
-                                                       const float* __restrict__ vel, const float* __restrict__ u,
                                                        float4* __restrict__ jd, float* __restrict__ hs,
-                                                       uint8_t* __restrict__ st_s, float4* __restrict__ jf,
-                                                       float* __restrict__ u_s, int64_t* __restrict__ ctr)
+                                                       uint8_t* __restrict__ st_s, int64_t* __restrict__ ctr)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
@@ -116,13 +114,6 @@ __global__ void __launch_bounds__(256) k_dens_prologue(int64_t n, const uint32_t
         const uint8_t st = fresh ? (uint8_t)ST_ACTIVE : status[o];
         st_s[p] = st == ST_OVERFLOW ? (uint8_t)ST_ACTIVE : st;
         bad = !((m > 0.0f) && isfinite(m) && (h > 0.0f) && isfinite(h));
-        if (jf) {
-            const float uu = u[o];
-            const float vx = vel[3 * (int64_t)o], vy = vel[3 * (int64_t)o + 1], vz = vel[3 * (int64_t)o + 2];
-            bad |= !(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz);
-            jf[3 * p + 1] = make_float4(vx, vy, vz, m);
-            u_s[p] = uu;
-        }
     }
     // one count per block instead of per-particle atomics on a shared counter
     const int n_bad = __syncthreads_count(bad);
@@ -245,16 +236,21 @@ __device__ __forceinline__ void write_result(const DensArgs& A, int i, uint32_t 
     max_ev = max(max_ev, s.nev);
     if (A.jf) {
         // the ghost step of this particle (the same arithmetic as the force
-        // loop's ghost kernel, so both give the same bits); the second float4,
-        // (v, m), was written by the prologue
+        // loop's ghost kernel, so both give the same bits), with the checks
+        // of its velocity and u: every particle of the pass passes here once
         const float4 x = A.jd[i];
         const float h = s.h;
-        const float uu = A.u_s[i];
+        const float uu = A.u_in[o];
+        const float vx = A.vel_in[3 * (int64_t)o], vy = A.vel_in[3 * (int64_t)o + 1],
+                    vz = A.vel_in[3 * (int64_t)o + 2];
+        if (!(uu >= 0.0f) || !isfinite(uu) || !isfinite(vx) || !isfinite(vy) || !isfinite(vz))
+            atomicAdd((unsigned long long*)&ctr_slot(A.ctr)[CT_BAD_INPUT], 1ull);
         const float gamma = A.gamma;
         const float P = (gamma - 1.0f) * rho * uu;
         const float c = sqrtf(gamma * (gamma - 1.0f) * uu);
         const float phi = f * P / (rho * rho);
         A.jf[3 * (int64_t)i + 0] = make_float4(x.x, x.y, x.z, h * h);
+        A.jf[3 * (int64_t)i + 1] = make_float4(vx, vy, vz, x.w);
         A.jf[3 * (int64_t)i + 2] = make_float4(rho, phi, c, 1.0f / h);
     }
 }
@@ -971,12 +967,10 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     uint8_t* st_s = static_cast<uint8_t*>(c->st_s.p);
     const bool ghost = ghost_vel && ghost_u;
     float4* jf = ghost ? static_cast<float4*>(c->jf.p) : nullptr;
-    float* u_s = ghost ? static_cast<float*>(c->u_s.p) : nullptr;
     fill_u32(ctr, 0u, 2 * (int64_t)CT_COUNT, s);  // sums, spread slots, queue heads
     k_dens_prologue<<<blocks_for(n, 256), 256, 0, s>>>(n, static_cast<uint32_t*>(c->perm.p),
                                                         static_cast<float4*>(c->xrel.p), mass, h, status,
-                                                        fresh ? 1 : 0, ghost_vel, ghost_u, jd, hs, st_s, jf, u_s,
-                                                        ctr);
+                                                        fresh ? 1 : 0, jd, hs, st_s, ctr);
     SPH_HIP(hipGetLastError());
     DensArgs A;
     A.jd = jd;
@@ -1008,7 +1002,8 @@ void density_enqueue(sph_ctx* c, const float* mass, float* h, float* rho, float*
     A.lpi_min = 2;
     while (A.lpi_min < 16 && A.lpi_min * DSLOTS < 1.7 * expect) A.lpi_min *= 2;
     A.scan_cells = static_cast<int*>(c->scan_cells.p);
-    A.u_s = u_s;
+    A.vel_in = ghost ? ghost_vel : nullptr;
+    A.u_in = ghost ? ghost_u : nullptr;
     A.jf = jf;
     A.gamma = (float)c->prm.gamma;
     A.drift = static_cast<float*>(c->drift.p);
@@ -1058,7 +1053,6 @@ void density_buffers(sph_ctx* c)
     ensure<float>(c, c->hs, n);
     ensure<float>(c, c->rhos, n);
     ensure<float>(c, c->fs, n);
-    ensure<float>(c, c->u_s, n);
     ensure<uint8_t>(c, c->st_s, n);
     ensure<int>(c, c->scan_cells, (size_t)c->n_leaves);
 }
