@@ -156,14 +156,22 @@ def test_short_rescan_queue(gpu_lib, layout):
     try:
         g = gpu_lib.run_workload(ctx, d)
         info = ctx.build_info()
+        # the pass on the same cells: its ghost step runs in the re-scanning
+        # kernel for the queued particles
+        t = {k: torch.from_numpy(d[k]).cuda().float() for k in ("mass", "h0", "vel", "u")}
+        rp = ctx.pass_(t["mass"], t["h0"].clone(), t["vel"], t["u"], nw=torch.empty_like(t["h0"]))
+        torch.cuda.synchronize()
+        gp = {k: rp[k].double().cpu().numpy() for k in ("h", "rho", "f", "nw", "acc", "dudt")}
     finally:
         ctx.close()
-    torch.cuda.synchronize()
     r = oracle.run(d)
     e = errors(g, r)
     st = g["stats_density"]
     print("short queue", layout, "N", n, "mixed", int(inside.sum()), e, st, info, flush=True)
     assert_within(e, TOL32, "short queue " + layout)
+    ep = errors(gp, r)
+    print("short queue pass", layout, ep, rp["stats"], flush=True)
+    assert_within(ep, TOL32, "short queue pass " + layout)
     assert int(inside.sum()) <= st["rescanned_density"] < n // 2
     n_d = int(r["nngb"].sum())
     assert abs(st["interactions_density"] - n_d) <= 1e-5 * n_d + 2
@@ -193,7 +201,8 @@ def test_positions_outside_the_box(gpu_lib):
 
 
 def test_failed_pass_invalidates_time_step(gpu_lib):
-    """A pass refused for a negative u leaves no signal velocities behind:
+    """A pass refused for a negative u (or a non-finite velocity) leaves no
+    signal velocities behind:
     sph_timestep then reports SPH_E_STATE instead of a stale step."""
     import torch
     sph = gpu_lib
@@ -212,6 +221,12 @@ def test_failed_pass_invalidates_time_step(gpu_lib):
         with pytest.raises(sph.SphError) as ei:
             ctx.timestep(0.3)
         assert ei.value.code == sph.SPH_E_STATE
+        # a non-finite velocity, checked where the pass's ghost step reads it
+        bad_v = t["vel"].clone()
+        bad_v[11, 2] = float("nan")
+        with pytest.raises(sph.SphError) as ei:
+            ctx.pass_(t["mass"], t["h0"].clone(), bad_v, t["u"])
+        assert ei.value.code == sph.SPH_E_ARG
         # the separate calls too
         ctx.density(t["mass"], t["h0"].clone())
         with pytest.raises(sph.SphError) as ei:
