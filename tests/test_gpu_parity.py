@@ -129,18 +129,22 @@ def test_coincident_particles(gpu_lib, fp64):
     assert np.all(r["nngb"][n:] >= 1)
 
 
-@pytest.mark.parametrize("layout", ["top_cells", "big_leaves"])
+@pytest.mark.parametrize("layout", ["top_cells", "few_cells", "big_leaves"])
 def test_short_rescan_queue(gpu_lib, layout):
     """Mixed masses inside one small sphere: only the cells that reach it go
     to the re-scanning kernel, a queue far shorter than the kernel's
     wavefronts, so several wavefronts share each queued cell. Every particle
-    must be solved exactly once and match the oracle. big_leaves: clustered
-    particles with leaves of up to 256, so a queued cell holds several blocks
-    of 64 flagged particles."""
+    must be solved exactly once and match the oracle. few_cells: under a
+    hundred queued cells among 2,744, each split eight ways (most items find
+    no group). big_leaves: clustered particles with leaves of up to 256, so a
+    queued cell holds several blocks of 64 flagged particles."""
     import torch
     if layout == "top_cells":
         d = workloads.lattice_box(24, [1508, 907], jitter=0.3, u=1.0, vel_sigma=0.2)
         params, radius = {}, 0.1
+    elif layout == "few_cells":
+        d = workloads.lattice_box(34, [1508, 908], jitter=0.3, u=1.0, vel_sigma=0.2)
+        params, radius = {}, 0.04
     else:
         d = workloads.clustered(n_uniform=1 << 13, n_spheres=2, per_sphere=4096, a_range=(0.02, 0.04))
         params, radius = {"leaf_target": 256}, 2.0 * float(d["h0"].min())
