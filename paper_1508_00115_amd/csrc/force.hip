@@ -224,8 +224,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) k_
                 int nl = force_scan<lpi, !DC>(sj, slen, sub, i0v.x, i0v.y, i0v.z, h2_i, lists);
                 if (!valid) nl = 0;
                 cnt += nl;
-                // phase B: the pair terms of the compacted neighbours only
-#pragma unroll 2
+                // phase B: the pair terms of the compacted neighbours only (not
+                // unrolled: the lanes' list lengths differ, and a second copy of
+                // the body measured 2% slower on every set)
+#pragma unroll 1
                 for (int e = 0; e < nl; ++e) {
                     const int k = lst[e * 64];
                     const float4 p0 = sj[k];
