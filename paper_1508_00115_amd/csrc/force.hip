@@ -40,6 +40,7 @@ constexpr int BS = 64;     // one wavefront per block (finest LDS allocation)
 constexpr int WAVES = BS / 64;
 constexpr int FCAP = 128;  // candidates per LDS chunk (3 float4 each)
 constexpr int FSLOTS = FCAP / 4;  // a lane (4+ lanes per particle) tests at most every fourth candidate
+static_assert(FCAP % (2 * 4) == 0, "the phase-A stride (two candidates per lane, four lanes) divides a chunk");
 
 __global__ void k_force_prologue(int64_t n, const uint32_t* __restrict__ perm, const float4* __restrict__ jd,
                                  const float* __restrict__ hs, const float* __restrict__ rhos,
@@ -90,24 +91,25 @@ struct ForceArgs {
 // y, z, h^2) and appends the chunk index of every candidate inside
 // max(h_i, h_j), except the particle itself, to its byte list (row e of the
 // lists holds entry e of every lane; o is the byte offset of this lane's next
-// entry). The chunk is padded with far positions to a multiple of the stride
-// (pad_tile), four tile reads are in flight and the appends are branch-free.
-// A lane tests at most FCAP / 2 candidates of a chunk, so its list cannot
-// overflow.
+// entry). The chunk is padded with far positions to its full size
+// (pad_tile), two tile reads are in flight (four, or eight, measured slower:
+// the registers they hold) and the appends are branch-free.
+// A lane (four per particle) tests at most FCAP / 4 candidates of a chunk,
+// so its list of FSLOTS cannot overflow.
 // OWN_H false (the divergence and curl): only the pairs inside h_i.
 template <int LPI, bool OWN_H>
 __device__ __forceinline__ int force_scan(const float4* sj, int len, int sub, float xx, float xy, float xz,
                                           float h2_i, uint8_t* lists)
 {
-    const int len_pad = (len + 4 * LPI - 1) & ~(4 * LPI - 1);
+    const int len_pad = (len + 2 * LPI - 1) & ~(2 * LPI - 1);
     const unsigned o0 = threadIdx.x & 63;
     unsigned o = o0;
-    for (int k0 = sub; k0 < len_pad; k0 += 4 * LPI) {
-        float4 pj[4];
+    for (int k0 = sub; k0 < len_pad; k0 += 2 * LPI) {
+        float4 pj[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pj[u] = sj[k0 + u * LPI];
+        for (int u = 0; u < 2; ++u) pj[u] = sj[k0 + u * LPI];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const float dx = xx - pj[u].x, dy = xy - pj[u].y, dz = xz - pj[u].z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const bool in = (r2 < (OWN_H ? fmaxf(h2_i, pj[u].w) : h2_i)) & (r2 > 0.0f);
