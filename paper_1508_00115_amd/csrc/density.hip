@@ -45,8 +45,13 @@ constexpr int DSLOTS = 30;     // list entries per lane, plus one spare slot tha
                                // takes the stores of misses once a list is full
                                // (with a 128-candidate tile: < 10 KB of LDS per
                                // wavefront, 16 wavefronts per CU)
+constexpr int DCH_U = 192;     // candidates per chunk of the persistent list kernel without
+                               // culling, which streams every chunk: fewer, longer chunks per
+                               // cell (batched list kernel -1.1%). At three wavefronts per SIMD
+                               // the LDS allows it; the hardware-dispatch instance, at four,
+                               // would lose wavefronts (Sedov +5%), and keeps DCH
 constexpr int SCAP = 512;      // candidates per LDS chunk (re-scanning kernel)
-static_assert(DCH % (4 * 16) == 0 && DCH % (8 * 4) == 0, "every phase-A stride divides a chunk");
+static_assert(DCH % (4 * 16) == 0 && DCH_U % (8 * 4) == 0 && DCH_U % 64 == 0, "every phase-A stride divides a chunk");
 
 struct DensArgs {
     const float4* jd;        // sorted (x, y, z) in the leaf frame, m
@@ -405,9 +410,10 @@ __device__ __forceinline__ void eval_list(float* lst, int len, float hinv, float
 template <int TCAP, bool PERSIST, bool DETAIL, bool CULL>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST ? 3 : 4))) k_density(DensArgs A)
 {
-    __shared__ float4 tile[CULL ? TCAP : DCH];  // (no resident tiles without CULL)
+    constexpr int CH = (CULL || !PERSIST) ? DCH : DCH_U;  // candidates per streamed chunk
+    __shared__ float4 tile[CULL ? TCAP : CH];  // (no resident tiles without CULL)
     __shared__ float lists[(DSLOTS + 1) * 64];
-    __shared__ uint8_t marks[DCH];  // record starts of the chunk being fetched
+    __shared__ uint8_t marks[CH];  // record starts of the chunk being fetched
     __shared__ float4 box_lds[2];   // the cell's particle box (cull_pbox), culling cells only
     const int lane = threadIdx.x & 63;
     float4* sj = tile;
@@ -469,7 +475,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
         // a layout of top cells only runs with four lanes per particle (its
         // cells hold similar numbers of particles, for which the choice is
         // four, and the fixed count lets the compiler specialise every loop)
-        const int lpi = CULL ? choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, DCH) : 4;
+        const int lpi = CULL ? choose_lpi(ni, nj, A.lpi_min, 5.0f * A.nl_est, resident, CH) : 4;
         const int lg = __builtin_ctz(lpi);
         const int per_pass = 64 >> lg;
         const int g = lane >> lg;
@@ -537,10 +543,10 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                 // so it keeps every candidate.
                 const float reach2 = !cull ? 0.0f : cull_reach2(resident ? geom_y : wave_max(s.done ? 0.0f : s.Hi));
                 int kept_tot = 0;
-                ChunkRegs<1, DCH> R;
+                ChunkRegs<1, CH> R;
                 if (stream) {
                     cursor_seek(cu, A.p_rec, A.p_shift, 0);
-                    fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, DCH), marks);
+                    fetch_chunk(R, A.jd, cu.nb, 0, cursor_chunk(cu, 0, CH), marks);
                 }
                 if (have_next && !pre_issued) {
                     // the next cell's records, in flight from here on
@@ -552,7 +558,7 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                 m0 = __shfl(px.w, 0, 64);
                 int len;
                 for (int c0 = 0; c0 < nj; c0 += len) {
-                    len = stream ? R.len : min(DCH, nj - c0);
+                    len = stream ? R.len : min(CH, nj - c0);
                     const float4* tc = resident ? sj + c0 : sj;
                     int slen;  // candidates of this chunk within reach
                     if (stream) {
@@ -574,14 +580,14 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(PERSIST
                             slen = len;
                         }
                         // (a resident tile is scanned again by later passes)
-                        if (resident) kept_pack |= (unsigned)slen << (8 * (c0 / DCH));
+                        if (resident) kept_pack |= (unsigned)slen << (8 * (c0 / CH));
                         const int nx = c0 + len;
                         if (nx < nj) {
                             cursor_seek(cu, A.p_rec, A.p_shift, nx);
-                            fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, DCH), marks);
+                            fetch_chunk(R, A.jd, cu.nb, nx - cu.off0, cursor_chunk(cu, nx, CH), marks);
                         }
                     } else {
-                        slen = (int)((kept_pack >> (8 * (c0 / DCH))) & 0xffu);
+                        slen = (int)((kept_pack >> (8 * (c0 / CH))) & 0xffu);
                     }
                     kept_tot += slen;
                     if (lpi == 2)
